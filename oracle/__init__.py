@@ -33,11 +33,13 @@ _lib = None
 
 
 def lib():
+    """Load the oracle; ORACLE_LIB may name another build of oracle.c (mutation tests)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("ORACLE_LIB", LIB)
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
+        L = ctypes.CDLL(path)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.orc_constants.argtypes = [vp]
         L.orc_bose.argtypes = [dbl, dbl]

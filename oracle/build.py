@@ -6,15 +6,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose=False):
+def build(verbose=False, source=None, out=None):
+    source = source or os.path.join(HERE, "oracle.c")
+    out = out or LIB
     cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-Wall", "-Wextra", "-Wno-unused-parameter", "-D_DEFAULT_SOURCE",
-           "-o", LIB + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"]
+           "-o", out + ".tmp", source, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -99,7 +99,7 @@ def make_config(name):
     return cfg
 
 
-def small_config(mesh, n3=32, n4=100, cell="prim", T=(300.0,)):
+def small_config(mesh, n3=32, n4=96, cell="prim", T=(300.0,)):
     """Same recipe as the named workloads on a small mesh, every q1 with weight 1."""
     c = _cell(cell)
     omega, evec, vel = _harmonic(cell, int(mesh))

@@ -43,18 +43,13 @@ def _canonical(sites):
 
 
 def candidate_clusters(cell, n_shells=3):
-    """Pair clusters by increasing shell, then nearest-neighbour angle triples."""
+    """Candidate cluster groups, in the order they are offered: nearest-neighbour angle
+    triples, then pair clusters by increasing shell.  Pair clusters alone would give
+    blocks that are fully symmetric in their Cartesian indices (a pair energy depends
+    on one relative displacement only); the three-body clusters break that, so the
+    tables exercise every index of the contraction."""
     _, shells = neighbour_shells(cell, n_shells=n_shells)
     groups, seen = [], set()
-    for pairs in shells:
-        grp = []
-        for a, b, c in pairs:
-            sites = ((a, (0, 0, 0)), (b, tuple(c)))
-            key = _canonical(sites)
-            if key not in seen:
-                seen.add(key)
-                grp.append(key)
-        groups.append(grp)
     grp = []
     for a in range(cell.n_at):
         nn = [(b, tuple(c)) for aa, b, c in shells[0] if aa == a]
@@ -64,6 +59,15 @@ def candidate_clusters(cell, n_shells=3):
                 seen.add(key)
                 grp.append(key)
     groups.append(grp)
+    for pairs in shells:
+        grp = []
+        for a, b, c in pairs:
+            sites = ((a, (0, 0, 0)), (b, tuple(c)))
+            key = _canonical(sites)
+            if key not in seen:
+                seen.add(key)
+                grp.append(key)
+        groups.append(grp)
     return groups
 
 
@@ -114,28 +118,29 @@ def _terms_from_clusters(clusters, order, tensors):
 def build_ifc(cell, order, target_terms, rng, rms):
     """Return dict(atoms, cells, phi, n_terms, clusters) with about `target_terms` terms.
 
-    Clusters are drawn shell by shell in a seeded order; a cluster is kept only if it
-    brings the term count closer to the target, so the count is met exactly when
-    reachable and is otherwise the nearest reachable value.  A final global rescale sets the RMS of all entries to `rms`
+    One seeded three-body cluster is taken first; pair clusters are then offered
+    shell by shell in a seeded order, and a cluster is kept if it
+    brings the term count closer to the target or adds no new term (it then only
+    enriches existing blocks), so the count ends at the nearest value this greedy
+    pass reaches.  A final global rescale sets the RMS of all entries to `rms`
     (linear, so invariance and symmetry are kept).
     """
     groups = candidate_clusters(cell)
     chosen, tensors, count_keys = [], [], set()
-    for grp in groups:
+    for gi, grp in enumerate(groups):
         order_idx = rng.permutation(len(grp))
+        if gi == 0:
+            order_idx = order_idx[:1]   # one three-body cluster, the rest pairs
         for i in order_idx:
             sites = grp[i]
             K = len(sites) - 1
             T = rng.standard_normal((3 * K,) * order)
             keys = set(_terms_from_clusters([sites], order, [T]).keys())
-            if abs(len(count_keys | keys) - target_terms) < abs(len(count_keys) - target_terms):
+            n_new = len(count_keys | keys)
+            if n_new == len(count_keys) or abs(n_new - target_terms) < abs(len(count_keys) - target_terms):
                 chosen.append(sites)
                 tensors.append(T)
                 count_keys |= keys
-            if len(count_keys) == target_terms:
-                break
-        if len(count_keys) == target_terms:
-            break
     acc = _terms_from_clusters(chosen, order, tensors)
     keys = sorted(acc.keys())
     n = len(keys)

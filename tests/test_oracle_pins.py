@@ -391,3 +391,41 @@ def test_kappa_constant_tau():
     ref = tau * total / (3 * N * cfg["volume"]) * g["kappa_unit_W_per_m_K"]
     assert np.trace(k) / 3 == pytest.approx(ref, rel=1e-13)
     np.testing.assert_allclose(k, k.T, rtol=1e-14, atol=1e-14 * abs(ref))
+
+
+@pytest.mark.parametrize("ptype,mesh,sig", [(T3P, 4, 0.6283185307179586), (T3M, 4, 0.6283185307179586),
+                                            (T4PM, 3, 0.6283185307179586), (T4PP, 4, 10.0), (T4MM, 4, 10.0)])
+def test_enumerated_records_conserve_energy_and_momentum(ptype, mesh, sig):
+    """Closing each brute-force record with momentum conservation done here, every kept
+    process satisfies the energy filter and lists its equal-sign partners in order."""
+    cfg = small_config(mesh)
+    S = oracle.System(cfg)
+    nb = cfg["nb"]
+    mesh3 = np.asarray(cfg["mesh"])
+    coords = mesh_coords(mesh3)
+    om = cfg["omega"].reshape(-1)
+    sg = oracle.SIGNS[ptype]
+    rows = row_modes(cfg)[::23]
+    total = 0
+    for g0 in rows:
+        recs = S.enumerate_row(ptype, g0, sig)
+        total += len(recs)
+        for r in recs[:: max(1, len(recs) // 200)]:
+            r = int(r)
+            g = [int(g0), r & 0xFFFFFF]
+            if oracle.ORDER[ptype] == 4:
+                g.append((r >> 24) & 0xFFFFFF)
+                jl = (r >> 48) & 0xFF
+            else:
+                jl = (r >> 24) & 0xFF
+            Q = sum(sg[k] * coords[g[k] // nb] for k in range(len(g)))
+            ql = np.mod(sg[-1] * (-Q), mesh3)
+            iql = int((ql[0] * mesh3[1] + ql[1]) * mesh3[2] + ql[2])
+            g.append(iql * nb + jl)
+            w = om[g]
+            delta = w[0] + sum(sg[k] * w[k] for k in range(1, len(g)))
+            assert abs(delta) <= 3.0 * sig * (1 + 1e-12)
+            assert np.all(w >= cfg["omega_floor"])
+            same = {T3P: [], T3M: [1, 2], T4PP: [1, 2], T4PM: [2, 3], T4MM: [1, 2, 3]}[ptype]
+            assert all(g[a] <= g[b] for a, b in zip(same, same[1:]))
+    assert total > 0
