@@ -1,0 +1,224 @@
+/*
+ * fp.h - C ABI of libfp: per-process three- and four-phonon scattering rates on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the hybrid CPU-GPU scheme of the paper (Methodology section;
+ * Appendix Algorithms 3 and 4): the host enumerates, per phonon mode, the
+ * partner tuples that conserve crystal momentum and pass the energy filter, as
+ * CSR lists of packed indices; the GPU evaluates every listed process
+ * (matrix element, |V|^2, Gaussian delta, Bose-Einstein factors) and reduces
+ * the contributions per mode into the scattering rate Gamma and the weighted
+ * phase space WP, scaled by const/nptk and 1/nptk as at the end of Algorithm 4.
+ *
+ * Conventions shared by every entry point
+ *   units       amu, Angstrom, ps, K; omega in rad/ps; force constants in
+ *               eV/Angstrom^m; Gamma in 1/ps (a rate 1/tau, not a linewidth)
+ *   q-mesh      Gamma-centred N0 x N1 x N2; point n = (n0, n1, n2) has index
+ *               iq = (n0*N1 + n1)*N2 + n2 and wavevector sum_d n_d b_d / N_d
+ *   modes       nb = 3*n_atoms branches; global mode index g = iq*nb + j
+ *   eigvecs     e[g][3*atom + alpha], complex128 stored as (re, im) pairs,
+ *               normalised; e(-q) = conj e(q); e(q + G) = e(q) (phases on
+ *               lattice vectors only)
+ *   force       term t of order m: atoms[t][0..m-1], slot 0 in the home cell,
+ *   constants   cells[t][r-1][0..2] integer lattice coordinates of slot r,
+ *               phi[t][alpha0]...[alpha_{m-1}] row-major (3^m values)
+ *   matrix      V = sum_t sum_alpha phi_t/sqrt(prod M) e_lambda(a0)
+ *   element       prod_{r>=1} eps_r(a_r) exp(i sum_{r>=1} Q_r . R_{t,r}),
+ *               Q_r = s_r q_r, eps_r = e (s_r = +1) or conj e (s_r = -1)
+ *
+ * Process types (fp_ptype) and what one record of that type means:
+ *   FP_3P   lambda + lambda'  -> lambda''            q'' = q + q'
+ *   FP_3M   lambda -> lambda' + lambda''            q'' = q - q'
+ *   FP_4PP  lambda + lambda' + lambda'' -> lambda'''  q''' = q + q' + q''
+ *   FP_4PM  lambda + lambda' -> lambda'' + lambda'''  q''' = q + q' - q''
+ *   FP_4MM  lambda -> lambda' + lambda'' + lambda'''  q''' = q - q' - q''
+ * Records are one uint64 each (0-based forms of the paper's Ind2/Ind3):
+ *   3ph: bits 0-23 g', bits 24-31 j''            (q'' from momentum)
+ *   4ph: bits 0-23 g', bits 24-47 g'', bits 48-55 j'''  (q''' from momentum)
+ * Lists are triangle-reduced over interchangeable partners (the paper's
+ * triangular iteration domain, Methodology section): FP_3M and FP_4PP keep
+ * g' <= g'', FP_4PM keeps g'' <= g''', FP_4MM keeps g' <= g'' <= g'''; the
+ * weight of a record (1, 1/2 or 1/6) follows from equality of those indices.
+ *
+ * Rates (FP_3P/FP_3M: prefactor pi hbar/(4N), ordered-sum weights 1, 1/2;
+ * 4ph: pi hbar^2/(8N^2), weights 1/2, 1/2, 1/6; N = N0*N1*N2):
+ *   Gamma_lambda = pref sum_records w |V|^2 occ G(Delta) / prod(omega)
+ *   WP_lambda    = (1/N or 1/N^2) sum_records w occ G(Delta) / prod(omega)
+ *   G(D) = exp(-D^2/sigma^2)/(sigma sqrt(pi))  (Algorithm 1, WP)
+ *   occ: 3+ n'-n''; 3- 1+n'+n''; ++ n'n''(1+n''')-(1+n')(1+n'')n''';
+ *        +- n'(1+n'')(1+n''')-(1+n')n''n'''; -- (1+n')(1+n'')(1+n''')-n'n''n'''
+ *   n = 1/expm1(hbar omega / kB T)
+ *
+ * Errors: every entry point returns fp_status; argument and state checks are
+ * synchronous; fp_last_error() returns a description of the last failure.
+ * Device-side range violations (a record or row mode outside the loaded mesh)
+ * never read out of bounds: the offending record contributes nothing and a
+ * device flag is raised, which fp_check() reports as FP_ERR_RANGE (and every
+ * rates call does when the environment variable FP_VALIDATE=1).  Nothing aborts,
+ * throws or prints.
+ *
+ * Threading: a context is not thread-safe; use one per host thread.
+ */
+#ifndef FP_H
+#define FP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fp_ctx fp_ctx;
+
+typedef enum {
+    FP_OK = 0,
+    FP_ERR_ARG = -1,         /* null pointer, bad size or value */
+    FP_ERR_STATE = -2,       /* modes or force constants not loaded, or mismatched */
+    FP_ERR_RANGE = -3,       /* a record or row mode outside the loaded mesh (device flag) */
+    FP_ERR_NOMEM = -4,       /* device or host allocation failed */
+    FP_ERR_HIP = -5,         /* HIP runtime error */
+    FP_ERR_UNSUPPORTED = -6  /* a size beyond the documented limits */
+} fp_status;
+
+typedef enum { FP_FP64 = 0, FP_MIXED = 1 } fp_precision;
+
+/* OR-ed into the precision argument of fp_rates3/fp_rates4: add into the
+ * outputs instead of overwriting them (Gamma = Gamma3 + Gamma4 in one pass). */
+#define FP_ACCUMULATE 0x100
+
+typedef enum { FP_3P = 0, FP_3M = 1, FP_4PP = 2, FP_4PM = 3, FP_4MM = 4 } fp_ptype;
+
+/* Limits: n_modes < 2^24, nb <= 96 (32 atoms), n_T <= 8, lists per call <= 8,
+ * lcm(N0, N1, N2) <= 1024, force-constant terms per order <= 4096. */
+#define FP_MAX_T 8
+#define FP_MAX_LISTS 8
+
+/* Create a context on HIP device `device`; *out receives it.  Allocates the
+ * context's small device buffers.  FP_ERR_ARG if out is NULL, FP_ERR_HIP if the
+ * device cannot be used. */
+fp_status fp_create(fp_ctx** out, int32_t device);
+
+/* Free every device buffer the context owns.  NULL is accepted. */
+void fp_destroy(fp_ctx* ctx);
+
+/* Text of the last error on this context ("" if none).  Owned by the context. */
+const char* fp_last_error(const fp_ctx* ctx);
+
+/* Harmonic data of the mesh (the "Get q, omega, v" steps of Algorithms 1-4).
+ * All pointers are host memory; the library copies them (synchronously) into
+ * device memory it owns, replacing any previous load (force constants must then
+ * be loaded again).
+ *   mesh[3]      N0, N1, N2 >= 1
+ *   lattice[9]   rows a1, a2, a3 in Angstrom (for the cell volume)
+ *   masses       [n_atoms] amu, > 0
+ *   omega        [N*nb] rad/ps, finite and >= 0
+ *   evec         [N*nb*nb] complex as 2*N*nb*nb doubles
+ *   vel          [N*nb*3] group velocities in Angstrom/ps (used only by
+ *                fp_kappa_rta; may be NULL)
+ *   omega_floor  modes below it are inactive (rad/ps); lists must not use them
+ * FP_ERR_ARG on NULL/invalid values, FP_ERR_UNSUPPORTED beyond the limits. */
+fp_status fp_load_modes(fp_ctx* ctx, const int32_t mesh[3], int32_t n_atoms, const double lattice[9],
+                        const double* masses, const double* omega, const double* evec, const double* vel,
+                        double omega_floor);
+
+/* Force constants of order 3 or 4 (the tables behind the matrix element of
+ * Algorithm 4, whose arguments the paper elides).  atoms and cells are host
+ * arrays ([n_terms][order] and [n_terms][order-1][3]); phi is [n_terms][3^order]
+ * in eV/Angstrom^order, host memory if phi_on_device == 0, else device memory
+ * read on `hip_stream` (so a caller can keep the values device-resident, e.g.
+ * under automatic differentiation).  The library converts units, folds the
+ * mass factors in and groups the terms; it owns the result.  Requires
+ * fp_load_modes first (FP_ERR_STATE).  FP_ERR_ARG on atoms/cells out of range. */
+fp_status fp_load_ifc(fp_ctx* ctx, int32_t order, int64_t n_terms, const int32_t* atoms, const int32_t* cells,
+                      const double* phi, int32_t phi_on_device, void* hip_stream);
+
+/* One CSR process list: the rows are modes lambda (the paper's mm loop), the
+ * records of row r are rec[row_off[r] .. row_off[r+1]) (N_accum/Ind2/Ind3 of
+ * Algorithm 3).  row_mode, row_off and rec are DEVICE pointers owned by the
+ * caller, which keeps them alive until the stream has passed the call.  Rows of
+ * one list must name distinct modes.  n_rec is row_off[n_rows] (host value). */
+typedef struct {
+    int32_t type; /* fp_ptype */
+    int32_t reserved;
+    int64_t n_rows;
+    int64_t n_rec;
+    const int32_t* row_mode;  /* [n_rows] global mode g of lambda */
+    const int64_t* row_off;   /* [n_rows+1], row_off[0] = 0, non-decreasing */
+    const uint64_t* rec;      /* [n_rec] packed records */
+} fp_plist;
+
+/* Three-phonon rates over 3ph lists (types FP_3P/FP_3M).  Enqueued on
+ * `hip_stream` (hipStream_t, NULL = default stream); returns after argument
+ * checks without waiting for the GPU.  Outputs are DEVICE arrays
+ * [n_T][N*nb] in g order, OVERWRITTEN (modes in no row get 0); either may be
+ * NULL to skip it (with FP_ACCUMULATE they are added to instead).  T_K is a
+ * host array of n_T temperatures (K, > 0); sigma is the Gaussian width in
+ * rad/ps.  precision must be FP_FP64 for order 3.
+ * One launch evaluates every row of every list.  Requires fp_load_modes and
+ * fp_load_ifc(order 3). */
+fp_status fp_rates3(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
+                    double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
+
+/* Four-phonon rates over 4ph lists (types FP_4PP/FP_4PM/FP_4MM); otherwise as
+ * fp_rates3.  Requires fp_load_ifc(order 4). */
+fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
+                    double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
+
+/* kappa_RTA (post-processing of the rates, Results section):
+ *   kappa^{ab}(T) = 1/(N Omega kB T^2) sum_{q in Q1} w_q sum_j n(n+1) (hbar omega)^2 v^a v^b / Gamma
+ * in W/(m K), summed over the irreducible points q1[n_q1] (device int32) with
+ * weights q1_weight[n_q1] (device double, sum = N).  gamma is a DEVICE array
+ * [n_T][N*nb] (total rate per mode); modes with omega < floor or Gamma <= 0
+ * contribute nothing.  kappa_out: DEVICE [n_T][9].  dkappa_dgamma: DEVICE
+ * [n_T][N*nb] derivative of tr(kappa)/3 with respect to Gamma (zero outside
+ * the q1 modes), or NULL.  Requires velocities in fp_load_modes. */
+fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const double* q1_weight, int32_t n_T,
+                       const double* T_K, const double* gamma, double* kappa_out, double* dkappa_dgamma,
+                       void* hip_stream);
+
+/* Tuning knobs of the rate kernels (set by the autotuner; defaults are sane):
+ *   "ppl"            records per lane per work unit, 1..64 (unit = 64*ppl records)
+ *   "blocks_per_cu"  resident 256-thread blocks per compute unit in the
+ *                    persistent launch, 1..16
+ * FP_ERR_ARG for an unknown name or a value out of range. */
+fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
+
+/* Kernel timing for measurement: with enable != 0 every launch of the rate
+ * kernel is bracketed by HIP events on its stream; fp_profile_read waits for
+ * them and returns the summed milliseconds and the launch count of the order-m
+ * rate kernel (m = 3 or 4) since the last enable, then clears the record. */
+fp_status fp_profile(fp_ctx* ctx, int32_t enable);
+fp_status fp_profile_read(fp_ctx* ctx, int32_t order, double* total_ms, int64_t* launches);
+
+/* Wait for `hip_stream` and report device-side range violations raised since
+ * the last check (FP_ERR_RANGE), clearing the flag. */
+fp_status fp_check(fp_ctx* ctx, void* hip_stream);
+
+/* Host enumeration of one list (Algorithm 3, generalised to every type), in two
+ * passes like the paper's N_plus / N_accum / Ind2-Ind3 steps.  Host memory
+ * throughout; `omega` is [N*nb] as in fp_load_modes.
+ *   fp_enumerate_count fills row_off[n_rows+1] (exclusive prefix sum of the
+ *     per-row counts; row_off[n_rows] = total records)
+ *   fp_enumerate_fill writes rec[row_off[n_rows]] given that row_off
+ * A candidate is kept iff every mode has omega >= omega_floor, its
+ * interchangeable partners are in ascending g order (triangle reduction) and
+ * |Delta| <= nsigma*sigma, with Delta evaluated in double precision left to
+ * right in record order (((w + s'w') + s''w'') + s'''w''').  Within a row the
+ * records are ordered by (g', g'', j''').  keep_fraction in (0, 1] keeps a
+ * deterministic hash-selected subset (1 keeps all) and seed selects the hash.
+ * n_threads <= 0 uses every hardware thread.  FP_ERR_ARG on invalid input,
+ * FP_ERR_UNSUPPORTED beyond the record encoding's limits. */
+fp_status fp_enumerate_count(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
+                             double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
+                             double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
+                             int64_t* row_off);
+fp_status fp_enumerate_fill(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
+                            double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
+                            double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
+                            const int64_t* row_off, uint64_t* rec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FP_H */

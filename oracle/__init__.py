@@ -42,6 +42,8 @@ def lib():
         L = ctypes.CDLL(path)
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.orc_constants.argtypes = [vp]
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
         L.orc_bose.argtypes = [dbl, dbl]
         L.orc_bose.restype = dbl
         L.orc_gauss.argtypes = [dbl, dbl]
@@ -66,6 +68,10 @@ def constants():
     out = np.zeros(4)
     lib().orc_constants(_p(out))
     return dict(hbar=out[0], kb=out[1], ev=out[2], kappa_unit=out[3])
+
+
+def threads():
+    return int(lib().orc_threads())
 
 
 def bose(omega, T):

@@ -114,6 +114,15 @@ static void kadd(ksum* k, double x) {
 
 static double kval(const ksum* k) { return k->s + k->c; }
 
+/* OpenMP threads the rate sums use */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void orc_constants(double out[4]) {
     out[0] = c_hbar();
     out[1] = c_kb();

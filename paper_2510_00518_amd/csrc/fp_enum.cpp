@@ -1,0 +1,235 @@
+// Host enumeration of filtered, triangle-reduced process lists (the CPU half of
+// the paper's hybrid scheme, Appendix Algorithm 3, generalised to both
+// three-phonon signs and the three four-phonon types).
+//
+// Pass 1 counts the kept partners of every row (the paper's N_plus) and forms
+// their exclusive prefix sum (N_accum); pass 2 writes the packed records
+// (Ind2/Ind3).  Rows are distributed over std::threads with an atomic counter;
+// each row is written by exactly one thread, so the output does not depend on
+// the thread count.
+//
+// The energy mismatch is evaluated in double precision, strictly left to right
+// in record order, and this file is compiled without floating-point
+// contraction, so the filter decision is reproducible bit for bit.
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "fp.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+struct TypeInfo {
+    int order;
+    int s[4];  // signs of slots 0..order-1 (slot 0 is the mode itself, +1)
+};
+
+bool type_info(int32_t type, TypeInfo* ti) {
+    switch (type) {
+        case FP_3P: *ti = {3, {1, 1, -1, 0}}; return true;
+        case FP_3M: *ti = {3, {1, -1, -1, 0}}; return true;
+        case FP_4PP: *ti = {4, {1, 1, 1, -1}}; return true;
+        case FP_4PM: *ti = {4, {1, 1, -1, -1}}; return true;
+        case FP_4MM: *ti = {4, {1, -1, -1, -1}}; return true;
+        default: return false;
+    }
+}
+
+inline int64_t wrapi(int64_t x, int64_t n) { return ((x % n) + n) % n; }
+
+// SplitMix64 finaliser (Steele, Lea, Flood 2014): the hash behind keep_fraction.
+inline uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+struct Enum {
+    TypeInfo ti;
+    int64_t N[3], nq;
+    int32_t nb;
+    const double* omega;
+    double floor_, cut;
+    uint64_t keep_threshold;  // keep iff hash < threshold (all when keep_all)
+    bool keep_all;
+    uint64_t seed;
+
+    void coords(int64_t iq, int64_t c[3]) const {
+        c[2] = iq % N[2];
+        c[1] = (iq / N[2]) % N[1];
+        c[0] = iq / (N[1] * N[2]);
+    }
+    int64_t index(const int64_t c[3]) const {
+        return (wrapi(c[0], N[0]) * N[1] + wrapi(c[1], N[1])) * N[2] + wrapi(c[2], N[2]);
+    }
+    bool keep(uint64_t row_g, uint64_t rec) const {
+        if (keep_all) return true;
+        return mix64(seed ^ mix64(row_g ^ mix64(rec))) < keep_threshold;
+    }
+
+    // Visit the kept records of row mode g0 in (g', g'', j''') order.
+    template <class F>
+    void row(int64_t g0, F&& emit) const {
+        const double w0 = omega[g0];
+        if (!(w0 >= floor_)) return;
+        int64_t q0[3];
+        coords(g0 / nb, q0);
+        const int* s = ti.s;
+        if (ti.order == 3) {
+            for (int64_t iq1 = 0; iq1 < nq; ++iq1) {
+                int64_t q1[3], q2[3];
+                coords(iq1, q1);
+                // s2 q2 = -(q0 + s1 q1)
+                for (int d = 0; d < 3; ++d) q2[d] = s[2] * (-(q0[d] + s[1] * q1[d]));
+                const int64_t iq2 = index(q2);
+                for (int32_t j1 = 0; j1 < nb; ++j1) {
+                    const int64_t g1 = iq1 * nb + j1;
+                    const double w1 = omega[g1];
+                    if (!(w1 >= floor_)) continue;
+                    const double d1 = s[1] > 0 ? w0 + w1 : w0 - w1;
+                    for (int32_t j2 = 0; j2 < nb; ++j2) {
+                        const int64_t g2 = iq2 * nb + j2;
+                        if (ti.s[1] < 0 && g2 < g1) continue;  // FP_3M: g' <= g''
+                        const double w2 = omega[g2];
+                        if (!(w2 >= floor_)) continue;
+                        const double delta = s[2] > 0 ? d1 + w2 : d1 - w2;
+                        if (!(std::fabs(delta) <= cut)) continue;
+                        const uint64_t rec = (uint64_t)g1 | ((uint64_t)j2 << 24);
+                        if (keep((uint64_t)g0, rec)) emit(rec);
+                    }
+                }
+            }
+            return;
+        }
+        const bool tri12 = (s[1] == s[2]);            // ++ and --: g' <= g''
+        const bool tri23 = (s[2] == s[3]);            // +- and --: g'' <= g'''
+        for (int64_t iq1 = 0; iq1 < nq; ++iq1) {
+            int64_t q1[3];
+            coords(iq1, q1);
+            for (int32_t j1 = 0; j1 < nb; ++j1) {
+                const int64_t g1 = iq1 * nb + j1;
+                const double w1 = omega[g1];
+                if (!(w1 >= floor_)) continue;
+                const double d1 = s[1] > 0 ? w0 + w1 : w0 - w1;
+                for (int64_t iq2 = tri12 ? iq1 : 0; iq2 < nq; ++iq2) {
+                    int64_t q2[3], q3[3];
+                    coords(iq2, q2);
+                    for (int d = 0; d < 3; ++d) q3[d] = s[3] * (-(q0[d] + s[1] * q1[d] + s[2] * q2[d]));
+                    const int64_t iq3 = index(q3);
+                    for (int32_t j2 = 0; j2 < nb; ++j2) {
+                        const int64_t g2 = iq2 * nb + j2;
+                        if (tri12 && g2 < g1) continue;
+                        const double w2 = omega[g2];
+                        if (!(w2 >= floor_)) continue;
+                        const double d2 = s[2] > 0 ? d1 + w2 : d1 - w2;
+                        for (int32_t j3 = 0; j3 < nb; ++j3) {
+                            const int64_t g3 = iq3 * nb + j3;
+                            if (tri23 && g3 < g2) continue;
+                            const double w3 = omega[g3];
+                            if (!(w3 >= floor_)) continue;
+                            const double delta = s[3] > 0 ? d2 + w3 : d2 - w3;
+                            if (!(std::fabs(delta) <= cut)) continue;
+                            const uint64_t rec = (uint64_t)g1 | ((uint64_t)g2 << 24) | ((uint64_t)j3 << 48);
+                            if (keep((uint64_t)g0, rec)) emit(rec);
+                        }
+                    }
+                }
+            }
+        }
+    }
+};
+
+fp_status setup(Enum* e, int32_t type, const int32_t mesh[3], int32_t nb, const double* omega, double omega_floor,
+                int64_t n_rows, const int32_t* row_mode, double sigma, double nsigma, double keep_fraction,
+                uint64_t seed) {
+    if (!mesh || !omega || (n_rows > 0 && !row_mode) || n_rows < 0) return FP_ERR_ARG;
+    if (!type_info(type, &e->ti)) return FP_ERR_ARG;
+    if (nb < 1 || nb > 96 || !(sigma > 0.0) || !(nsigma > 0.0) || !(keep_fraction > 0.0 && keep_fraction <= 1.0))
+        return FP_ERR_ARG;
+    e->nq = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh[d] < 1) return FP_ERR_ARG;
+        e->N[d] = mesh[d];
+        e->nq *= mesh[d];
+    }
+    if (e->nq * nb >= (int64_t(1) << 24)) return FP_ERR_UNSUPPORTED;
+    for (int64_t r = 0; r < n_rows; ++r)
+        if (row_mode[r] < 0 || row_mode[r] >= e->nq * nb) return FP_ERR_ARG;
+    e->nb = nb;
+    e->omega = omega;
+    e->floor_ = omega_floor;
+    e->cut = nsigma * sigma;
+    e->keep_all = keep_fraction >= 1.0;
+    e->keep_threshold = e->keep_all ? ~0ULL : (uint64_t)std::ldexp(keep_fraction, 64);
+    e->seed = seed;
+    return FP_OK;
+}
+
+template <class F>
+void parallel_rows(int64_t n_rows, int32_t n_threads, F&& body) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = n_threads > 0 ? n_threads : (hw ? hw : 1);
+    if (nt > n_rows) nt = n_rows > 0 ? n_rows : 1;
+    std::atomic<int64_t> next(0);
+    auto work = [&]() {
+        for (;;) {
+            int64_t r = next.fetch_add(1);
+            if (r >= n_rows) break;
+            body(r);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int64_t t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+}
+
+}  // namespace
+
+extern "C" fp_status fp_enumerate_count(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
+                                        double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
+                                        double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
+                                        int64_t* row_off) {
+    Enum e;
+    fp_status st = setup(&e, type, mesh, nb, omega, omega_floor, n_rows, row_mode, sigma, nsigma, keep_fraction,
+                         seed);
+    if (st != FP_OK) return st;
+    if (!row_off) return FP_ERR_ARG;
+    std::vector<int64_t> cnt((size_t)n_rows, 0);
+    parallel_rows(n_rows, n_threads, [&](int64_t r) {
+        int64_t c = 0;
+        e.row(row_mode[r], [&](uint64_t) { ++c; });
+        cnt[(size_t)r] = c;
+    });
+    row_off[0] = 0;
+    for (int64_t r = 0; r < n_rows; ++r) row_off[r + 1] = row_off[r] + cnt[(size_t)r];
+    return FP_OK;
+}
+
+extern "C" fp_status fp_enumerate_fill(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
+                                       double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
+                                       double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
+                                       const int64_t* row_off, uint64_t* rec) {
+    Enum e;
+    fp_status st = setup(&e, type, mesh, nb, omega, omega_floor, n_rows, row_mode, sigma, nsigma, keep_fraction,
+                         seed);
+    if (st != FP_OK) return st;
+    if (!row_off || (!rec && row_off[n_rows] > 0)) return FP_ERR_ARG;
+    std::atomic<int> bad(0);
+    parallel_rows(n_rows, n_threads, [&](int64_t r) {
+        int64_t pos = row_off[r];
+        const int64_t end = row_off[r + 1];
+        e.row(row_mode[r], [&](uint64_t v) {
+            if (pos < end) rec[pos] = v;
+            ++pos;
+        });
+        if (pos != end) bad.store(1);
+    });
+    return bad.load() ? FP_ERR_ARG : FP_OK;
+}

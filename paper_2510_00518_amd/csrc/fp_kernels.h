@@ -1,0 +1,608 @@
+// Device kernels of libfp (gfx950).  Included once, by fp_lib.hip.
+//
+// Data layout in HBM (all owned by the context unless noted):
+//   omega  f64 [n_modes]                 g = iq*nb + j
+//   evec   f64x2 [n_modes][nb]           branch-major within a q-point
+//   occ    f64 [n_T][n_modes]            Bose-Einstein occupation per temperature
+//   roots  f64x2 [L]                     exp(2 pi i k / L), L = lcm(N0, N1, N2)
+//   ifc    f64 [n_terms][3^m]            phi * eV / sqrt(prod M), terms sorted by
+//                                        the atoms of slots 1..m-1 ("groups")
+//          i32 [n_terms][8]              a0, phase vectors A (3), B (3), pad
+//          i32 [n_terms][4]              C (3): phase vector of the mode's own q
+//          i32 [n_groups][8]             atoms b, c, d, first term, end term
+//   phit   f64x2 [rows][n_terms][3^(m-1)] force constants contracted with the
+//                                        row mode's eigenvector and q-phase
+//   units  {start, row, count}           work units: <= U consecutive records of one row
+//   partial f64 [units][2][n_T]          per-unit sums of Gamma and WP terms
+//
+// Matrix element with the momentum constraint eliminated (Q_last fixed by
+// q + sum Q = 0 mod G), for order 4:
+//   V = sum_t exp(2 pi i (Q1.A_t + Q2.B_t + q.C_t)/L) sum_{beta gamma delta}
+//       phit_t[beta gamma delta] eps1(b_t)_beta eps2(c_t)_gamma eps3(d_t)_delta
+// with A_t = R1 - R3, B_t = R2 - R3, C_t = -R3 (each scaled by L/N_d, mod L);
+// order 3 uses A_t = R1 - R2, C_t = -R2.  The q.C_t phase and the contraction
+// with e_lambda are folded into phit once per row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fpk {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcd = 8;          // MI355X: 8 accelerator complex dies, blocks dealt round-robin
+constexpr int kMaxRoots = 1024;
+
+struct RowInfo {
+    const uint64_t* rec;  // list record array
+    int64_t beg, end;     // record range of the row
+    int32_t mode;         // global mode of lambda, -1 if the row is invalid
+    int32_t type;         // fp_ptype
+};
+
+struct UnitDesc {
+    int64_t start;  // first record index
+    int32_t row;    // global row, -1 for padding units
+    int32_t count;  // records in the unit
+};
+
+struct ListArg {
+    int32_t type;
+    int32_t pad;
+    int64_t n_rows, row_base, n_rec;
+    const int32_t* row_mode;
+    const int64_t* row_off;
+    const uint64_t* rec;
+};
+
+struct ListsArg {
+    int32_t n_lists;
+    int32_t pad;
+    int64_t total_rows;
+    ListArg l[8];
+};
+
+struct Temps {
+    double x[8];  // hbar / (kB T)
+};
+
+__device__ inline void raise_flag(int* flag) { atomicOr(flag, 1); }
+
+// ---------------------------------------------------------------- utilities
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_zero_int(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// n[T][g] = 1/expm1(hbar w / kB T); inactive modes get 0 (never referenced by valid lists)
+__global__ void k_occ(const double* __restrict__ omega, int64_t n_modes, int32_t n_T, Temps t, double floor_,
+                      double* __restrict__ occ) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_modes * n_T;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = i % n_modes;
+        const int it = (int)(i / n_modes);
+        const double w = omega[g];
+        occ[i] = w >= floor_ ? 1.0 / expm1(t.x[it] * w) : 0.0;
+    }
+}
+
+// ------------------------------------------------------------- work units
+
+// One thread per global row: validate the CSR row and count its units.
+__global__ void k_rows(ListsArg la, int64_t n_modes, int64_t unit, RowInfo* __restrict__ rows,
+                       int64_t* __restrict__ row_units, int* flag) {
+    for (int64_t gr = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gr < la.total_rows;
+         gr += (int64_t)gridDim.x * blockDim.x) {
+        int l = 0;
+        while (l + 1 < la.n_lists && gr >= la.l[l + 1].row_base) ++l;
+        const ListArg& L = la.l[l];
+        const int64_t r = gr - L.row_base;
+        int64_t beg = L.row_off[r], end = L.row_off[r + 1];
+        int32_t mode = L.row_mode[r];
+        bool ok = beg >= 0 && end >= beg && end <= L.n_rec && mode >= 0 && mode < n_modes;
+        if (!ok) {
+            raise_flag(flag);
+            beg = end = 0;
+            mode = -1;
+        }
+        RowInfo ri;
+        ri.rec = L.rec;
+        ri.beg = beg;
+        ri.end = end;
+        ri.mode = mode;
+        ri.type = L.type;
+        rows[gr] = ri;
+        row_units[gr] = (end - beg + unit - 1) / unit;
+    }
+}
+
+// Exclusive prefix sum of row_units into unit_off[0..n]; one block.
+__global__ void k_scan(const int64_t* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+    __shared__ int64_t part[kBlock];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n + kBlock - 1) / kBlock;
+    const int64_t b = tid * chunk, e = b + chunk < n ? b + chunk : n;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += in[i];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int i = 0; i < kBlock; ++i) {
+            const int64_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[tid];
+    for (int64_t i = b; i < e; ++i) {
+        out[i] = run;
+        run += in[i];
+    }
+    if (tid == kBlock - 1) out[n] = run;
+}
+
+__global__ void k_units(const int64_t* __restrict__ unit_off, int64_t n_rows, const RowInfo* __restrict__ rows,
+                        int64_t unit, int64_t n_units_max, UnitDesc* __restrict__ units) {
+    const int64_t total = unit_off[n_rows];
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n_units_max;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        UnitDesc d;
+        if (u >= total) {
+            d.start = 0;
+            d.row = -1;
+            d.count = 0;
+        } else {
+            int64_t lo = 0, hi = n_rows;  // unit_off[lo] <= u < unit_off[hi]
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (unit_off[mid] <= u) lo = mid; else hi = mid;
+            }
+            const RowInfo ri = rows[lo];
+            d.start = ri.beg + (u - unit_off[lo]) * unit;
+            const int64_t left = ri.end - d.start;
+            d.row = (int32_t)lo;
+            d.count = (int32_t)(left < unit ? left : unit);
+        }
+        units[u] = d;
+    }
+}
+
+// ------------------------------------------------------- force constants
+
+// phi_s[t'][c] = phi[perm[t']][c] * scale[t']  (sorted, unit-converted, mass-scaled)
+__global__ void k_ifc_scale(const double* __restrict__ phi, const int32_t* __restrict__ perm,
+                            const double* __restrict__ scale, int64_t n_terms, int32_t ncomp,
+                            double* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_terms * ncomp;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / ncomp;
+        const int c = (int)(i % ncomp);
+        out[i] = phi[(int64_t)perm[t] * ncomp + c] * scale[t];
+    }
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ inline uint32_t mod_l(uint32_t k, uint32_t L, uint32_t magic) {
+    // magic = floor(2^32 / L): the quotient estimate is at most one short
+    const uint32_t q = __umulhi(k, magic);
+    uint32_t r = k - q * L;
+    return r >= L ? r - L : r;
+}
+
+struct ModeGeom {
+    int32_t N0, N1, N2, nb;
+    int32_t L;
+    uint32_t magic;
+    int32_t s0, s1, s2;  // L / N_d
+};
+
+// phit[row][t][c] = exp(2 pi i q.C_t / L) sum_alpha phi_s[t][alpha][c] e_lambda(a0_t)_alpha
+template <int M>
+__global__ void k_precontract(const RowInfo* __restrict__ rows, int64_t n_rows, const double2* __restrict__ evec,
+                              const double2* __restrict__ roots, ModeGeom geo, const double* __restrict__ phi_s,
+                              const int32_t* __restrict__ tmeta, const int32_t* __restrict__ tc, int64_t n_terms,
+                              double2* __restrict__ phit) {
+    constexpr int NC = M == 3 ? 9 : 27;
+    const int64_t total = n_rows * n_terms * NC;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % NC);
+        const int64_t t = (i / NC) % n_terms;
+        const int64_t r = i / (NC * n_terms);
+        const int32_t g = rows[r].mode;
+        double2 acc = make_double2(0.0, 0.0);
+        if (g >= 0) {
+            const int32_t iq = g / geo.nb;
+            const int32_t n2 = iq % geo.N2, n1 = (iq / geo.N2) % geo.N1, n0 = iq / (geo.N1 * geo.N2);
+            const int32_t a0 = tmeta[t * 8 + 0];
+            const double* p = phi_s + t * (NC * 3);
+            const double2* e = evec + (int64_t)g * geo.nb + 3 * a0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double f = p[a * NC + c];
+                const double2 ev = e[a];
+                acc.x += f * ev.x;
+                acc.y += f * ev.y;
+            }
+            const uint32_t k = (uint32_t)(n0 * tc[t * 4 + 0] + n1 * tc[t * 4 + 1] + n2 * tc[t * 4 + 2]);
+            acc = cmul(roots[mod_l(k, geo.L, geo.magic)], acc);
+        }
+        phit[i] = acc;
+    }
+}
+
+// --------------------------------------------------------------- the rates
+
+struct RatesArgs {
+    int64_t n_units;
+    int64_t n_modes;
+    int32_t n_terms, n_groups;
+    int32_t n_T;
+    int32_t ppl;  // records per lane per unit
+    ModeGeom geo;
+    double inv_sigma2, gnorm;  // 1/sigma^2, 1/(sigma sqrt(pi))
+};
+
+// Pointers travel as separate restrict-qualified arguments so that the compiler
+// can prove the wave-uniform tables (phit, tmeta, groups, rows, units) are never
+// written during the kernel and fetch them with scalar loads.
+#define FP_RATES_PARAMS                                                                                       \
+    const double* __restrict__ omega, const double2* __restrict__ evec, const double* __restrict__ occ,      \
+        const double2* __restrict__ roots, const double2* __restrict__ phit, const int32_t* __restrict__ tmeta, \
+        const int32_t* __restrict__ groups, const RowInfo* __restrict__ rows,                                  \
+        const UnitDesc* __restrict__ units, double* __restrict__ partial, int* __restrict__ flag, RatesArgs a
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ inline void type_signs(int type, int& s1, int& s2, int& s3) {
+    // 3ph: s1, s2; 4ph: s1, s2, s3 (slot 0 is +1)
+    switch (type) {
+        case 0: s1 = 1; s2 = -1; s3 = 0; break;    // 3+
+        case 1: s1 = -1; s2 = -1; s3 = 0; break;   // 3-
+        case 2: s1 = 1; s2 = 1; s3 = -1; break;    // ++
+        case 3: s1 = 1; s2 = -1; s3 = -1; break;   // +-
+        default: s1 = -1; s2 = -1; s3 = -1; break; // --
+    }
+}
+
+__device__ inline int wrapn(int x, int n) {
+    // x in (-2n, 2n)
+    x = x % n;
+    return x < 0 ? x + n : x;
+}
+
+template <int M, int MAXT>
+__global__ __launch_bounds__(kBlock, 2) void k_rates(FP_RATES_PARAMS) {
+    __shared__ double2 sroots[kMaxRoots];
+    for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Blocks are dealt to the dies round-robin; give each die a contiguous range
+    // of units so consecutive units of one row share that die's L2.
+    const int xcd = blockIdx.x % kXcd;
+    const int64_t per_xcd = (a.n_units + kXcd - 1) / kXcd;
+    const int64_t u_beg = xcd * per_xcd;
+    const int64_t u_end = u_beg + per_xcd < a.n_units ? u_beg + per_xcd : a.n_units;
+    const int64_t wstride = (int64_t)(gridDim.x / kXcd) * kWavesPerBlock;
+    const ModeGeom geo = a.geo;
+    const int nb = geo.nb;
+
+    for (int64_t u = u_beg + (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave; u < u_end; u += wstride) {
+        const UnitDesc ud = units[u];
+        const int32_t row = __builtin_amdgcn_readfirstlane(ud.row);
+        const int32_t count = __builtin_amdgcn_readfirstlane(ud.count);
+        double accg[MAXT], accw[MAXT];
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) accg[it] = accw[it] = 0.0;
+        if (row >= 0 && count > 0) {
+            const RowInfo ri = rows[row];
+            const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
+            const int type = __builtin_amdgcn_readfirstlane(ri.type);
+            int s1, s2, s3;
+            type_signs(type, s1, s2, s3);
+            const int32_t iq0 = g0 / nb;
+            const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
+            const double w0 = omega[g0];
+            const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * (M == 3 ? 9 : 27);
+            for (int p = 0; p < a.ppl; ++p) {
+                const int idx = p * kWave + lane;
+                if (idx >= count) break;
+                const uint64_t rec = ri.rec[ud.start + idx];
+                const int32_t g1 = (int32_t)(rec & 0xFFFFFFu);
+                int32_t g2, j_last;
+                if (M == 3) {
+                    g2 = 0;
+                    j_last = (int32_t)((rec >> 24) & 0xFFu);
+                } else {
+                    g2 = (int32_t)((rec >> 24) & 0xFFFFFFu);
+                    j_last = (int32_t)((rec >> 48) & 0xFFu);
+                }
+                if (g1 >= a.n_modes || g2 >= a.n_modes || j_last >= nb) {
+                    raise_flag(flag);
+                    continue;
+                }
+                // signed wavevectors of the listed partners, last partner by momentum
+                const int32_t iq1 = g1 / nb;
+                const int32_t c10 = iq1 / (geo.N1 * geo.N2), c11 = (iq1 / geo.N2) % geo.N1, c12 = iq1 % geo.N2;
+                const int32_t Q10 = s1 > 0 ? c10 : wrapn(-c10, geo.N0);
+                const int32_t Q11 = s1 > 0 ? c11 : wrapn(-c11, geo.N1);
+                const int32_t Q12 = s1 > 0 ? c12 : wrapn(-c12, geo.N2);
+                int32_t Q20 = 0, Q21 = 0, Q22 = 0;
+                if (M == 4) {
+                    const int32_t iq2 = g2 / nb;
+                    const int32_t c20 = iq2 / (geo.N1 * geo.N2), c21 = (iq2 / geo.N2) % geo.N1, c22 = iq2 % geo.N2;
+                    Q20 = s2 > 0 ? c20 : wrapn(-c20, geo.N0);
+                    Q21 = s2 > 0 ? c21 : wrapn(-c21, geo.N1);
+                    Q22 = s2 > 0 ? c22 : wrapn(-c22, geo.N2);
+                }
+                const int sl = M == 3 ? s2 : s3;
+                // Q_last = -(q + Q1 (+ Q2)); q_last = s_last * Q_last
+                int32_t ql0 = wrapn(-(c00 + Q10 + Q20), geo.N0);
+                int32_t ql1 = wrapn(-(c01 + Q11 + Q21), geo.N1);
+                int32_t ql2 = wrapn(-(c02 + Q12 + Q22), geo.N2);
+                if (sl < 0) {
+                    ql0 = wrapn(-ql0, geo.N0);
+                    ql1 = wrapn(-ql1, geo.N1);
+                    ql2 = wrapn(-ql2, geo.N2);
+                }
+                const int32_t gl = ((ql0 * geo.N1 + ql1) * geo.N2 + ql2) * nb + j_last;
+                const double w1 = omega[g1];
+                const double wl = omega[gl];
+                const double w2 = M == 4 ? omega[g2] : wl;
+                double delta = s1 > 0 ? w0 + w1 : w0 - w1;
+                delta = s2 > 0 ? delta + w2 : delta - w2;
+                if (M == 4) delta = s3 > 0 ? delta + wl : delta - wl;
+                double wprod = w0 * w1 * w2;
+                if (M == 4) wprod *= wl;
+                // triangle weight from equality of interchangeable partners
+                double wt = 1.0;
+                if (M == 3) {
+                    if (type == 1 && g1 == gl) wt = 0.5;
+                } else if (type == 2) {
+                    if (g1 == g2) wt = 0.5;
+                } else if (type == 3) {
+                    if (g2 == gl) wt = 0.5;
+                } else {
+                    const int eq = (g1 == g2) + (g2 == gl) + (g1 == gl);
+                    wt = eq == 3 ? (1.0 / 6.0) : (eq >= 1 ? 0.5 : 1.0);
+                }
+                const double base = wt * exp(-(delta * delta) * a.inv_sigma2) * a.gnorm / wprod;
+
+                // ---- matrix element
+                const double2* __restrict__ e1 = evec + (int64_t)g1 * nb;
+                const double2* __restrict__ e2 = evec + (int64_t)(M == 4 ? g2 : gl) * nb;
+                const double2* __restrict__ e3 = evec + (int64_t)gl * nb;
+                const double c1 = s1 > 0 ? 1.0 : -1.0;
+                const double c2 = s2 > 0 ? 1.0 : -1.0;
+                const double c3 = sl > 0 ? 1.0 : -1.0;
+                double Vr = 0.0, Vi = 0.0;
+                for (int gi = 0; gi < a.n_groups; ++gi) {
+                    const int32_t* G = groups + gi * 8;
+                    const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
+                    if (M == 3) {
+                        double2 x[3], y[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            x[k] = e1[3 * ab + k];
+                            x[k].y *= c1;
+                            y[k] = e2[3 * ac + k];
+                            y[k].y *= c2;
+                        }
+                        double2 P[9];
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) P[b * 3 + c] = cmul(x[b], y[c]);
+                        for (int t = t0; t < t1; ++t) {
+                            const int32_t* tm = tmeta + t * 8;
+                            const uint32_t k = (uint32_t)(Q10 * tm[1] + Q11 * tm[2] + Q12 * tm[3]);
+                            const double2 ph = sroots[mod_l(k, geo.L, geo.magic)];
+                            const double2* F = phit_row + (int64_t)t * 9;
+                            double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+#pragma unroll
+                            for (int c = 0; c < 9; c += 2) {
+                                const double2 f = F[c];
+                                sr0 += f.x * P[c].x;
+                                sr0 -= f.y * P[c].y;
+                                si0 += f.x * P[c].y;
+                                si0 += f.y * P[c].x;
+                                if (c + 1 < 9) {
+                                    const double2 h = F[c + 1];
+                                    sr1 += h.x * P[c + 1].x;
+                                    sr1 -= h.y * P[c + 1].y;
+                                    si1 += h.x * P[c + 1].y;
+                                    si1 += h.y * P[c + 1].x;
+                                }
+                            }
+                            const double sr = sr0 + sr1, si = si0 + si1;
+                            Vr += ph.x * sr - ph.y * si;
+                            Vi += ph.x * si + ph.y * sr;
+                        }
+                    } else {
+                        double2 x[3], y[3], z[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            x[k] = e1[3 * ab + k];
+                            x[k].y *= c1;
+                            y[k] = e2[3 * ac + k];
+                            y[k].y *= c2;
+                            z[k] = e3[3 * ad + k];
+                            z[k].y *= c3;
+                        }
+                        double2 P[27];
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                const double2 xy = cmul(x[b], y[c]);
+#pragma unroll
+                                for (int d = 0; d < 3; ++d) P[(b * 3 + c) * 3 + d] = cmul(xy, z[d]);
+                            }
+                        for (int t = t0; t < t1; ++t) {
+                            const int32_t* tm = tmeta + t * 8;
+                            const uint32_t k = (uint32_t)(Q10 * tm[1] + Q11 * tm[2] + Q12 * tm[3] + Q20 * tm[4] +
+                                                          Q21 * tm[5] + Q22 * tm[6]);
+                            const double2 ph = sroots[mod_l(k, geo.L, geo.magic)];
+                            const double2* F = phit_row + (int64_t)t * 27;
+                            double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+#pragma unroll
+                            for (int c = 0; c < 27; c += 2) {
+                                const double2 f = F[c];
+                                sr0 += f.x * P[c].x;
+                                sr0 -= f.y * P[c].y;
+                                si0 += f.x * P[c].y;
+                                si0 += f.y * P[c].x;
+                                if (c + 1 < 27) {
+                                    const double2 h = F[c + 1];
+                                    sr1 += h.x * P[c + 1].x;
+                                    sr1 -= h.y * P[c + 1].y;
+                                    si1 += h.x * P[c + 1].y;
+                                    si1 += h.y * P[c + 1].x;
+                                }
+                            }
+                            const double sr = sr0 + sr1, si = si0 + si1;
+                            Vr += ph.x * sr - ph.y * si;
+                            Vi += ph.x * si + ph.y * sr;
+                        }
+                    }
+                }
+                const double V2 = Vr * Vr + Vi * Vi;
+
+                // ---- occupation per temperature
+#pragma unroll
+                for (int it = 0; it < MAXT; ++it) {
+                    if (it < a.n_T) {
+                        const double* n = occ + (int64_t)it * a.n_modes;
+                        const double n1 = n[g1], nl = n[gl];
+                        double occ;
+                        if (M == 3) {
+                            occ = type == 0 ? n1 - nl : 1.0 + n1 + nl;
+                        } else {
+                            const double n2 = n[g2];
+                            if (type == 2)
+                                occ = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
+                            else if (type == 3)
+                                occ = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
+                            else
+                                occ = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
+                        }
+                        const double x = base * occ;
+                        accw[it] += x;
+                        accg[it] += x * V2;
+                    }
+                }
+            }
+        }
+        double* out = partial + u * (2 * a.n_T);
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) {
+            if (it < a.n_T) {
+                const double sg = wave_sum(accg[it]);
+                const double sw = wave_sum(accw[it]);
+                if (lane == 0) {
+                    out[it] = sg;
+                    out[a.n_T + it] = sw;
+                }
+            }
+        }
+    }
+}
+
+// One block per row of one list: sum the row's unit partials in a fixed tree
+// order and add pref * sum into out[T][mode].
+__global__ void k_finalize(const double* __restrict__ partial, const int64_t* __restrict__ unit_off,
+                           const RowInfo* __restrict__ rows, int64_t row0, int32_t n_T, double pref, double wpref,
+                           double* __restrict__ gamma_out, double* __restrict__ wp_out, int64_t n_modes) {
+    __shared__ double red[kBlock];
+    const int64_t r = row0 + blockIdx.x;
+    const int32_t mode = rows[r].mode;
+    const int64_t u0 = unit_off[r], u1 = unit_off[r + 1];
+    for (int q = 0; q < 2 * n_T; ++q) {
+        double s = 0.0;
+        for (int64_t u = u0 + threadIdx.x; u < u1; u += kBlock) s += partial[u * (2 * n_T) + q];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && mode >= 0) {
+            const int it = q < n_T ? q : q - n_T;
+            if (q < n_T) {
+                if (gamma_out) gamma_out[(int64_t)it * n_modes + mode] += pref * red[0];
+            } else {
+                if (wp_out) wp_out[(int64_t)it * n_modes + mode] += wpref * red[0];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------- kappa_RTA
+
+// One block per temperature: kappa[T][9] and optionally d(tr kappa/3)/dGamma.
+__global__ void k_kappa(const int32_t* __restrict__ q1, const double* __restrict__ q1w, int32_t n_q1, int32_t nb,
+                        const double* __restrict__ omega, const double* __restrict__ vel,
+                        const double* __restrict__ gamma, int64_t n_modes, Temps tx, Temps pref,
+                        double floor_, double* __restrict__ kappa, double* __restrict__ dk, int* flag) {
+    __shared__ double red[kBlock];
+    const int it = blockIdx.x;
+    const double x = tx.x[it];
+    const double* G = gamma + (int64_t)it * n_modes;
+    const int64_t n = (int64_t)n_q1 * nb;
+    double acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+        const int64_t iq = q1[i / nb];
+        if (iq < 0 || iq * nb >= n_modes) {
+            raise_flag(flag);
+            continue;
+        }
+        const int64_t g = iq * nb + i % nb;
+        const double w = omega[g];
+        const double gm = G[g];
+        double c = 0.0;
+        if (w >= floor_ && gm > 0.0) {
+            const double nn = 1.0 / expm1(x * w);
+            // n(n+1) (hbar w)^2 / kB T^2 * w_q, with the 1/(kB T^2 N Omega) in pref
+            c = q1w[i / nb] * nn * (nn + 1.0) * w * w;
+        }
+        const double v0 = vel[g * 3], v1 = vel[g * 3 + 1], v2 = vel[g * 3 + 2];
+        const double inv = c > 0.0 ? 1.0 / gm : 0.0;
+        acc[0] += c * v0 * v0 * inv; acc[1] += c * v0 * v1 * inv; acc[2] += c * v0 * v2 * inv;
+        acc[3] += c * v1 * v0 * inv; acc[4] += c * v1 * v1 * inv; acc[5] += c * v1 * v2 * inv;
+        acc[6] += c * v2 * v0 * inv; acc[7] += c * v2 * v1 * inv; acc[8] += c * v2 * v2 * inv;
+        if (dk) dk[(int64_t)it * n_modes + g] = -pref.x[it] * c * (v0 * v0 + v1 * v1 + v2 * v2) * inv * inv / 3.0;
+    }
+    for (int k = 0; k < 9; ++k) {
+        red[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) kappa[it * 9 + k] = pref.x[it] * red[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace fpk

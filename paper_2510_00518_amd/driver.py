@@ -1,0 +1,103 @@
+"""One pass of the rate path for a workload: sequencing of libfp calls.
+
+This module holds no arithmetic of the method.  It uploads a workload's lists
+to device tensors, loads modes and force constants, and issues, in order,
+fp_load_ifc (order 3 and 4), fp_rates3, fp_rates4 (accumulating into the same
+Gamma) and fp_kappa_rta, all on one stream.
+"""
+import numpy as np
+
+from . import fp
+from .synth import row_modes
+
+TYPES3 = (fp.FP_3P, fp.FP_3M)
+TYPES4 = (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM)
+
+
+def host_lists(cfg, types, rows=None, sigma=None, nsigma=None, keep_fraction=1.0, seed=0, n_threads=0):
+    """{type: (row_mode, row_off, rec)} from the library's host enumerator."""
+    out = {}
+    for t in types:
+        out[t] = fp.enumerate_list(t, cfg, row_mode=rows, sigma=sigma, nsigma=nsigma, keep_fraction=keep_fraction,
+                                   seed=seed, n_threads=n_threads)
+    return out
+
+
+class RatePath:
+    def __init__(self, cfg, device=0, ctx=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.device = torch.device("cuda", device)
+        self.ctx = ctx if ctx is not None else fp.fp_create(device)
+        self.own_ctx = ctx is None
+        fp.fp_load_modes(self.ctx, cfg["mesh"], cfg["n_atoms"], cfg["lattice"], cfg["masses"], cfg["omega"],
+                         cfg["evec"], cfg["vel"], cfg["omega_floor"])
+        self.n_modes = int(cfg["omega"].size)
+        self.lists3, self.lists4 = [], []
+        self.phi3 = self.phi4 = None
+        if cfg.get("ifc3") is not None:
+            self.phi3 = torch.as_tensor(cfg["ifc3"]["phi"]).to(self.device)
+        if cfg.get("ifc4") is not None:
+            self.phi4 = torch.as_tensor(cfg["ifc4"]["phi"]).to(self.device)
+        self.q1 = torch.as_tensor(np.ascontiguousarray(cfg["q1"], dtype=np.int32)).to(self.device)
+        self.q1w = torch.as_tensor(np.ascontiguousarray(cfg["q1_weight"], dtype=np.float64)).to(self.device)
+
+    def close(self):
+        if self.own_ctx and self.ctx is not None:
+            fp.fp_destroy(self.ctx)
+        self.ctx = None
+
+    def set_lists(self, lists):
+        """lists: {type: (row_mode, row_off, rec)} host arrays."""
+        self.lists3, self.lists4 = [], []
+        for t, (rm, off, rec) in sorted(lists.items()):
+            pl = fp.PList.from_host(t, rm, off, rec, self.device)
+            (self.lists3 if fp.ORDER[t] == 3 else self.lists4).append(pl)
+
+    @property
+    def n_proc4(self):
+        return sum(pl.n_rec for pl in self.lists4)
+
+    @property
+    def n_proc3(self):
+        return sum(pl.n_rec for pl in self.lists3)
+
+    def outputs(self, n_T):
+        t = self.torch
+        return (t.zeros((n_T, self.n_modes), dtype=t.float64, device=self.device),
+                t.zeros((n_T, self.n_modes), dtype=t.float64, device=self.device))
+
+    def load_ifc(self, phi3=None, phi4=None):
+        cfg = self.cfg
+        if self.lists3 or phi3 is not None:
+            p = self.phi3 if phi3 is None else phi3
+            fp.fp_load_ifc(self.ctx, 3, cfg["ifc3"]["atoms"], cfg["ifc3"]["cells"], p)
+        if self.lists4 or phi4 is not None:
+            p = self.phi4 if phi4 is None else phi4
+            fp.fp_load_ifc(self.ctx, 4, cfg["ifc4"]["atoms"], cfg["ifc4"]["cells"], p)
+
+    def rates(self, T, gamma, wp=None, order=None):
+        """Gamma (and WP) over every loaded list: order 3 then order 4, accumulated."""
+        sigma = self.cfg["sigma"]
+        first = True
+        if self.lists3 and order in (None, 3):
+            fp.fp_rates3(self.ctx, self.lists3, T, sigma, fp.FP_FP64, gamma, wp)
+            first = False
+        if self.lists4 and order in (None, 4):
+            prec = fp.FP_FP64 if first else fp.FP_FP64 | fp.FP_ACCUMULATE
+            fp.fp_rates4(self.ctx, self.lists4, T, sigma, prec, gamma, wp)
+            first = False
+        if first:
+            gamma.zero_()
+            if wp is not None:
+                wp.zero_()
+
+    def kappa(self, T, gamma, kappa_out, dkappa=None):
+        fp.fp_kappa_rta(self.ctx, self.q1, self.q1w, T, gamma, kappa_out, dkappa)
+
+    def step(self, T, gamma, kappa_out, wp=None):
+        """The whole hot path once: force-constant load, 3ph + 4ph rates, kappa."""
+        self.load_ifc()
+        self.rates(T, gamma, wp)
+        self.kappa(T, gamma, kappa_out)

@@ -1,0 +1,144 @@
+"""Host-side checks of libfp (no GPU needed): the library loads and exports every
+function include/fp.h declares, and the host enumerator (the CPU half of the
+hybrid scheme) produces exactly the process sets the oracle's brute-force
+enumeration produces."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_00518_amd import fp
+from paper_2510_00518_amd.synth import make_config, mesh_coords, row_modes, small_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = _declared()
+    assert "fp_rates4" in names and "fp_load_ifc" in names and "fp_enumerate_fill" in names
+    L = fp.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(fp.EXPORTS) == names
+
+
+def test_no_device_is_reported_not_crashed():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert fp.lib().fp_create(ctypes.byref(h), 0) == fp.FP_ERR_HIP
+    assert fp.lib().fp_create(None, 0) == fp.FP_ERR_ARG
+
+
+def test_null_context_arguments():
+    L = fp.lib()
+    assert L.fp_load_modes(None, None, 2, None, None, None, None, None, 0.0) == fp.FP_ERR_ARG
+    assert L.fp_rates4(None, None, 0, 1, None, 1.0, 0, None, None, None) == fp.FP_ERR_ARG
+    assert L.fp_check(None, None) == fp.FP_ERR_ARG
+    assert L.fp_last_error(None) == b"null context"
+    L.fp_destroy(None)
+
+
+def _oracle_sets(cfg, ptype, rows, sigma, nsigma):
+    S = oracle.System(cfg)
+    return [S.enumerate_row(ptype, g, sigma, nsigma) for g in rows]
+
+
+CASES = [(fp.FP_3P, 2, 3.0, 3.0), (fp.FP_3M, 3, None, 3.0), (fp.FP_3P, 4, None, 2.0), (fp.FP_3M, 4, 3.0, 3.0),
+         (fp.FP_4PP, 2, 16.0, 3.0), (fp.FP_4PM, 2, None, 3.0), (fp.FP_4MM, 2, 16.0, 3.0), (fp.FP_4PM, 3, None, 2.0),
+         (fp.FP_4PP, 4, 10.0, 3.0), (fp.FP_4MM, 4, 10.0, 3.0), (fp.FP_4PM, 4, None, 3.0)]
+
+
+@pytest.mark.parametrize("ptype,mesh,sigma,nsigma", CASES)
+def test_enumerator_matches_oracle_brute_force(ptype, mesh, sigma, nsigma):
+    cfg = small_config(mesh)
+    sig = cfg["sigma"] if sigma is None else sigma
+    rows = row_modes(cfg)
+    if mesh == 4 and fp.ORDER[ptype] == 4:
+        rows = rows[::19]
+    rm, off, rec = fp.enumerate_list(ptype, cfg, row_mode=rows, sigma=sig, nsigma=nsigma)
+    want = _oracle_sets(cfg, ptype, rows, sig, nsigma)
+    assert off[-1] == sum(len(w) for w in want)
+    for r, w in enumerate(want):
+        got = rec[off[r]:off[r + 1]]
+        # within a row the records are ordered by (g', g'', j''')
+        g1, g2, jl = got & 0xFFFFFF, (got >> np.uint64(24)) & 0xFFFFFF, got >> np.uint64(48)
+        key = (g1.astype(np.int64) << 40) | (g2.astype(np.int64) << 16) | jl.astype(np.int64)
+        assert np.all(key[1:] > key[:-1])
+        np.testing.assert_array_equal(np.sort(got), w)
+    assert off[-1] > 0
+
+
+def test_enumerator_thread_count_invariant_and_momentum():
+    cfg = small_config(4)
+    rows = row_modes(cfg)[::7]
+    a = fp.enumerate_list(fp.FP_4PM, cfg, row_mode=rows, n_threads=1)
+    b = fp.enumerate_list(fp.FP_4PM, cfg, row_mode=rows, n_threads=5)
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+    # every record closes crystal momentum through a real mesh point and conserves energy within the cut
+    nb, mesh = cfg["nb"], np.asarray(cfg["mesh"])
+    coords = mesh_coords(mesh)
+    om = cfg["omega"].reshape(-1)
+    for r, g0 in enumerate(rows):
+        for v in a[2][a[1][r]:a[1][r + 1]]:
+            v = int(v)
+            g1, g2, j3 = v & 0xFFFFFF, (v >> 24) & 0xFFFFFF, (v >> 48) & 0xFF
+            q3 = np.mod(coords[g0 // nb] + coords[g1 // nb] - coords[g2 // nb], mesh)
+            g3 = int((q3[0] * mesh[1] + q3[1]) * mesh[2] + q3[2]) * nb + j3
+            assert g2 <= g3
+            assert abs(om[g0] + om[g1] - om[g2] - om[g3]) <= 3.0 * cfg["sigma"] * (1 + 1e-12)
+
+
+def test_enumerator_keep_fraction_is_a_deterministic_subset():
+    cfg = small_config(4)
+    rows = row_modes(cfg)[::11]
+    full = fp.enumerate_list(fp.FP_4PM, cfg, row_mode=rows)
+    half = fp.enumerate_list(fp.FP_4PM, cfg, row_mode=rows, keep_fraction=0.3, seed=42)
+    again = fp.enumerate_list(fp.FP_4PM, cfg, row_mode=rows, keep_fraction=0.3, seed=42)
+    np.testing.assert_array_equal(half[2], again[2])
+    frac = half[1][-1] / full[1][-1]
+    assert 0.25 < frac < 0.35
+    for r in range(len(rows)):
+        assert set(half[2][half[1][r]:half[1][r + 1]]) <= set(full[2][full[1][r]:full[1][r + 1]])
+
+
+def test_enumerator_argument_errors():
+    cfg = small_config(2)
+    with pytest.raises(fp.FpError) as e:
+        fp.fp_enumerate_count(7, cfg["mesh"], cfg["nb"], cfg["omega"], 1e-3, [5], 1.0, 3.0)
+    assert e.value.status == fp.FP_ERR_ARG
+    with pytest.raises(fp.FpError):
+        fp.fp_enumerate_count(fp.FP_3P, cfg["mesh"], cfg["nb"], cfg["omega"], 1e-3, [10 ** 6], 1.0, 3.0)
+    with pytest.raises(fp.FpError):
+        fp.fp_enumerate_count(fp.FP_3P, cfg["mesh"], cfg["nb"], cfg["omega"], 1e-3, [5], -1.0, 3.0)
+    with pytest.raises(fp.FpError) as e:
+        fp.fp_enumerate_count(fp.FP_3P, [300, 300, 300], 6, np.zeros(300 ** 3 * 6), 1e-3, [5], 1.0, 3.0)
+    assert e.value.status == fp.FP_ERR_UNSUPPORTED
+    # an inconsistent row_off is rejected, not overrun
+    off = fp.fp_enumerate_count(fp.FP_4PM, cfg["mesh"], cfg["nb"], cfg["omega"], 1e-3, [10], 1.0, 3.0)
+    bad = off.copy()
+    bad[-1] = max(0, bad[-1] - 1)
+    with pytest.raises(fp.FpError):
+        fp.fp_enumerate_fill(fp.FP_4PM, cfg["mesh"], cfg["nb"], cfg["omega"], 1e-3, [10], 1.0, 3.0, bad)
+
+
+@pytest.mark.slow
+def test_c2_list_sizes():
+    """Process counts of the 8^3 four-phonon workload (the benchmark's lists)."""
+    cfg = make_config("C2")
+    total = 0
+    for t in (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM):
+        rm, off, _ = fp.enumerate_list(t, cfg)
+        total += off[-1]
+    assert 5e7 < total < 3e8
