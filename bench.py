@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 FP64 lanes x 2 FLOP x 2.4 GHz
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rates4_c2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rates4_fcc8_4ph.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_00518_amd", "csrc", f) for f in ("fp_kernels.h", "fp_lib.hip")]
 
 
@@ -94,7 +94,7 @@ def main():
         from __graft_entry__ import build
         build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    cfg = make_config("C2")
+    cfg = make_config("fcc8_4ph")
     n4 = int(cfg["ifc4"]["n_terms"])
     T = [float(x) for x in cfg["T"]]
     log("bench: enumerating lists on the host")

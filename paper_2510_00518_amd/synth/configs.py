@@ -1,18 +1,21 @@
 """The five seeded synthetic workloads (diamond-structure, silicon-like mass).
 
-  C1  3ph, 2-atom FCC, 4^3 mesh, every q1 (weight 1), 32 cubic terms
-  C2  4ph, 2-atom FCC, 8^3 mesh, Oh-irreducible q1, C1's cubic terms + 96 quartic terms
-  C3  3ph+4ph, 2-atom FCC, 16^3 mesh, irreducible q1, 64 cubic + 160 quartic terms,
-      T in {300, 600, 900} K
-  C4  4ph, 8-atom simple-cubic conventional cell, 10^3 mesh, irreducible q1,
-      200 quartic terms, per-q1 list lengths drawn log-uniform in [1e4, 1e7]
-  C5  adjoint workload: 2-atom FCC, 8^3 mesh, C3's 64 cubic + 160 quartic terms
+  fcc4_3ph         3ph, 2-atom FCC, 4^3 mesh, every q1 (weight 1), 32 cubic terms
+  fcc8_4ph         4ph, 2-atom FCC, 8^3 mesh, Oh-irreducible q1, the same 32 cubic
+                   terms + 96 quartic terms
+  fcc16_34ph       3ph+4ph, 2-atom FCC, 16^3 mesh, irreducible q1, 64 cubic + 160
+                   quartic terms, T in {300, 600, 900} K
+  sc10_4ph_uneven  4ph, 8-atom simple-cubic conventional cell, 10^3 mesh,
+                   irreducible q1, 200 quartic terms, per-q1 list lengths drawn
+                   log-uniform in [1e4, 1e7]
+  fcc8_adjoint     adjoint workload: 2-atom FCC, 8^3 mesh, the 64 cubic + 160
+                   quartic terms of fcc16_34ph
 
 Common recipe: a = 5.431 A, masses 28 amu, per-shell spring constants
 k1, k2 ~ U[5, 15] eV/A^2, cubic coefficients scaled to RMS 1 eV/A^3, quartic to
 RMS 0.3 eV/A^4, Gaussian width sigma = 0.1 THz = 2 pi * 0.1 rad/ps, filter
 |Delta| <= 3 sigma, omega floor 1e-3 rad/ps.  Seeds: default_rng(251000518 + k)
-with k = 0 springs, 1 cubic, 2 quartic, 3 gradient-component pick, 4 C4 lengths.
+with k = 0 springs, 1 cubic, 2 quartic, 3 gradient-component pick, 4 uneven list lengths.
 """
 import functools
 
@@ -29,19 +32,19 @@ NSIGMA = 3.0
 OMEGA_FLOOR = 1e-3          # rad/ps
 
 _SPEC = {
-    "C1": dict(cell="prim", mesh=4, q1="all", n3=32, n4=0, T=[300.0]),
-    "C2": dict(cell="prim", mesh=8, q1="irr", n3=32, n4=96, T=[300.0]),
-    "C3": dict(cell="prim", mesh=16, q1="irr", n3=64, n4=160, T=[300.0, 600.0, 900.0]),
-    "C4": dict(cell="conv", mesh=10, q1="irr", n3=0, n4=200, T=[300.0]),
-    "C5": dict(cell="prim", mesh=8, q1="irr", n3=64, n4=160, T=[300.0]),
+    "fcc4_3ph": dict(cell="prim", mesh=4, q1="all", n3=32, n4=0, T=[300.0]),
+    "fcc8_4ph": dict(cell="prim", mesh=8, q1="irr", n3=32, n4=96, T=[300.0]),
+    "fcc16_34ph": dict(cell="prim", mesh=16, q1="irr", n3=64, n4=160, T=[300.0, 600.0, 900.0]),
+    "sc10_4ph_uneven": dict(cell="conv", mesh=10, q1="irr", n3=0, n4=200, T=[300.0]),
+    "fcc8_adjoint": dict(cell="prim", mesh=8, q1="irr", n3=64, n4=160, T=[300.0]),
 }
 
 DESCRIPTION = {
-    "C1": "3ph FP64, 2-atom diamond cell, 4x4x4 mesh, all q1, 32 cubic terms",
-    "C2": "4ph FP64, 2-atom diamond cell, 8x8x8 mesh, irreducible q1, 32 cubic + 96 quartic terms",
-    "C3": "3ph+4ph, 2-atom diamond cell, 16x16x16 mesh, irreducible q1, 64 cubic + 160 quartic terms",
-    "C4": "4ph, 8-atom cubic diamond cell, 10x10x10 mesh, irreducible q1, 200 quartic terms, uneven lists",
-    "C5": "adjoint, 2-atom diamond cell, 8x8x8 mesh, 64 cubic + 160 quartic terms",
+    "fcc4_3ph": "3ph FP64, 2-atom diamond cell, 4x4x4 mesh, all q1, 32 cubic terms",
+    "fcc8_4ph": "4ph FP64, 2-atom diamond cell, 8x8x8 mesh, irreducible q1, 32 cubic + 96 quartic terms",
+    "fcc16_34ph": "3ph+4ph, 2-atom diamond cell, 16x16x16 mesh, irreducible q1, 64 cubic + 160 quartic terms",
+    "sc10_4ph_uneven": "4ph, 8-atom cubic diamond cell, 10x10x10 mesh, irreducible q1, 200 quartic terms, uneven lists",
+    "fcc8_adjoint": "adjoint, 2-atom diamond cell, 8x8x8 mesh, 64 cubic + 160 quartic terms",
 }
 
 
@@ -94,7 +97,7 @@ def make_config(name):
         sigma=SIGMA, nsigma=NSIGMA, omega_floor=OMEGA_FLOOR, T=np.array(s["T"]),
         ifc3=_ifc(s["cell"], 3, s["n3"]), ifc4=_ifc(s["cell"], 4, s["n4"]),
     )
-    if name == "C4":
+    if name == "sc10_4ph_uneven":
         cfg["q1_lengths"] = c4_lengths(len(q1))
     return cfg
 

@@ -134,9 +134,9 @@ def test_enumerator_argument_errors():
 
 
 @pytest.mark.slow
-def test_c2_list_sizes():
+def test_fcc8_4ph_list_sizes():
     """Process counts of the 8^3 four-phonon workload (the benchmark's lists)."""
-    cfg = make_config("C2")
+    cfg = make_config("fcc8_4ph")
     total = 0
     for t in (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM):
         rm, off, _ = fp.enumerate_list(t, cfg)

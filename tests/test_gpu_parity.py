@@ -91,16 +91,16 @@ def assert_parity(got, want, what, rtol=RTOL):
     assert err.max() <= rtol, what
 
 
-def test_c1_three_phonon(ctx):
-    cfg = make_config("C1")
+def test_fcc4_three_phonon(ctx):
+    cfg = make_config("fcc4_3ph")
     rows = row_modes(cfg)
-    say("C1 3ph: rows", len(rows))
+    say("fcc4_3ph: rows", len(rows))
     lists = oracle_lists(cfg, (fp.FP_3P, fp.FP_3M), rows, cfg["sigma"])
     for T in ([300.0], [300.0, 600.0, 900.0]):
         g, w = gpu_rates(ctx, cfg, lists, T)
         go, wo = oracle_mode_rates(cfg, lists, T, cfg["sigma"])
-        assert_parity(g, go, f"C1 Gamma3 T={T}")
-        assert_parity(w, wo, f"C1 WP3 T={T}")
+        assert_parity(g, go, f"fcc4_3ph Gamma3 T={T}")
+        assert_parity(w, wo, f"fcc4_3ph WP3 T={T}")
         inactive = np.setdiff1d(np.arange(cfg["omega"].size), rows)
         assert np.all(g[:, inactive] == 0.0)
 
@@ -210,7 +210,7 @@ def test_edge_cases(ctx):
 def test_kappa(ctx):
     import torch
     from paper_2510_00518_amd.driver import RatePath
-    cfg = make_config("C2")
+    cfg = make_config("fcc8_4ph")
     S_gamma = np.random.default_rng(1).uniform(0.01, 0.5, size=(2, cfg["omega"].size))
     T = [300.0, 700.0]
     p = RatePath(cfg, ctx=ctx)
@@ -234,17 +234,17 @@ def test_kappa(ctx):
 
 
 @pytest.mark.slow
-def test_c2_full_size_sampled(ctx):
+def test_fcc8_4ph_full_size_sampled(ctx):
     """The 8^3 four-phonon workload at full size, in the benchmark's launch
     configuration; sampled modes checked against the oracle one by one."""
     import torch
     from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists
-    cfg = make_config("C2")
-    say("C2: enumerating (library, host)")
+    cfg = make_config("fcc8_4ph")
+    say("fcc8_4ph: enumerating (library, host)")
     lists = host_lists(cfg, TYPES3 + TYPES4)
     p = RatePath(cfg, ctx=ctx)
     p.set_lists(lists)
-    say("C2: records 4ph", p.n_proc4, "3ph", p.n_proc3)
+    say("fcc8_4ph: records 4ph", p.n_proc4, "3ph", p.n_proc3)
     gam, wp = p.outputs(1)
     p.load_ifc()
     p.rates([300.0], gam, wp)
@@ -269,5 +269,5 @@ def test_c2_full_size_sampled(ctx):
             if len(ref):
                 go, _, _, _ = S.rates(t, [gm], [300.0], cfg["sigma"], row_off=np.array([0, len(ref)]), rec=ref)
                 total += go[0, 0]
-        say(f"C2 mode {gm}: gpu {g[gm]:.12e} oracle {total:.12e}")
+        say(f"fcc8_4ph mode {gm}: gpu {g[gm]:.12e} oracle {total:.12e}")
         assert g[gm] == pytest.approx(total, rel=RTOL)

@@ -279,12 +279,12 @@ def test_detailed_balance(ptype):
 
 @pytest.fixture(scope="module")
 def c1():
-    cfg = make_config("C1")
+    cfg = make_config("fcc4_3ph")
     return cfg, oracle.System(cfg)
 
 
 def test_candidate_count_closed_form(c1):
-    """Brute mode examines N*nb^2 ordered 3ph candidates per mode: 64*6*64*36 = 884736 on C1."""
+    """Brute mode examines N*nb^2 ordered 3ph candidates per mode: 64*6*64*36 = 884736 on fcc4_3ph."""
     cfg, S = c1
     all_modes = np.arange(64 * 6, dtype=np.int32)
     for pt in (T3P, T3M):
@@ -293,7 +293,7 @@ def test_candidate_count_closed_form(c1):
 
 
 def test_time_reversal_rates(c1):
-    """Gamma(-q, j) = Gamma(q, j) for every mode of C1."""
+    """Gamma(-q, j) = Gamma(q, j) for every mode of fcc4_3ph."""
     cfg, S = c1
     rows = row_modes(cfg)
     nb = cfg["nb"]
@@ -370,7 +370,7 @@ def test_brute_ordered_sum_equals_triangle_list(ptype, mesh, sig, stride):
 
 def test_kappa_constant_tau():
     """With Gamma = 1/tau for every mode, kappa = tau/(3 N Omega) sum_q w_q sum_j C |v|^2."""
-    cfg = make_config("C2")
+    cfg = make_config("fcc8_4ph")
     g = _golden_constants()
     tau = 7.5
     gam = np.full(cfg["omega"].size, 1.0 / tau)

@@ -65,7 +65,7 @@ def test_ifc_blocks_not_cartesian_symmetric(cell, order, n):
 
 
 def test_ifc_counts_and_scale():
-    c2, c3, c4 = make_config("C2"), make_config("C3"), make_config("C4")
+    c2, c3, c4 = make_config("fcc8_4ph"), make_config("fcc16_34ph"), make_config("sc10_4ph_uneven")
     # counts the greedy cluster pass reaches for targets 32, 96, 64, 160, 200
     assert c2["ifc3"]["n_terms"] == 32
     assert c2["ifc4"]["n_terms"] == 94
@@ -100,7 +100,7 @@ def _dyn_cartesian(cell, fc2, qcart):
 def test_harmonic_eigenproblem(kind, mesh):
     cell = _cell(kind)
     if kind == "prim":
-        cfg = small_config(mesh) if mesh != 8 else make_config("C2")
+        cfg = small_config(mesh) if mesh != 8 else make_config("fcc8_4ph")
     else:
         cfg = small_config(mesh, n3=0, n4=0, cell="conv")
     fc2 = spring_fc2(cell, springs())
