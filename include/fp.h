@@ -164,6 +164,20 @@ fp_status fp_rates3(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t
 fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                     double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
 
+/* Adjoint of the rates (vector-Jacobian product): given dL/dGamma, a DEVICE
+ * array [n_T][N*nb], write dL/dPhi for the raw force-constant entries,
+ *   dphi3 DEVICE [n3][27] (eV/A^3 units of phi) and dphi4 DEVICE [n4][81],
+ * in the term order of fp_load_ifc (either may be NULL to skip that order;
+ * OVERWRITTEN, or added to with FP_ACCUMULATE).  Gamma is quadratic in the
+ * force constants, so dL/dPhi = sum_p c_p 2 Re(conj(V_p) dV_p/dPhi) with c_p the
+ * process weight; V is recomputed from the lists, never stored.  The lists may
+ * mix both orders; the other arguments are as in fp_rates3/fp_rates4.  FP64
+ * only.  Deterministic: partial sums are kept per block and reduced in a fixed
+ * order. */
+fp_status fp_rates_backward(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
+                            double sigma, int32_t precision, const double* dL_dgamma, double* dphi3, double* dphi4,
+                            void* hip_stream);
+
 /* kappa_RTA (post-processing of the rates, Results section):
  *   kappa^{ab}(T) = 1/(N Omega kB T^2) sum_{q in Q1} w_q sum_j n(n+1) (hbar omega)^2 v^a v^b / Gamma
  * in W/(m K), summed over the irreducible points q1[n_q1] (device int32) with
@@ -179,7 +193,10 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
 /* Tuning knobs of the rate kernels (set by the autotuner; defaults are sane):
  *   "ppl"            records per lane per work unit, 1..64 (unit = 64*ppl records)
  *   "blocks_per_cu"  resident 256-thread blocks per compute unit in the
- *                    persistent launch, 1..16
+ *                    persistent launch, 1..16; 0 = as many as fit
+ *   "variant"        order-4 contraction form, 0..3 (P-form or W-form, one or
+ *                    two processes per lane)
+ *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
 

@@ -55,6 +55,7 @@ def lib():
         L.orc_enumerate.restype = i64
         L.orc_occupation.argtypes = [ctypes.c_int, vp]
         L.orc_occupation.restype = dbl
+        L.orc_grad.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, dbl, ctypes.c_int, vp, vp, vp]
         L.orc_kappa.argtypes = [i32, vp, vp, i32, vp, vp, vp, dbl, dbl, i64, dbl, vp]
         _lib = L
     return _lib
@@ -156,6 +157,23 @@ class System:
         if rc:
             raise ValueError(f"orc_rates failed ({rc})")
         return gam, wp, kept, cand
+
+    def grad(self, ptype, row_mode, T, sigma, row_off, rec, dLdG, out=None):
+        """d(sum dLdG[r][T] Gamma_r(T))/d(raw force constants of the list's order), added into out."""
+        row_mode = np.ascontiguousarray(row_mode, dtype=np.int32)
+        T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
+        m = ORDER[ptype]
+        n_terms = int(self.s.n3 if m == 3 else self.s.n4)
+        if out is None:
+            out = np.zeros((n_terms, 3 ** m))
+        dl = np.ascontiguousarray(dLdG, dtype=np.float64).reshape(len(row_mode), len(T))
+        ro = np.ascontiguousarray(row_off, dtype=np.int64)
+        rc_ = np.ascontiguousarray(rec, dtype=np.uint64) if len(rec) else np.zeros(1, np.uint64)
+        rc = lib().orc_grad(self.ptr, ptype, len(row_mode), _p(row_mode), _p(ro), _p(rc_), float(sigma), len(T),
+                            _p(T), _p(dl), _p(out))
+        if rc:
+            raise ValueError(f"orc_grad failed ({rc})")
+        return out
 
     def enumerate_row(self, ptype, g, sigma, nsigma=3.0):
         """Canonical packed records of one row by brute force (sorted)."""

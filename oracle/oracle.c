@@ -533,6 +533,120 @@ int orc_rates(const orc_sys* s, int ptype, int mode, int64_t n_rows, const int32
 }
 
 /*
+ * Gradient of L = sum_{r,T} dLdG[r][T] * Gamma_r(T) with respect to the raw
+ * force-constant entries of the list's order (eV/A^m), added into dphi
+ * [n_terms][3^m].  Lists in list mode.  Gamma is quadratic in the force
+ * constants:
+ *   dL/dPhi_t^{a...} = sum_p c_p 2 Re(conj(V_p) dV_p/dPhi_t^{a...}),
+ *   c_p = pref * sum_T dLdG[T] * w occ_T G / prod(omega),
+ *   dV_p/dPhi_t^{a...} = eV/sqrt(prod M) eps_0 ... eps_{m-1} exp(i sum Q_r.R_{t,r}).
+ */
+int orc_grad(const orc_sys* s, int ptype, int64_t n_rows, const int32_t* row_mode, const int64_t* row_off,
+             const uint64_t* rec, double sigma, int n_T, const double* T, const double* dLdG, double* dphi) {
+    if (ptype < 0 || ptype > 4 || n_T < 1 || n_T > MAX_T) return -1;
+    int m = type_order(ptype);
+    int64_t n_terms = m == 3 ? s->n3 : s->n4;
+    if (n_terms <= 0) return -2;
+    const int32_t* atoms = m == 3 ? s->atoms3 : s->atoms4;
+    const int32_t* cells = m == 3 ? s->cells3 : s->cells4;
+    int ncomp = m == 3 ? 27 : 81;
+    int nb = 3 * s->n_atoms;
+    int64_t N = n_q(s);
+    int32_t sg[4];
+    type_signs(ptype, sg);
+    double pre = prefactor(m, N), ev = c_ev();
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = omp_get_max_threads();
+    if (nthr > MAX_THREADS) nthr = MAX_THREADS;
+#endif
+    size_t per = (size_t)n_terms * ncomp;
+    ksum* part = calloc((size_t)nthr * per, sizeof(ksum));
+    if (!part) return -3;
+    int64_t total = row_off[n_rows];
+#pragma omp parallel num_threads(nthr)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        ksum* acc = part + (size_t)tid * per;
+        int64_t row = 0;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < total; ++i) {
+            while (row_off[row + 1] <= i) ++row;
+            while (row_off[row] > i) --row;
+            int64_t qc[4][3] = {{0}};
+            int32_t br[4] = {0};
+            int64_t g[4] = {0};
+            double w[4] = {0.0};
+            g[0] = row_mode[row];
+            q_coords(s, g[0] / nb, qc[0]);
+            br[0] = (int32_t)(g[0] % nb);
+            uint64_t r = rec[i];
+            g[1] = (int64_t)(r & 0xFFFFFFu);
+            q_coords(s, g[1] / nb, qc[1]);
+            br[1] = (int32_t)(g[1] % nb);
+            if (m == 3) {
+                br[2] = (int32_t)((r >> 24) & 0xFFu);
+            } else {
+                g[2] = (int64_t)((r >> 24) & 0xFFFFFFu);
+                q_coords(s, g[2] / nb, qc[2]);
+                br[2] = (int32_t)(g[2] % nb);
+                br[3] = (int32_t)((r >> 48) & 0xFFu);
+            }
+            closing_slot(s, m, sg, qc);
+            for (int k = 1; k < m; ++k) g[k] = q_index(s, qc[k]) * nb + br[k];
+            for (int k = 0; k < m; ++k) w[k] = s->omega[g[k]];
+            double delta = mismatch(m, sg, w);
+            double G = orc_gauss(delta, sigma);
+            double wprod = 1.0;
+            for (int k = 0; k < m; ++k) wprod *= w[k];
+            double base = triangle_weight(ptype, g) * G / wprod;
+            double c = 0.0;
+            for (int it = 0; it < n_T; ++it) {
+                double n[4];
+                for (int k = 0; k < m; ++k) n[k] = orc_bose(w[k], T[it]);
+                c += dLdG[row * n_T + it] * pre * base * occupation(ptype, n);
+            }
+            c *= 2.0;
+            cplx V = vertex(s, m, (const int64_t(*)[3])qc, br, sg);
+            cplx Vc = {V.re, -V.im};
+            for (int64_t t = 0; t < n_terms; ++t) {
+                const int32_t* at = atoms + t * m;
+                const int32_t* ce = cells + t * (m - 1) * 3;
+                int64_t k3[3] = {0, 0, 0};
+                for (int rr = 1; rr < m; ++rr)
+                    for (int d = 0; d < 3; ++d) k3[d] += (int64_t)sg[rr] * qc[rr][d] * ce[(rr - 1) * 3 + d];
+                cplx ph = root_of_unity(s, k3);
+                double msc = 1.0;
+                for (int rr = 0; rr < m; ++rr) msc *= s->masses[at[rr]];
+                cplx f = cmul(Vc, ph);
+                double sc = c * ev / sqrt(msc);
+                for (int idx = 0; idx < ncomp; ++idx) {
+                    int a[4];
+                    int rem = idx;
+                    for (int rr = m - 1; rr >= 0; --rr) {
+                        a[rr] = rem % 3;
+                        rem /= 3;
+                    }
+                    cplx prod = f;
+                    for (int rr = 0; rr < m; ++rr) prod = cmul(prod, evec_at(s, g[rr], 3 * at[rr] + a[rr], sg[rr]));
+                    kadd(&acc[t * ncomp + idx], sc * prod.re);
+                }
+            }
+        }
+    }
+    for (size_t k = 0; k < per; ++k) {
+        ksum tot = {0.0, 0.0};
+        for (int t = 0; t < nthr; ++t) kadd(&tot, kval(&part[(size_t)t * per + k]));
+        dphi[k] += kval(&tot);
+    }
+    free(part);
+    return 0;
+}
+
+/*
  * Brute-force enumeration of one row: every ordered partner tuple that passes the
  * filter and whose equal-sign partners are already in ascending mode order is
  * written as a packed record (3ph: g1 | j2<<24; 4ph: g1 | g2<<24 | j3<<48).

@@ -1,0 +1,294 @@
+// Adjoint of the rates: d(sum_{lambda,T} dL/dGamma_lambda(T) Gamma_lambda(T)) / dPhi.
+// Included once, by fp_lib.hip, after fp_kernels.h.
+//
+// Gamma is quadratic in the force constants, so for every listed process p
+//   dL/dPhi_t^{a0 c} = sum_p c_p Re(conj(V_p) dV_p/dPhi_t^{a0 c}),
+//   c_p = 2 pref sum_T dL/dGamma(T) w occ_T G / prod(omega),
+//   dV_p/dPhi_t^{a0 c} = s_t e_lambda(a0_t)_{a0} exp(i q.C_t) ph_t(p) P_p[c],
+// with s_t = eV/sqrt(prod M), ph_t(p) = exp(2 pi i (Q1.A_t + Q2.B_t)/L) and
+// P_p[c] = eps1_beta eps2_gamma (eps3_delta) the partner product of term t's
+// group.  Per row (fixed lambda) the process sum is a matrix product over the
+// process dimension:
+//   D_t[c] = sum_p H[t,p] P[p,c],   H[t,p] = c_p conj(V_p) ph_t(p),
+// which runs on FP64 MFMA (v_mfma_f64_16x16x4f64: 16 terms x 16 components,
+// K = 4 processes per instruction, the lanes carrying the process dimension).
+// V is recomputed, never stored.  Each block owns a fixed set of chunks of
+// records (one row per chunk) and keeps its D tiles in registers across a
+// chunk; at the end of a chunk it folds them with e_lambda and exp(i q.C_t)
+// into its own partial dPhi, written by exactly one lane per entry, so the
+// result does not depend on timing.  A final kernel sums the block partials in
+// block order.
+#pragma once
+
+namespace fpk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSub = kBlock;  // processes staged per sub-chunk (one per thread)
+
+// Matrix element of one process (the forward contraction, one process per lane).
+template <int M>
+__device__ inline double2 vertex_one(const Proc& pr, double c1, double c2, double c3, int nb,
+                                     const double2* __restrict__ evec, const double2* __restrict__ phit_row,
+                                     const int32_t* __restrict__ groups, int n_groups,
+                                     const int32_t* __restrict__ tmeta, const double2* sroots, const ModeGeom& geo) {
+    double2 V = make_double2(0.0, 0.0);
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const int32_t* G = groups + gi * 8;
+        const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
+        if (M == 3) {
+            double2 P[9];
+            const double2* e1 = evec + (int64_t)pr.g1 * nb + 3 * ab;
+            const double2* e2 = evec + (int64_t)pr.g2 * nb + 3 * ac;
+            double2 x[3], y[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                x[k] = ld_eps(e1 + k, c1);
+                y[k] = ld_eps(e2 + k, c2);
+            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) P[b * 3 + c] = cmul(x[b], y[c]);
+            for (int t = t0; t < t1; ++t) {
+                const int32_t* tm = tmeta + t * 8;
+                const double2* F = phit_row + (int64_t)t * 9;
+                double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < 9; ++c) s = cfma(s, F[c], P[c]);
+                const uint32_t k = (uint32_t)(pr.Q10 * tm[1] + pr.Q11 * tm[2] + pr.Q12 * tm[3]);
+                V = cfma(V, sroots[mod_l(k, geo.L, geo.magic)], s);
+            }
+        } else {
+            double2 x[3], w[9];
+            const double2* e1 = evec + (int64_t)pr.g1 * nb + 3 * ab;
+            const double2* e2 = evec + (int64_t)pr.g2 * nb + 3 * ac;
+            const double2* e3 = evec + (int64_t)pr.gl * nb + 3 * ad;
+            double2 y[3], z[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                x[k] = ld_eps(e1 + k, c1);
+                y[k] = ld_eps(e2 + k, c2);
+                z[k] = ld_eps(e3 + k, c3);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) w[c * 3 + d] = cmul(y[c], z[d]);
+            for (int t = t0; t < t1; ++t) {
+                const int32_t* tm = tmeta + t * 8;
+                const double2* F = phit_row + (int64_t)t * 27;
+                double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    double2 uu = make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) uu = cfma(uu, F[b * 9 + c], w[c]);
+                    s = cfma(s, uu, x[b]);
+                }
+                const uint32_t k = (uint32_t)(pr.Q10 * tm[1] + pr.Q11 * tm[2] + pr.Q12 * tm[3] + pr.Q20 * tm[4] +
+                                              pr.Q21 * tm[5] + pr.Q22 * tm[6]);
+                V = cfma(V, sroots[mod_l(k, geo.L, geo.magic)], s);
+            }
+        }
+    }
+    return V;
+}
+
+struct GradArgs {
+    int64_t n_units;   // chunk descriptors
+    int64_t n_modes;
+    int32_t n_terms, n_groups, n_pairs;
+    int32_t n_T;
+    ModeGeom geo;
+    double inv_sigma2, gnorm, pref;
+    Temps dummy;
+};
+
+// Pair table entry: {group, first term, term count (<= 16), first component}.
+#define FP_GRAD_PARAMS                                                                                           \
+    const double* __restrict__ omega, const double2* __restrict__ evec, const double* __restrict__ occ,         \
+        const double2* __restrict__ roots, const double2* __restrict__ phit, const int32_t* __restrict__ tmeta,    \
+        const int32_t* __restrict__ tc, const int32_t* __restrict__ groups, const int32_t* __restrict__ pairs,   \
+        const double* __restrict__ tscale, const RowInfo* __restrict__ rows, const UnitDesc* __restrict__ units, \
+        const double* __restrict__ dldg, double* __restrict__ gpart, int* __restrict__ flag, GradArgs a
+
+template <int M, int MAXT, int MAXP>
+__global__ __launch_bounds__(kBlock, 1) void k_grad(FP_GRAD_PARAMS) {
+    constexpr int NC = M == 3 ? 9 : 27;    // components after the mode's own index
+    constexpr int NCOMP = 3 * NC;          // 3^m entries per term
+    __shared__ double2 sroots[kMaxRoots];
+    __shared__ double2 sh_h[kSub];
+    __shared__ int32_t sh_q[kSub][2];
+    __shared__ int32_t sh_g[kSub][3];
+    for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
+    __syncthreads();
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const ModeGeom geo = a.geo;
+    const int nb = geo.nb;
+    double* __restrict__ mypart = gpart + (int64_t)blockIdx.x * a.n_terms * NCOMP;
+    const int li = lane & 15;   // A row (term) / B column (component) / D column
+    const int lk = lane >> 4;   // K index (process within a K-step) / D row block
+    const int pass_size = kWavesPerBlock * MAXP;
+    const int n_pass = (a.n_pairs + pass_size - 1) / pass_size;
+
+    for (int64_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
+        const UnitDesc ud = units[u];
+        const int32_t row = __builtin_amdgcn_readfirstlane(ud.row);
+        const int32_t count = __builtin_amdgcn_readfirstlane(ud.count);
+        if (row < 0 || count <= 0) continue;
+        const RowInfo ri = rows[row];
+        const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
+        const int type = __builtin_amdgcn_readfirstlane(ri.type);
+        int s1, s2, s3;
+        type_signs(type, s1, s2, s3);
+        const int sl = M == 3 ? s2 : s3;
+        const double c1 = s1 > 0 ? 1.0 : -1.0;
+        const double c2 = s2 > 0 ? 1.0 : -1.0;
+        const double c3 = sl > 0 ? 1.0 : -1.0;
+        const int32_t iq0 = g0 / nb;
+        const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
+        const double w0 = omega[g0];
+        const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * NC;
+        double dl[MAXT];
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) dl[it] = it < a.n_T ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
+
+        for (int pass = 0; pass < n_pass; ++pass) {
+            d4 Cr[MAXP], Ci[MAXP];
+#pragma unroll
+            for (int j = 0; j < MAXP; ++j) Cr[j] = Ci[j] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int sub = 0; sub < count; sub += kSub) {
+                // ---- stage: recompute V for one process per thread
+                {
+                    const int idx = sub + tid;
+                    const bool have = idx < count;
+                    const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
+                    const Proc pr = setup_proc<M>(have, rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega,
+                                                  a.n_modes, flag, a.inv_sigma2, a.gnorm);
+                    const double2 V = vertex_one<M>(pr, c1, c2, c3, nb, evec, phit_row, groups, a.n_groups, tmeta,
+                                                    sroots, geo);
+                    double cw = 0.0;
+#pragma unroll
+                    for (int it = 0; it < MAXT; ++it) {
+                        if (it < a.n_T) {
+                            const double* n = occ + (int64_t)it * a.n_modes;
+                            const double n1 = n[pr.g1], nl = n[pr.gl];
+                            double oc;
+                            if (M == 3) {
+                                oc = type == 0 ? n1 - nl : 1.0 + n1 + nl;
+                            } else {
+                                const double n2 = n[pr.g2];
+                                if (type == 2)
+                                    oc = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
+                                else if (type == 3)
+                                    oc = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
+                                else
+                                    oc = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
+                            }
+                            cw += dl[it] * oc;
+                        }
+                    }
+                    cw *= 2.0 * a.pref * pr.base;
+                    sh_h[tid] = make_double2(cw * V.x, -cw * V.y);
+                    sh_q[tid][0] = pr.Q10 | (pr.Q11 << 10) | (pr.Q12 << 20);
+                    sh_q[tid][1] = pr.Q20 | (pr.Q21 << 10) | (pr.Q22 << 20);
+                    sh_g[tid][0] = pr.g1;
+                    sh_g[tid][1] = pr.g2;
+                    sh_g[tid][2] = pr.gl;
+                }
+                __syncthreads();
+                // ---- D tiles: each wave owns pairs wave + 4 j (+ pass offset)
+#pragma unroll
+                for (int j = 0; j < MAXP; ++j) {
+                    const int pi = pass * pass_size + j * kWavesPerBlock + wave;
+                    if (pi < a.n_pairs) {
+                        const int32_t* PP = pairs + pi * 4;
+                        const int32_t gi = PP[0], tbeg = PP[1], tcnt = PP[2], cbeg = PP[3];
+                        const int32_t* G = groups + gi * 8;
+                        const int32_t ab = G[0], ac = G[1], ad = G[2];
+                        // A role: term tbeg + li; B role: component cbeg + li
+                        const bool aval = li < tcnt;
+                        const int32_t* tm = tmeta + (tbeg + (aval ? li : 0)) * 8;
+                        const int32_t A0 = tm[1], A1 = tm[2], A2 = tm[3], B0 = tm[4], B1 = tm[5], B2 = tm[6];
+                        const int cc = cbeg + li;
+                        const bool bval = cc < NC;
+                        const int cs = bval ? cc : 0;
+                        const int beta = M == 3 ? cs / 3 : cs / 9;
+                        const int gam = M == 3 ? cs % 3 : (cs / 3) % 3;
+                        const int del = cs % 3;
+                        d4 cr = Cr[j], ci = Ci[j];
+                        for (int ks = 0; ks < kSub / 4; ++ks) {
+                            const int p = 4 * ks + lk;
+                            const double2 h = sh_h[p];
+                            const int32_t q1 = sh_q[p][0], q2 = sh_q[p][1];
+                            const uint32_t kk = (uint32_t)((q1 & 1023) * A0 + ((q1 >> 10) & 1023) * A1 +
+                                                           ((q1 >> 20) & 1023) * A2 + (q2 & 1023) * B0 +
+                                                           ((q2 >> 10) & 1023) * B1 + ((q2 >> 20) & 1023) * B2);
+                            double2 H = cmul(h, sroots[mod_l(kk, geo.L, geo.magic)]);
+                            if (!aval) H = make_double2(0.0, 0.0);
+                            const double2 xe = ld_eps(evec + (int64_t)sh_g[p][0] * nb + 3 * ab + beta, c1);
+                            const double2 ye = ld_eps(evec + (int64_t)sh_g[p][1] * nb + 3 * ac + gam, c2);
+                            double2 P = cmul(xe, ye);
+                            if (M == 4) P = cmul(P, ld_eps(evec + (int64_t)sh_g[p][2] * nb + 3 * ad + del, c3));
+                            if (!bval) P = make_double2(0.0, 0.0);
+                            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(H.x, P.x, cr, 0, 0, 0);
+                            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-H.y, P.y, cr, 0, 0, 0);
+                            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(H.x, P.y, ci, 0, 0, 0);
+                            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(H.y, P.x, ci, 0, 0, 0);
+                        }
+                        Cr[j] = cr;
+                        Ci[j] = ci;
+                    }
+                }
+                __syncthreads();
+            }
+            // ---- fold: dPhi_t[a0][c] += s_t Re(e_lambda(a0_t)_a0 exp(i q.C_t) D_t[c])
+#pragma unroll
+            for (int j = 0; j < MAXP; ++j) {
+                const int pi = pass * pass_size + j * kWavesPerBlock + wave;
+                if (pi < a.n_pairs) {
+                    const int32_t* PP = pairs + pi * 4;
+                    const int32_t tbeg = PP[1], tcnt = PP[2], cbeg = PP[3];
+                    const int cc = cbeg + li;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ti = 4 * r + lk;  // D row held in register r of this lane
+                        if (ti < tcnt && cc < NC) {
+                            const int t = tbeg + ti;
+                            const int32_t a0 = tmeta[t * 8];
+                            const uint32_t kq = (uint32_t)(c00 * tc[t * 4] + c01 * tc[t * 4 + 1] + c02 * tc[t * 4 + 2]);
+                            const double2 phq = sroots[mod_l(kq, geo.L, geo.magic)];
+                            const double2 D = cmul(phq, make_double2(Cr[j][r], Ci[j][r]));
+                            const double sc = tscale[t];
+                            double* out = mypart + (int64_t)t * NCOMP + cc;
+#pragma unroll
+                            for (int al = 0; al < 3; ++al) {
+                                const double2 e = evec[(int64_t)g0 * nb + 3 * a0 + al];
+                                out[al * NC] += sc * (e.x * D.x - e.y * D.y);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// dphi[perm[t]][k] (+)= sum_b gpart[b][t][k], summed in block order.
+__global__ void k_grad_reduce(const double* __restrict__ gpart, int64_t n_blocks, int64_t n_terms, int32_t ncomp,
+                              const int32_t* __restrict__ perm, int accumulate, double* __restrict__ dphi) {
+    const int64_t n = n_terms * ncomp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t b = 0; b < n_blocks; ++b) s += gpart[b * n + i];
+        const int64_t t = i / ncomp, k = i % ncomp;
+        double* o = dphi + (int64_t)perm[t] * ncomp + k;
+        *o = accumulate ? *o + s : s;
+    }
+}
+
+}  // namespace fpk

@@ -287,8 +287,117 @@ __device__ inline int wrapn(int x, int n) {
     return x < 0 ? x + n : x;
 }
 
-template <int M, int MAXT>
-__global__ __launch_bounds__(kBlock, 2) void k_rates(FP_RATES_PARAMS) {
+// One listed process as seen by one lane: partner modes, signed partner
+// wavevectors (mesh integers), and the weight w G(Delta)/prod(omega).  An empty
+// slot (past the end of the unit, or a record outside the mesh) points every
+// index at the row's own mode and carries weight 0, so the uniform loops below
+// read only valid memory and add nothing.
+struct Proc {
+    int32_t g1, g2, gl;
+    int32_t Q10, Q11, Q12, Q20, Q21, Q22;
+    double base;
+};
+
+template <int M>
+__device__ inline Proc setup_proc(bool have, uint64_t rec, int type, int s1, int s2, int s3, int32_t g0, int32_t c00,
+                                  int32_t c01, int32_t c02, double w0, const ModeGeom& geo,
+                                  const double* __restrict__ omega, int64_t n_modes, int* __restrict__ flag,
+                                  double inv_sigma2, double gnorm) {
+    Proc p;
+    p.g1 = p.g2 = p.gl = g0;
+    p.Q10 = p.Q11 = p.Q12 = p.Q20 = p.Q21 = p.Q22 = 0;
+    p.base = 0.0;
+    if (!have) return p;
+    const int nb = geo.nb;
+    const int32_t g1 = (int32_t)(rec & 0xFFFFFFu);
+    int32_t g2, j_last;
+    if (M == 3) {
+        g2 = 0;
+        j_last = (int32_t)((rec >> 24) & 0xFFu);
+    } else {
+        g2 = (int32_t)((rec >> 24) & 0xFFFFFFu);
+        j_last = (int32_t)((rec >> 48) & 0xFFu);
+    }
+    if (g1 >= n_modes || g2 >= n_modes || j_last >= nb) {
+        raise_flag(flag);
+        return p;
+    }
+    // signed wavevectors of the listed partners; the last partner follows from momentum
+    const int32_t iq1 = g1 / nb;
+    const int32_t c10 = iq1 / (geo.N1 * geo.N2), c11 = (iq1 / geo.N2) % geo.N1, c12 = iq1 % geo.N2;
+    p.Q10 = s1 > 0 ? c10 : wrapn(-c10, geo.N0);
+    p.Q11 = s1 > 0 ? c11 : wrapn(-c11, geo.N1);
+    p.Q12 = s1 > 0 ? c12 : wrapn(-c12, geo.N2);
+    if (M == 4) {
+        const int32_t iq2 = g2 / nb;
+        const int32_t c20 = iq2 / (geo.N1 * geo.N2), c21 = (iq2 / geo.N2) % geo.N1, c22 = iq2 % geo.N2;
+        p.Q20 = s2 > 0 ? c20 : wrapn(-c20, geo.N0);
+        p.Q21 = s2 > 0 ? c21 : wrapn(-c21, geo.N1);
+        p.Q22 = s2 > 0 ? c22 : wrapn(-c22, geo.N2);
+    }
+    const int sl = M == 3 ? s2 : s3;
+    // Q_last = -(q + Q1 (+ Q2)); q_last = s_last * Q_last
+    int32_t ql0 = wrapn(-(c00 + p.Q10 + p.Q20), geo.N0);
+    int32_t ql1 = wrapn(-(c01 + p.Q11 + p.Q21), geo.N1);
+    int32_t ql2 = wrapn(-(c02 + p.Q12 + p.Q22), geo.N2);
+    if (sl < 0) {
+        ql0 = wrapn(-ql0, geo.N0);
+        ql1 = wrapn(-ql1, geo.N1);
+        ql2 = wrapn(-ql2, geo.N2);
+    }
+    const int32_t gl = ((ql0 * geo.N1 + ql1) * geo.N2 + ql2) * nb + j_last;
+    const double w1 = omega[g1];
+    const double wl = omega[gl];
+    const double w2 = M == 4 ? omega[g2] : wl;
+    double delta = s1 > 0 ? w0 + w1 : w0 - w1;
+    delta = s2 > 0 ? delta + w2 : delta - w2;
+    if (M == 4) delta = s3 > 0 ? delta + wl : delta - wl;
+    double wprod = w0 * w1 * w2;
+    if (M == 4) wprod *= wl;
+    // triangle weight from equality of interchangeable partners
+    double wt = 1.0;
+    if (M == 3) {
+        if (type == 1 && g1 == gl) wt = 0.5;
+    } else if (type == 2) {
+        if (g1 == g2) wt = 0.5;
+    } else if (type == 3) {
+        if (g2 == gl) wt = 0.5;
+    } else {
+        const int eq = (g1 == g2) + (g2 == gl) + (g1 == gl);
+        wt = eq == 3 ? (1.0 / 6.0) : (eq >= 1 ? 0.5 : 1.0);
+    }
+    p.g1 = g1;
+    p.g2 = M == 4 ? g2 : gl;  // order 3: slot 2 is the momentum-fixed partner
+    p.gl = gl;
+    p.base = wt * exp(-(delta * delta) * inv_sigma2) * gnorm / wprod;
+    return p;
+}
+
+__device__ inline double2 cfma(double2 acc, double2 a, double2 b) {
+    acc.x += a.x * b.x;
+    acc.x -= a.y * b.y;
+    acc.y += a.x * b.y;
+    acc.y += a.y * b.x;
+    return acc;
+}
+
+__device__ inline double2 ld_eps(const double2* __restrict__ e, double csign) {
+    double2 v = *e;
+    v.y *= csign;
+    return v;
+}
+
+// Contraction variants (wave-uniform force-constant stream, per-lane eigenvectors):
+//   CT = 0  P-form: P = eps1 (x) eps2 (x) eps3 once per partner-atom group, then
+//           27 complex MACs + 1 phase MAC per term (order 4; order 3: 9 + 1)
+//   CT = 1  W-form: w = eps2 (x) eps3 per group, then per term 27 MACs into three
+//           partial sums u_beta, 3 MACs with eps1, 1 phase MAC (order 4 only);
+//           a third of the P-form's registers for 3 more MACs per term
+// NP processes per lane are evaluated together, so every scalar-loaded
+// force-constant value feeds NP times as many FMAs.
+template <int M, int MAXT, int CT, int NP, int WAVES>
+__global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
+    constexpr int NC = M == 3 ? 9 : 27;
     __shared__ double2 sroots[kMaxRoots];
     for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
     __syncthreads();
@@ -318,195 +427,185 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates(FP_RATES_PARAMS) {
             const int type = __builtin_amdgcn_readfirstlane(ri.type);
             int s1, s2, s3;
             type_signs(type, s1, s2, s3);
+            const int sl = M == 3 ? s2 : s3;
+            const double c1 = s1 > 0 ? 1.0 : -1.0;
+            const double c2 = s2 > 0 ? 1.0 : -1.0;
+            const double c3 = sl > 0 ? 1.0 : -1.0;
             const int32_t iq0 = g0 / nb;
             const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
             const double w0 = omega[g0];
-            const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * (M == 3 ? 9 : 27);
-            for (int p = 0; p < a.ppl; ++p) {
-                const int idx = p * kWave + lane;
-                if (idx >= count) break;
-                const uint64_t rec = ri.rec[ud.start + idx];
-                const int32_t g1 = (int32_t)(rec & 0xFFFFFFu);
-                int32_t g2, j_last;
-                if (M == 3) {
-                    g2 = 0;
-                    j_last = (int32_t)((rec >> 24) & 0xFFu);
-                } else {
-                    g2 = (int32_t)((rec >> 24) & 0xFFFFFFu);
-                    j_last = (int32_t)((rec >> 48) & 0xFFu);
+            const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * NC;
+            for (int p0 = 0; p0 * kWave < count; p0 += NP) {
+                Proc pr[NP];
+#pragma unroll
+                for (int i = 0; i < NP; ++i) {
+                    const int idx = (p0 + i) * kWave + lane;
+                    const bool have = idx < count && p0 + i < a.ppl;
+                    const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
+                    pr[i] = setup_proc<M>(have, rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
+                                          flag, a.inv_sigma2, a.gnorm);
                 }
-                if (g1 >= a.n_modes || g2 >= a.n_modes || j_last >= nb) {
-                    raise_flag(flag);
-                    continue;
-                }
-                // signed wavevectors of the listed partners, last partner by momentum
-                const int32_t iq1 = g1 / nb;
-                const int32_t c10 = iq1 / (geo.N1 * geo.N2), c11 = (iq1 / geo.N2) % geo.N1, c12 = iq1 % geo.N2;
-                const int32_t Q10 = s1 > 0 ? c10 : wrapn(-c10, geo.N0);
-                const int32_t Q11 = s1 > 0 ? c11 : wrapn(-c11, geo.N1);
-                const int32_t Q12 = s1 > 0 ? c12 : wrapn(-c12, geo.N2);
-                int32_t Q20 = 0, Q21 = 0, Q22 = 0;
-                if (M == 4) {
-                    const int32_t iq2 = g2 / nb;
-                    const int32_t c20 = iq2 / (geo.N1 * geo.N2), c21 = (iq2 / geo.N2) % geo.N1, c22 = iq2 % geo.N2;
-                    Q20 = s2 > 0 ? c20 : wrapn(-c20, geo.N0);
-                    Q21 = s2 > 0 ? c21 : wrapn(-c21, geo.N1);
-                    Q22 = s2 > 0 ? c22 : wrapn(-c22, geo.N2);
-                }
-                const int sl = M == 3 ? s2 : s3;
-                // Q_last = -(q + Q1 (+ Q2)); q_last = s_last * Q_last
-                int32_t ql0 = wrapn(-(c00 + Q10 + Q20), geo.N0);
-                int32_t ql1 = wrapn(-(c01 + Q11 + Q21), geo.N1);
-                int32_t ql2 = wrapn(-(c02 + Q12 + Q22), geo.N2);
-                if (sl < 0) {
-                    ql0 = wrapn(-ql0, geo.N0);
-                    ql1 = wrapn(-ql1, geo.N1);
-                    ql2 = wrapn(-ql2, geo.N2);
-                }
-                const int32_t gl = ((ql0 * geo.N1 + ql1) * geo.N2 + ql2) * nb + j_last;
-                const double w1 = omega[g1];
-                const double wl = omega[gl];
-                const double w2 = M == 4 ? omega[g2] : wl;
-                double delta = s1 > 0 ? w0 + w1 : w0 - w1;
-                delta = s2 > 0 ? delta + w2 : delta - w2;
-                if (M == 4) delta = s3 > 0 ? delta + wl : delta - wl;
-                double wprod = w0 * w1 * w2;
-                if (M == 4) wprod *= wl;
-                // triangle weight from equality of interchangeable partners
-                double wt = 1.0;
-                if (M == 3) {
-                    if (type == 1 && g1 == gl) wt = 0.5;
-                } else if (type == 2) {
-                    if (g1 == g2) wt = 0.5;
-                } else if (type == 3) {
-                    if (g2 == gl) wt = 0.5;
-                } else {
-                    const int eq = (g1 == g2) + (g2 == gl) + (g1 == gl);
-                    wt = eq == 3 ? (1.0 / 6.0) : (eq >= 1 ? 0.5 : 1.0);
-                }
-                const double base = wt * exp(-(delta * delta) * a.inv_sigma2) * a.gnorm / wprod;
-
-                // ---- matrix element
-                const double2* __restrict__ e1 = evec + (int64_t)g1 * nb;
-                const double2* __restrict__ e2 = evec + (int64_t)(M == 4 ? g2 : gl) * nb;
-                const double2* __restrict__ e3 = evec + (int64_t)gl * nb;
-                const double c1 = s1 > 0 ? 1.0 : -1.0;
-                const double c2 = s2 > 0 ? 1.0 : -1.0;
-                const double c3 = sl > 0 ? 1.0 : -1.0;
-                double Vr = 0.0, Vi = 0.0;
+                double2 V[NP];
+#pragma unroll
+                for (int i = 0; i < NP; ++i) V[i] = make_double2(0.0, 0.0);
                 for (int gi = 0; gi < a.n_groups; ++gi) {
                     const int32_t* G = groups + gi * 8;
                     const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
                     if (M == 3) {
-                        double2 x[3], y[3];
+                        double2 P[NP][9];
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            x[k] = e1[3 * ab + k];
-                            x[k].y *= c1;
-                            y[k] = e2[3 * ac + k];
-                            y[k].y *= c2;
+                        for (int i = 0; i < NP; ++i) {
+                            const double2* e1 = evec + (int64_t)pr[i].g1 * nb + 3 * ab;
+                            const double2* e2 = evec + (int64_t)pr[i].g2 * nb + 3 * ac;
+                            double2 x[3], y[3];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                x[k] = ld_eps(e1 + k, c1);
+                                y[k] = ld_eps(e2 + k, c2);
+                            }
+#pragma unroll
+                            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) P[i][b * 3 + c] = cmul(x[b], y[c]);
                         }
-                        double2 P[9];
-#pragma unroll
-                        for (int b = 0; b < 3; ++b)
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) P[b * 3 + c] = cmul(x[b], y[c]);
                         for (int t = t0; t < t1; ++t) {
                             const int32_t* tm = tmeta + t * 8;
-                            const uint32_t k = (uint32_t)(Q10 * tm[1] + Q11 * tm[2] + Q12 * tm[3]);
-                            const double2 ph = sroots[mod_l(k, geo.L, geo.magic)];
                             const double2* F = phit_row + (int64_t)t * 9;
-                            double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+                            double2 sacc[NP];
 #pragma unroll
-                            for (int c = 0; c < 9; c += 2) {
+                            for (int i = 0; i < NP; ++i) sacc[i] = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int c = 0; c < 9; ++c) {
                                 const double2 f = F[c];
-                                sr0 += f.x * P[c].x;
-                                sr0 -= f.y * P[c].y;
-                                si0 += f.x * P[c].y;
-                                si0 += f.y * P[c].x;
-                                if (c + 1 < 9) {
-                                    const double2 h = F[c + 1];
-                                    sr1 += h.x * P[c + 1].x;
-                                    sr1 -= h.y * P[c + 1].y;
-                                    si1 += h.x * P[c + 1].y;
-                                    si1 += h.y * P[c + 1].x;
+#pragma unroll
+                                for (int i = 0; i < NP; ++i) sacc[i] = cfma(sacc[i], f, P[i][c]);
+                            }
+#pragma unroll
+                            for (int i = 0; i < NP; ++i) {
+                                const uint32_t k = (uint32_t)(pr[i].Q10 * tm[1] + pr[i].Q11 * tm[2] + pr[i].Q12 * tm[3]);
+                                V[i] = cfma(V[i], sroots[mod_l(k, geo.L, geo.magic)], sacc[i]);
+                            }
+                        }
+                    } else if (CT == 0) {
+                        double2 P[NP][27];
+#pragma unroll
+                        for (int i = 0; i < NP; ++i) {
+                            const double2* e1 = evec + (int64_t)pr[i].g1 * nb + 3 * ab;
+                            const double2* e2 = evec + (int64_t)pr[i].g2 * nb + 3 * ac;
+                            const double2* e3 = evec + (int64_t)pr[i].gl * nb + 3 * ad;
+                            double2 x[3], y[3], z[3];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                x[k] = ld_eps(e1 + k, c1);
+                                y[k] = ld_eps(e2 + k, c2);
+                                z[k] = ld_eps(e3 + k, c3);
+                            }
+#pragma unroll
+                            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) {
+                                    const double2 xy = cmul(x[b], y[c]);
+#pragma unroll
+                                    for (int d = 0; d < 3; ++d) P[i][(b * 3 + c) * 3 + d] = cmul(xy, z[d]);
+                                }
+                        }
+                        for (int t = t0; t < t1; ++t) {
+                            const int32_t* tm = tmeta + t * 8;
+                            const double2* F = phit_row + (int64_t)t * 27;
+                            double2 sa[NP], sb[NP];
+#pragma unroll
+                            for (int i = 0; i < NP; ++i) sa[i] = sb[i] = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int c = 0; c < 27; ++c) {
+                                const double2 f = F[c];
+#pragma unroll
+                                for (int i = 0; i < NP; ++i) {
+                                    if (c & 1) sb[i] = cfma(sb[i], f, P[i][c]);
+                                    else sa[i] = cfma(sa[i], f, P[i][c]);
                                 }
                             }
-                            const double sr = sr0 + sr1, si = si0 + si1;
-                            Vr += ph.x * sr - ph.y * si;
-                            Vi += ph.x * si + ph.y * sr;
+#pragma unroll
+                            for (int i = 0; i < NP; ++i) {
+                                const uint32_t k = (uint32_t)(pr[i].Q10 * tm[1] + pr[i].Q11 * tm[2] + pr[i].Q12 * tm[3] +
+                                                              pr[i].Q20 * tm[4] + pr[i].Q21 * tm[5] + pr[i].Q22 * tm[6]);
+                                const double2 s = make_double2(sa[i].x + sb[i].x, sa[i].y + sb[i].y);
+                                V[i] = cfma(V[i], sroots[mod_l(k, geo.L, geo.magic)], s);
+                            }
                         }
                     } else {
-                        double2 x[3], y[3], z[3];
+                        double2 x[NP][3], w[NP][9];
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            x[k] = e1[3 * ab + k];
-                            x[k].y *= c1;
-                            y[k] = e2[3 * ac + k];
-                            y[k].y *= c2;
-                            z[k] = e3[3 * ad + k];
-                            z[k].y *= c3;
-                        }
-                        double2 P[27];
+                        for (int i = 0; i < NP; ++i) {
+                            const double2* e1 = evec + (int64_t)pr[i].g1 * nb + 3 * ab;
+                            const double2* e2 = evec + (int64_t)pr[i].g2 * nb + 3 * ac;
+                            const double2* e3 = evec + (int64_t)pr[i].gl * nb + 3 * ad;
+                            double2 y[3], z[3];
 #pragma unroll
-                        for (int b = 0; b < 3; ++b)
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                const double2 xy = cmul(x[b], y[c]);
-#pragma unroll
-                                for (int d = 0; d < 3; ++d) P[(b * 3 + c) * 3 + d] = cmul(xy, z[d]);
+                            for (int k = 0; k < 3; ++k) {
+                                x[i][k] = ld_eps(e1 + k, c1);
+                                y[k] = ld_eps(e2 + k, c2);
+                                z[k] = ld_eps(e3 + k, c3);
                             }
+#pragma unroll
+                            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                                for (int d = 0; d < 3; ++d) w[i][c * 3 + d] = cmul(y[c], z[d]);
+                        }
                         for (int t = t0; t < t1; ++t) {
                             const int32_t* tm = tmeta + t * 8;
-                            const uint32_t k = (uint32_t)(Q10 * tm[1] + Q11 * tm[2] + Q12 * tm[3] + Q20 * tm[4] +
-                                                          Q21 * tm[5] + Q22 * tm[6]);
-                            const double2 ph = sroots[mod_l(k, geo.L, geo.magic)];
                             const double2* F = phit_row + (int64_t)t * 27;
-                            double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+                            double2 s[NP];
 #pragma unroll
-                            for (int c = 0; c < 27; c += 2) {
-                                const double2 f = F[c];
-                                sr0 += f.x * P[c].x;
-                                sr0 -= f.y * P[c].y;
-                                si0 += f.x * P[c].y;
-                                si0 += f.y * P[c].x;
-                                if (c + 1 < 27) {
-                                    const double2 h = F[c + 1];
-                                    sr1 += h.x * P[c + 1].x;
-                                    sr1 -= h.y * P[c + 1].y;
-                                    si1 += h.x * P[c + 1].y;
-                                    si1 += h.y * P[c + 1].x;
+                            for (int i = 0; i < NP; ++i) s[i] = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) {
+                                double2 uu[NP];
+#pragma unroll
+                                for (int i = 0; i < NP; ++i) uu[i] = make_double2(0.0, 0.0);
+#pragma unroll
+                                for (int c = 0; c < 9; ++c) {
+                                    const double2 f = F[b * 9 + c];
+#pragma unroll
+                                    for (int i = 0; i < NP; ++i) uu[i] = cfma(uu[i], f, w[i][c]);
                                 }
+#pragma unroll
+                                for (int i = 0; i < NP; ++i) s[i] = cfma(s[i], uu[i], x[i][b]);
                             }
-                            const double sr = sr0 + sr1, si = si0 + si1;
-                            Vr += ph.x * sr - ph.y * si;
-                            Vi += ph.x * si + ph.y * sr;
+#pragma unroll
+                            for (int i = 0; i < NP; ++i) {
+                                const uint32_t k = (uint32_t)(pr[i].Q10 * tm[1] + pr[i].Q11 * tm[2] + pr[i].Q12 * tm[3] +
+                                                              pr[i].Q20 * tm[4] + pr[i].Q21 * tm[5] + pr[i].Q22 * tm[6]);
+                                V[i] = cfma(V[i], sroots[mod_l(k, geo.L, geo.magic)], s[i]);
+                            }
                         }
                     }
                 }
-                const double V2 = Vr * Vr + Vi * Vi;
 
                 // ---- occupation per temperature
 #pragma unroll
-                for (int it = 0; it < MAXT; ++it) {
-                    if (it < a.n_T) {
-                        const double* n = occ + (int64_t)it * a.n_modes;
-                        const double n1 = n[g1], nl = n[gl];
-                        double occ;
-                        if (M == 3) {
-                            occ = type == 0 ? n1 - nl : 1.0 + n1 + nl;
-                        } else {
-                            const double n2 = n[g2];
-                            if (type == 2)
-                                occ = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
-                            else if (type == 3)
-                                occ = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
-                            else
-                                occ = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
+                for (int i = 0; i < NP; ++i) {
+                    const double V2 = V[i].x * V[i].x + V[i].y * V[i].y;
+#pragma unroll
+                    for (int it = 0; it < MAXT; ++it) {
+                        if (it < a.n_T) {
+                            const double* n = occ + (int64_t)it * a.n_modes;
+                            const double n1 = n[pr[i].g1], nl = n[pr[i].gl];
+                            double oc;
+                            if (M == 3) {
+                                oc = type == 0 ? n1 - nl : 1.0 + n1 + nl;
+                            } else {
+                                const double n2 = n[pr[i].g2];
+                                if (type == 2)
+                                    oc = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
+                                else if (type == 3)
+                                    oc = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
+                                else
+                                    oc = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
+                            }
+                            const double xw = pr[i].base * oc;
+                            accw[it] += xw;
+                            accg[it] += xw * V2;
                         }
-                        const double x = base * occ;
-                        accw[it] += x;
-                        accg[it] += x * V2;
                     }
                 }
             }

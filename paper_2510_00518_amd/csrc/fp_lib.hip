@@ -14,6 +14,7 @@
 
 #include "fp.h"
 #include "fp_kernels.h"
+#include "fp_grad.h"
 
 namespace {
 
@@ -61,11 +62,12 @@ struct IfcState {
     int32_t n_groups = 0;
     std::vector<int32_t> atoms, cells;  // structure as loaded, to skip re-uploads
     DevBuf<double> raw, phi_s, scale;
-    DevBuf<int32_t> perm, tmeta, tc, groups;
+    DevBuf<int32_t> perm, tmeta, tc, groups, pairs;
+    int32_t n_pairs = 0;  // 16-term x 16-component tiles of the adjoint, within groups
     void release() {
         raw.release(); phi_s.release(); scale.release();
-        perm.release(); tmeta.release(); tc.release(); groups.release();
-        order = 0; n_terms = 0; n_groups = 0;
+        perm.release(); tmeta.release(); tc.release(); groups.release(); pairs.release();
+        order = 0; n_terms = 0; n_groups = 0; n_pairs = 0;
         atoms.clear(); cells.clear();
     }
 };
@@ -95,10 +97,13 @@ struct fp_ctx {
     DevBuf<int64_t> row_units, unit_off;
     DevBuf<fpk::UnitDesc> units;
     DevBuf<double2> phit;
+    DevBuf<double> gpart;
     int* flag = nullptr;
     // tuning knobs
     int32_t ppl = 2;
-    int32_t blocks_per_cu = 2;
+    int32_t blocks_per_cu = 0;  // 0: as many resident blocks as the kernel's occupancy allows
+    int32_t variant = 1;        // order-4 contraction variant (see k_rates)
+    int32_t grad_chunk = 8192;  // records per adjoint chunk (a multiple of 256)
     // kernel timing
     bool profile = false;
     std::vector<hipEvent_t> ev_pool;
@@ -135,6 +140,8 @@ int64_t gcd64(int64_t a, int64_t b) {
 }
 
 int64_t wrapi(int64_t x, int64_t n) { return ((x % n) + n) % n; }
+
+int ORDER_OF(int32_t type) { return type == FP_3P || type == FP_3M ? 3 : 4; }
 
 fpk::ModeGeom geometry(const fp_ctx* c) {
     fpk::ModeGeom g;
@@ -192,7 +199,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->omega.release(); c->vel.release(); c->evec.release(); c->roots.release();
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
-    c->unit_off.release(); c->units.release(); c->phit.release();
+    c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release();
     if (c->flag) (void)hipFree(c->flag);
     for (auto& e : c->ev_used) {
         (void)hipEventDestroy(e.second.first);
@@ -210,8 +217,14 @@ extern "C" fp_status fp_set_knob(fp_ctx* c, const char* name, int64_t value) {
         if (value < 1 || value > 64) return fail(c, FP_ERR_ARG, "ppl must be in [1, 64]");
         c->ppl = (int32_t)value;
     } else if (!strcmp(name, "blocks_per_cu")) {
-        if (value < 1 || value > 16) return fail(c, FP_ERR_ARG, "blocks_per_cu must be in [1, 16]");
+        if (value < 0 || value > 16) return fail(c, FP_ERR_ARG, "blocks_per_cu must be in [0, 16]");
         c->blocks_per_cu = (int32_t)value;
+    } else if (!strcmp(name, "grad_chunk")) {
+        if (value < 256 || value > (1 << 22) || value % 256) return fail(c, FP_ERR_ARG, "grad_chunk: 256..2^22, multiple of 256");
+        c->grad_chunk = (int32_t)value;
+    } else if (!strcmp(name, "variant")) {
+        if (value < 0 || value > 3) return fail(c, FP_ERR_ARG, "variant must be in [0, 3]");
+        c->variant = (int32_t)value;
     } else {
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
     }
@@ -332,6 +345,17 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
                 groups[groups.size() - 8 + 4] = (int32_t)i + 1;
             }
         }
+        // adjoint tiles: 16 consecutive terms of one group x 16 components
+        std::vector<int32_t> pairs;
+        const int nc = m == 3 ? 9 : 27;
+        for (size_t g = 0; g + 8 <= groups.size(); g += 8) {
+            const int32_t t0 = groups[g + 3], t1 = groups[g + 4];
+            for (int32_t tb = t0; tb < t1; tb += 16)
+                for (int cb = 0; cb < nc; cb += 16) {
+                    const int32_t e[4] = {(int32_t)(g / 8), tb, std::min<int32_t>(16, t1 - tb), cb};
+                    pairs.insert(pairs.end(), e, e + 4);
+                }
+        }
         HIP_TRY(c, hipStreamSynchronize(st));  // previous launches may still read the old tables
         HIP_TRY(c, S.perm.ensure((size_t)n_terms));
         HIP_TRY(c, S.scale.ensure((size_t)n_terms));
@@ -344,6 +368,9 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
         HIP_TRY(c, hipMemcpy(S.tmeta.p, tmeta.data(), tmeta.size() * 4, hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(S.tc.p, tc.data(), tc.size() * 4, hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(S.groups.p, groups.data(), groups.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(c, S.pairs.ensure(pairs.size()));
+        HIP_TRY(c, hipMemcpy(S.pairs.p, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
+        S.n_pairs = (int32_t)(pairs.size() / 4);
         S.order = m;
         S.n_terms = n_terms;
         S.n_groups = (int32_t)(groups.size() / 8);
@@ -365,138 +392,247 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
 
 namespace {
 
-fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
-                    double sigma, int32_t precision, double* gamma_out, double* wp_out, void* stream) {
-    if (!c) return FP_ERR_ARG;
+// order-4 contraction variants: (form, processes per lane)
+struct Variant {
+    int ct, np;
+};
+constexpr Variant kVariants[4] = {{0, 1}, {1, 1}, {1, 2}, {0, 2}};
+
+template <int M, int T, int CT, int NP>
+fp_status launch_rates(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
+    auto kern = fpk::k_rates<M, T, CT, NP, 1>;
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
+    const int64_t want = (n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
+    nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+template <int M, int T>
+fp_status launch_variant(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
+    if (M == 3) return launch_rates<3, T, 0, 1>(c, st, n_units, a, S);
+    switch (c->variant) {
+        case 1: return launch_rates<4, T, 1, 1>(c, st, n_units, a, S);
+        case 2: return launch_rates<4, T, 1, 2>(c, st, n_units, a, S);
+        case 3: return launch_rates<4, T, 0, 2>(c, st, n_units, a, S);
+        default: return launch_rates<4, T, 0, 1>(c, st, n_units, a, S);
+    }
+}
+
+double rate_prefactor(const fp_ctx* c, int m) {
+    const double N = (double)c->nq;
+    return m == 3 ? kPi * kHbar / (4.0 * N) : kPi * kHbar * kHbar / (8.0 * N * N);
+}
+
+// Checks shared by the rate and adjoint calls.
+fp_status check_common(fp_ctx* c, int n_lists, const fp_plist* lists, int32_t n_T, const double* T_K, double sigma) {
     if (!c->modes) return fail(c, FP_ERR_STATE, "fp_load_modes must come first");
-    IfcState& S = c->ifc[m - 3];
-    if (S.order != m) return fail(c, FP_ERR_STATE, "force constants of order %d not loaded", m);
-    const bool accumulate = (precision & FP_ACCUMULATE) != 0;
-    precision &= ~FP_ACCUMULATE;
-    if (precision != FP_FP64)
-        return fail(c, FP_ERR_UNSUPPORTED, "only FP_FP64 is available for order %d", m);
     if (n_lists < 0 || n_lists > FP_MAX_LISTS || (n_lists > 0 && !lists))
         return fail(c, FP_ERR_ARG, "n_lists must be in [0, %d]", FP_MAX_LISTS);
     if (n_T < 1 || n_T > FP_MAX_T || !T_K) return fail(c, FP_ERR_ARG, "n_T must be in [1, %d]", FP_MAX_T);
     for (int i = 0; i < n_T; ++i)
         if (!(T_K[i] > 0.0) || !std::isfinite(T_K[i])) return fail(c, FP_ERR_ARG, "temperatures must be > 0");
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(c, FP_ERR_ARG, "sigma must be > 0");
-    fpk::ListsArg la;
-    memset(&la, 0, sizeof la);
-    la.n_lists = n_lists;
-    int64_t total_rows = 0, n_units_max = 0;
-    const int64_t unit = (int64_t)fpk::kWave * c->ppl;
     for (int l = 0; l < n_lists; ++l) {
         const fp_plist& P = lists[l];
-        const bool ok_type = m == 3 ? (P.type == FP_3P || P.type == FP_3M)
-                                    : (P.type == FP_4PP || P.type == FP_4PM || P.type == FP_4MM);
-        if (!ok_type) return fail(c, FP_ERR_ARG, "list %d has type %d, not of order %d", l, P.type, m);
+        if (P.type < FP_3P || P.type > FP_4MM) return fail(c, FP_ERR_ARG, "list %d has unknown type %d", l, P.type);
         if (P.n_rows < 0 || P.n_rec < 0) return fail(c, FP_ERR_ARG, "list %d: negative size", l);
         if (P.n_rows > 0 && (!P.row_mode || !P.row_off)) return fail(c, FP_ERR_ARG, "list %d: null row arrays", l);
         if (P.n_rec > 0 && !P.rec) return fail(c, FP_ERR_ARG, "list %d: null records", l);
-        la.l[l].type = P.type;
-        la.l[l].n_rows = P.n_rows;
-        la.l[l].row_base = total_rows;
-        la.l[l].n_rec = P.n_rec;
-        la.l[l].row_mode = P.row_mode;
-        la.l[l].row_off = P.row_off;
-        la.l[l].rec = P.rec;
+    }
+    return FP_OK;
+}
+
+struct Prepared {
+    fpk::ListsArg la;
+    int64_t total_rows = 0, n_units = 0;
+    fpk::ModeGeom geo;
+};
+
+// Per-call device tables for the lists of order m (sel[] picks them): Bose
+// table, row table, work units of `unit` records, and the pre-contracted
+// force constants of every row.
+fp_status prepare(fp_ctx* c, int m, const fp_plist* lists, const std::vector<int>& sel, int32_t n_T,
+                  const double* T_K, int64_t unit, hipStream_t st, Prepared* pp) {
+    IfcState& S = c->ifc[m - 3];
+    fpk::ListsArg& la = pp->la;
+    memset(&la, 0, sizeof la);
+    la.n_lists = (int32_t)sel.size();
+    int64_t total_rows = 0, n_units = 0;
+    for (size_t k = 0; k < sel.size(); ++k) {
+        const fp_plist& P = lists[sel[k]];
+        la.l[k].type = P.type;
+        la.l[k].n_rows = P.n_rows;
+        la.l[k].row_base = total_rows;
+        la.l[k].n_rec = P.n_rec;
+        la.l[k].row_mode = P.row_mode;
+        la.l[k].row_off = P.row_off;
+        la.l[k].rec = P.rec;
         total_rows += P.n_rows;
-        n_units_max += (P.n_rec + unit - 1) / unit + P.n_rows;
+        n_units += (P.n_rec + unit - 1) / unit + P.n_rows;
     }
     la.total_rows = total_rows;
+    pp->total_rows = total_rows;
+    pp->n_units = n_units;
+    pp->geo = geometry(c);
     if (total_rows > (int64_t(1) << 30)) return fail(c, FP_ERR_UNSUPPORTED, "too many rows");
-    hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(c, hipSetDevice(c->device));
+    if (total_rows == 0) return FP_OK;
     const int64_t nm = c->n_modes;
     const int ncomp = m == 3 ? 9 : 27;
-    // scratch
     HIP_TRY(c, c->occ.ensure((size_t)n_T * nm));
-    HIP_TRY(c, c->rows.ensure((size_t)std::max<int64_t>(total_rows, 1)));
+    HIP_TRY(c, c->rows.ensure((size_t)total_rows));
     HIP_TRY(c, c->row_units.ensure((size_t)total_rows + 1));
     HIP_TRY(c, c->unit_off.ensure((size_t)total_rows + 1));
-    HIP_TRY(c, c->units.ensure((size_t)std::max<int64_t>(n_units_max, 1)));
-    HIP_TRY(c, c->partial.ensure((size_t)std::max<int64_t>(n_units_max, 1) * 2 * n_T));
-    HIP_TRY(c, c->phit.ensure((size_t)std::max<int64_t>(total_rows, 1) * S.n_terms * ncomp));
-
+    HIP_TRY(c, c->units.ensure((size_t)std::max<int64_t>(n_units, 1)));
+    HIP_TRY(c, c->phit.ensure((size_t)total_rows * S.n_terms * ncomp));
     fpk::Temps tx;
     for (int i = 0; i < 8; ++i) tx.x[i] = i < n_T ? kHbar / (kBoltz * T_K[i]) : 0.0;
-    // outputs are overwritten unless accumulating: zero them first
-    if (gamma_out && !accumulate)
-        hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, gamma_out, n_T * nm, 0.0);
-    if (wp_out && !accumulate)
-        hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, wp_out, n_T * nm, 0.0);
-    if (total_rows == 0) {
-        HIP_TRY(c, hipGetLastError());
-        return FP_OK;
-    }
     hipLaunchKernelGGL(fpk::k_occ, dim3(grid_for(n_T * nm)), dim3(256), 0, st, c->omega.p, nm, n_T, tx, c->floor_,
                        c->occ.p);
     hipLaunchKernelGGL(fpk::k_rows, dim3(grid_for(total_rows)), dim3(256), 0, st, la, nm, unit, c->rows.p,
                        c->row_units.p, c->flag);
     hipLaunchKernelGGL(fpk::k_scan, dim3(1), dim3(fpk::kBlock), 0, st, c->row_units.p, total_rows, c->unit_off.p);
-    hipLaunchKernelGGL(fpk::k_units, dim3(grid_for(n_units_max)), dim3(256), 0, st, c->unit_off.p, total_rows,
-                       c->rows.p, unit, n_units_max, c->units.p);
-    const fpk::ModeGeom geo = geometry(c);
+    hipLaunchKernelGGL(fpk::k_units, dim3(grid_for(n_units)), dim3(256), 0, st, c->unit_off.p, total_rows, c->rows.p,
+                       unit, n_units, c->units.p);
     const int64_t npre = total_rows * S.n_terms * ncomp;
     if (m == 3)
         hipLaunchKernelGGL(fpk::k_precontract<3>, dim3(grid_for(npre)), dim3(256), 0, st, c->rows.p, total_rows,
-                           c->evec.p, c->roots.p, geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+                           c->evec.p, c->roots.p, pp->geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
     else
         hipLaunchKernelGGL(fpk::k_precontract<4>, dim3(grid_for(npre)), dim3(256), 0, st, c->rows.p, total_rows,
-                           c->evec.p, c->roots.p, geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+                           c->evec.p, c->roots.p, pp->geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
 
+fp_status timer_start(fp_ctx* c, hipStream_t st, hipEvent_t* ev0, hipEvent_t* ev1) {
+    *ev0 = *ev1 = nullptr;
+    if (!c->profile) return FP_OK;
+    for (hipEvent_t* e : {ev0, ev1}) {
+        if (!c->ev_pool.empty()) {
+            *e = c->ev_pool.back();
+            c->ev_pool.pop_back();
+        } else {
+            HIP_TRY(c, hipEventCreate(e));
+        }
+    }
+    HIP_TRY(c, hipEventRecord(*ev0, st));
+    return FP_OK;
+}
+
+fp_status timer_stop(fp_ctx* c, hipStream_t st, int tag, hipEvent_t ev0, hipEvent_t ev1) {
+    if (!c->profile) return FP_OK;
+    HIP_TRY(c, hipEventRecord(ev1, st));
+    c->ev_used.push_back({tag, {ev0, ev1}});
+    return FP_OK;
+}
+
+fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
+                    double sigma, int32_t precision, double* gamma_out, double* wp_out, void* stream) {
+    if (!c) return FP_ERR_ARG;
+    fp_status cs = check_common(c, n_lists, lists, n_T, T_K, sigma);
+    if (cs != FP_OK) return cs;
+    IfcState& S = c->ifc[m - 3];
+    if (S.order != m) return fail(c, FP_ERR_STATE, "force constants of order %d not loaded", m);
+    const bool accumulate = (precision & FP_ACCUMULATE) != 0;
+    precision &= ~FP_ACCUMULATE;
+    if (precision != FP_FP64) return fail(c, FP_ERR_UNSUPPORTED, "only FP_FP64 is available for order %d", m);
+    std::vector<int> sel;
+    for (int l = 0; l < n_lists; ++l) {
+        if (ORDER_OF(lists[l].type) != m)
+            return fail(c, FP_ERR_ARG, "list %d has type %d, not of order %d", l, lists[l].type, m);
+        sel.push_back(l);
+    }
+    const int np = m == 3 ? 1 : kVariants[c->variant].np;
+    const int64_t ppl = (c->ppl + np - 1) / np * np;
+    const int64_t unit = (int64_t)fpk::kWave * ppl;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t nm = c->n_modes;
+    // outputs are overwritten unless accumulating: zero them first
+    if (gamma_out && !accumulate)
+        hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, gamma_out, n_T * nm, 0.0);
+    if (wp_out && !accumulate)
+        hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, wp_out, n_T * nm, 0.0);
+    Prepared pp;
+    fp_status ps = prepare(c, m, lists, sel, n_T, T_K, unit, st, &pp);
+    if (ps != FP_OK) return ps;
+    if (pp.total_rows == 0) {
+        HIP_TRY(c, hipGetLastError());
+        return FP_OK;
+    }
+    HIP_TRY(c, c->partial.ensure((size_t)std::max<int64_t>(pp.n_units, 1) * 2 * n_T));
     fpk::RatesArgs a;
-    a.n_units = n_units_max;
+    a.n_units = pp.n_units;
     a.n_modes = nm;
     a.n_terms = (int32_t)S.n_terms;
     a.n_groups = S.n_groups;
     a.n_T = n_T;
-    a.ppl = c->ppl;
-    a.geo = geo;
+    a.ppl = (int32_t)ppl;
+    a.geo = pp.geo;
     a.inv_sigma2 = 1.0 / (sigma * sigma);
     a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
-    const int64_t want_blocks = (n_units_max + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
-    int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * c->blocks_per_cu, want_blocks);
-    nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (c->profile) {
-        for (hipEvent_t* e : {&ev0, &ev1}) {
-            if (!c->ev_pool.empty()) {
-                *e = c->ev_pool.back();
-                c->ev_pool.pop_back();
-            } else {
-                HIP_TRY(c, hipEventCreate(e));
-            }
-        }
-        HIP_TRY(c, hipEventRecord(ev0, st));
-    }
-#define FP_LAUNCH(M, T)                                                                                         \
-    hipLaunchKernelGGL((fpk::k_rates<M, T>), dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p,   \
-                       c->occ.p, c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, \
-                       c->flag, a)
-    if (m == 3) {
-        if (tsel == 1) FP_LAUNCH(3, 1); else if (tsel == 4) FP_LAUNCH(3, 4); else FP_LAUNCH(3, 8);
-    } else {
-        if (tsel == 1) FP_LAUNCH(4, 1); else if (tsel == 4) FP_LAUNCH(4, 4); else FP_LAUNCH(4, 8);
-    }
-#undef FP_LAUNCH
-    if (c->profile) {
-        HIP_TRY(c, hipEventRecord(ev1, st));
-        c->ev_used.push_back({m, {ev0, ev1}});
-    }
-    const double N = (double)c->nq;
-    const double pref = m == 3 ? kPi * kHbar / (4.0 * N) : kPi * kHbar * kHbar / (8.0 * N * N);
-    const double wpref = m == 3 ? 1.0 / N : 1.0 / (N * N);
-    for (int l = 0; l < n_lists; ++l) {
-        if (la.l[l].n_rows == 0) continue;
-        hipLaunchKernelGGL(fpk::k_finalize, dim3((unsigned)la.l[l].n_rows), dim3(fpk::kBlock), 0, st, c->partial.p,
-                           c->unit_off.p, c->rows.p, la.l[l].row_base, n_T, pref, wpref, gamma_out, wp_out, nm);
+    hipEvent_t ev0, ev1;
+    fp_status ts = timer_start(c, st, &ev0, &ev1);
+    if (ts != FP_OK) return ts;
+    fp_status ls;
+    if (m == 3)
+        ls = tsel == 1 ? launch_variant<3, 1>(c, st, pp.n_units, a, S)
+                       : (tsel == 4 ? launch_variant<3, 4>(c, st, pp.n_units, a, S)
+                                    : launch_variant<3, 8>(c, st, pp.n_units, a, S));
+    else
+        ls = tsel == 1 ? launch_variant<4, 1>(c, st, pp.n_units, a, S)
+                       : (tsel == 4 ? launch_variant<4, 4>(c, st, pp.n_units, a, S)
+                                    : launch_variant<4, 8>(c, st, pp.n_units, a, S));
+    if (ls != FP_OK) return ls;
+    ts = timer_stop(c, st, m, ev0, ev1);
+    if (ts != FP_OK) return ts;
+    const double pref = rate_prefactor(c, m);
+    const double wpref = m == 3 ? 1.0 / (double)c->nq : 1.0 / ((double)c->nq * (double)c->nq);
+    for (int k = 0; k < pp.la.n_lists; ++k) {
+        if (pp.la.l[k].n_rows == 0) continue;
+        hipLaunchKernelGGL(fpk::k_finalize, dim3((unsigned)pp.la.l[k].n_rows), dim3(fpk::kBlock), 0, st,
+                           c->partial.p, c->unit_off.p, c->rows.p, pp.la.l[k].row_base, n_T, pref, wpref, gamma_out,
+                           wp_out, nm);
     }
     HIP_TRY(c, hipGetLastError());
     if (c->validate) return fp_check(c, stream);
     return FP_OK;
+}
+
+template <int M, int T, int MAXP>
+fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
+                      const double* dldg, double* dphi, bool accumulate) {
+    auto kern = fpk::k_grad<M, T, MAXP>;
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * occ, pp.n_units));
+    const int ncomp = M == 3 ? 27 : 81;
+    const int64_t per = (int64_t)S.n_terms * ncomp;
+    HIP_TRY(c, c->gpart.ensure((size_t)(nblk * per)));
+    hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(nblk * per)), dim3(256), 0, st, c->gpart.p, nblk * per, 0.0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+                       c->roots.p, c->phit.p, S.tmeta.p, S.tc.p, S.groups.p, S.pairs.p, S.scale.p, c->rows.p,
+                       c->units.p, dldg, c->gpart.p, c->flag, a);
+    hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, nblk, S.n_terms, ncomp,
+                       S.perm.p, accumulate ? 1 : 0, dphi);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+template <int M, int T>
+fp_status launch_grad_p(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
+                        const double* dldg, double* dphi, bool accumulate) {
+    if (S.n_pairs <= 16) return launch_grad<M, T, 4>(c, st, pp, a, S, dldg, dphi, accumulate);
+    return launch_grad<M, T, 8>(c, st, pp, a, S, dldg, dphi, accumulate);
 }
 
 }  // namespace
@@ -511,6 +647,69 @@ extern "C" fp_status fp_rates4(fp_ctx* c, const fp_plist* lists, int32_t n_lists
     return run_rates(c, 4, lists, n_lists, n_T, T_K, sigma, precision, gamma_out, wp_out, stream);
 }
 
+extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t n_lists, int32_t n_T,
+                                       const double* T_K, double sigma, int32_t precision, const double* dL_dgamma,
+                                       double* dphi3, double* dphi4, void* stream) {
+    if (!c) return FP_ERR_ARG;
+    fp_status cs = check_common(c, n_lists, lists, n_T, T_K, sigma);
+    if (cs != FP_OK) return cs;
+    const bool accumulate = (precision & FP_ACCUMULATE) != 0;
+    precision &= ~FP_ACCUMULATE;
+    if (precision != FP_FP64) return fail(c, FP_ERR_UNSUPPORTED, "the adjoint is available in FP_FP64 only");
+    if (!dL_dgamma) return fail(c, FP_ERR_ARG, "dL_dgamma is null");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    for (int m = 3; m <= 4; ++m) {
+        double* dphi = m == 3 ? dphi3 : dphi4;
+        if (!dphi) continue;
+        IfcState& S = c->ifc[m - 3];
+        if (S.order != m) return fail(c, FP_ERR_STATE, "force constants of order %d not loaded", m);
+        const int ncomp = m == 3 ? 27 : 81;
+        std::vector<int> sel;
+        for (int l = 0; l < n_lists; ++l)
+            if (ORDER_OF(lists[l].type) == m) sel.push_back(l);
+        Prepared pp;
+        fp_status ps = prepare(c, m, lists, sel, n_T, T_K, c->grad_chunk, st, &pp);
+        if (ps != FP_OK) return ps;
+        if (pp.total_rows == 0) {
+            if (!accumulate)
+                hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(S.n_terms * ncomp)), dim3(256), 0, st, dphi,
+                                   S.n_terms * ncomp, 0.0);
+            continue;
+        }
+        fpk::GradArgs a;
+        memset(&a, 0, sizeof a);
+        a.n_units = pp.n_units;
+        a.n_modes = c->n_modes;
+        a.n_terms = (int32_t)S.n_terms;
+        a.n_groups = S.n_groups;
+        a.n_pairs = S.n_pairs;
+        a.n_T = n_T;
+        a.geo = pp.geo;
+        a.inv_sigma2 = 1.0 / (sigma * sigma);
+        a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+        a.pref = rate_prefactor(c, m);
+        const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
+        hipEvent_t ev0, ev1;
+        fp_status ts = timer_start(c, st, &ev0, &ev1);
+        if (ts != FP_OK) return ts;
+        fp_status ls;
+        if (m == 3)
+            ls = tsel == 1 ? launch_grad_p<3, 1>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
+                           : (tsel == 4 ? launch_grad_p<3, 4>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
+                                        : launch_grad_p<3, 8>(c, st, pp, a, S, dL_dgamma, dphi, accumulate));
+        else
+            ls = tsel == 1 ? launch_grad_p<4, 1>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
+                           : (tsel == 4 ? launch_grad_p<4, 4>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
+                                        : launch_grad_p<4, 8>(c, st, pp, a, S, dL_dgamma, dphi, accumulate));
+        if (ls != FP_OK) return ls;
+        ts = timer_stop(c, st, 10 + m, ev0, ev1);
+        if (ts != FP_OK) return ts;
+    }
+    if (c->validate) return fp_check(c, stream);
+    return FP_OK;
+}
+
 extern "C" fp_status fp_profile(fp_ctx* c, int32_t enable) {
     if (!c) return FP_ERR_ARG;
     for (auto& e : c->ev_used) {
@@ -523,7 +722,7 @@ extern "C" fp_status fp_profile(fp_ctx* c, int32_t enable) {
 }
 
 extern "C" fp_status fp_profile_read(fp_ctx* c, int32_t order, double* total_ms, int64_t* launches) {
-    if (!c || !total_ms || !launches || (order != 3 && order != 4)) return FP_ERR_ARG;
+    if (!c || !total_ms || !launches || (order != 3 && order != 4 && order != 13 && order != 14)) return FP_ERR_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
     double tot = 0.0;
     int64_t n = 0;

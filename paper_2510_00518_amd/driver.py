@@ -101,3 +101,53 @@ class RatePath:
         self.load_ifc()
         self.rates(T, gamma, wp)
         self.kappa(T, gamma, kappa_out)
+
+
+def rates_autograd():
+    """torch.autograd.Function classes over the library: Gamma(phi3, phi4) with the
+    library's adjoint as backward, and kappa_RTA(Gamma) with dkappa/dGamma."""
+    import torch
+
+    class Rates(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, phi3, phi4, path, T):
+            gamma = torch.zeros((len(T), path.n_modes), dtype=torch.float64, device=path.device)
+            path.load_ifc(phi3=phi3.detach().contiguous() if phi3 is not None else None,
+                          phi4=phi4.detach().contiguous() if phi4 is not None else None)
+            path.rates(T, gamma)
+            ctx.path, ctx.T = path, T
+            ctx.has3, ctx.has4 = phi3 is not None, phi4 is not None
+            ctx.save_for_backward(phi3 if phi3 is not None else torch.empty(0),
+                                  phi4 if phi4 is not None else torch.empty(0))
+            return gamma
+
+        @staticmethod
+        def backward(ctx, grad_gamma):
+            path = ctx.path
+            phi3, phi4 = ctx.saved_tensors
+            d3 = torch.zeros_like(phi3) if ctx.has3 else None
+            d4 = torch.zeros_like(phi4) if ctx.has4 else None
+            path.load_ifc(phi3=phi3.detach() if ctx.has3 else None, phi4=phi4.detach() if ctx.has4 else None)
+            fp.fp_rates_backward(path.ctx, path.lists3 + path.lists4, ctx.T, path.cfg["sigma"],
+                                 grad_gamma.contiguous(), d3 if path.lists3 else None, d4 if path.lists4 else None)
+            if d3 is not None and not path.lists3:
+                d3.zero_()
+            if d4 is not None and not path.lists4:
+                d4.zero_()
+            return d3, d4, None, None
+
+    class KappaRTA(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, gamma, path, T):
+            kap = torch.zeros((len(T), 9), dtype=torch.float64, device=path.device)
+            dk = torch.zeros_like(gamma)
+            path.kappa(T, gamma.contiguous(), kap, dk)
+            ctx.save_for_backward(dk)
+            return kap[:, [0, 4, 8]].sum(dim=1) / 3.0
+
+        @staticmethod
+        def backward(ctx, grad_k):
+            (dk,) = ctx.saved_tensors
+            return grad_k[:, None] * dk, None, None
+
+    return Rates, KappaRTA

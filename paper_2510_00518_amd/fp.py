@@ -23,8 +23,8 @@ FP_MAX_T = 8
 FP_MAX_LISTS = 8
 
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
-           "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_profile", "fp_profile_read", "fp_enumerate_count",
-           "fp_enumerate_fill"]
+           "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_profile", "fp_profile_read",
+           "fp_enumerate_count", "fp_enumerate_fill"]
 
 
 class FpError(RuntimeError):
@@ -59,6 +59,7 @@ def lib():
         L.fp_load_ifc.argtypes = [vp, i32, i64, vp, vp, vp, i32, vp]
         for f in (L.fp_rates3, L.fp_rates4):
             f.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp]
+        L.fp_rates_backward.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp, vp]
         L.fp_kappa_rta.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
         L.fp_check.argtypes = [vp, vp]
         L.fp_set_knob.argtypes = [vp, ctypes.c_char_p, i64]
@@ -187,6 +188,13 @@ def fp_rates3(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=No
 
 def fp_rates4(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=None, stream=None):
     _rates(lib().fp_rates4, ctx, lists, T, sigma, precision, gamma_out, wp_out, stream)
+
+
+def fp_rates_backward(ctx, lists, T, sigma, dL_dgamma, dphi3=None, dphi4=None, precision=FP_FP64, stream=None):
+    T = _host(np.atleast_1d(T), np.float64)
+    arr = _lists(lists)
+    _check(ctx, lib().fp_rates_backward(ctx, arr, len(lists), len(T), _hp(T), float(sigma), int(precision),
+                                        _dp(dL_dgamma), _dp(dphi3), _dp(dphi4), _stream(stream)))
 
 
 def fp_kappa_rta(ctx, q1, q1_weight, T, gamma, kappa_out, dkappa_dgamma=None, stream=None):

@@ -1,0 +1,159 @@
+"""GPU adjoint: fp_rates_backward against the oracle's analytic FP64 gradient
+(itself pinned by central differences and the Euler identity on the CPU), and
+d(kappa_RTA)/dPhi through the torch autograd wrappers against central
+differences of the GPU forward."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_00518_amd import fp
+from paper_2510_00518_amd.synth import make_config, row_modes, small_config
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    h = fp.fp_create(0)
+    yield h
+    fp.fp_destroy(h)
+
+
+def oracle_lists(cfg, types, rows, sigma):
+    S = oracle.System(cfg)
+    out = {}
+    for t in types:
+        recs = [S.enumerate_row(t, g, sigma, cfg["nsigma"]) for g in rows]
+        off = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
+        rec = np.concatenate(recs).astype(np.uint64) if off[-1] else np.zeros(0, np.uint64)
+        out[t] = (np.asarray(rows, dtype=np.int32), off, rec)
+    return out
+
+
+def gpu_grad(ctx, cfg, lists, T, dLdG, chunk=None):
+    import torch
+    from paper_2510_00518_amd.driver import RatePath
+    p = RatePath(cfg, ctx=ctx)
+    p.set_lists(lists)
+    p.load_ifc(phi3=p.phi3, phi4=p.phi4)
+    if chunk:
+        fp.fp_set_knob(ctx, "grad_chunk", chunk)
+    dl = torch.as_tensor(dLdG).cuda()
+    d3 = torch.zeros_like(p.phi3) if p.phi3 is not None else None
+    d4 = torch.zeros_like(p.phi4) if p.phi4 is not None else None
+    fp.fp_rates_backward(ctx, p.lists3 + p.lists4, T, cfg["sigma"], dl, d3 if p.lists3 else None,
+                         d4 if p.lists4 else None)
+    fp.fp_check(ctx)
+    torch.cuda.synchronize()
+    fp.fp_set_knob(ctx, "grad_chunk", 8192)
+    return (d3.cpu().numpy() if d3 is not None else None), (d4.cpu().numpy() if d4 is not None else None)
+
+
+def oracle_grad(cfg, lists, T, dLdG):
+    S = oracle.System(cfg)
+    out = {3: None, 4: None}
+    for t, (rm, off, rec) in lists.items():
+        m = oracle.ORDER[t]
+        if out[m] is None:
+            out[m] = np.zeros_like(cfg["ifc3" if m == 3 else "ifc4"]["phi"])
+        if off[-1]:
+            S.grad(t, rm, T, cfg["sigma"], off, rec, dLdG[:, rm].T, out=out[m])
+    return out[3], out[4]
+
+
+def assert_grad(got, want, what, rtol=1e-10):
+    floor = 1e-12 * np.abs(want).max()
+    err = np.abs(got - want) / np.maximum(np.abs(want), floor)
+    say(f"  {what}: max rel err {err.max():.2e}, median {np.median(err):.1e}, |g|max {np.abs(want).max():.3e}")
+    assert err.max() <= rtol, what
+
+
+@pytest.mark.parametrize("case", ["3ph", "4ph", "mixed"])
+def test_backward_matches_oracle_gradient(ctx, case):
+    cfg = small_config(3)
+    sig = 2.0
+    cfg = dict(cfg, sigma=sig)
+    rows = row_modes(cfg)[::3]
+    types = {"3ph": (fp.FP_3P, fp.FP_3M), "4ph": (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM),
+             "mixed": (fp.FP_3M, fp.FP_4PM)}[case]
+    lists = oracle_lists(cfg, types, rows, sig)
+    say(case, "records", {t: int(v[1][-1]) for t, v in lists.items()})
+    T = [300.0, 900.0]
+    dLdG = np.random.default_rng(3).uniform(0.5, 1.5, size=(len(T), cfg["omega"].size))
+    g3, g4 = gpu_grad(ctx, cfg, lists, T, dLdG)
+    o3, o4 = oracle_grad(cfg, lists, T, dLdG)
+    if o3 is not None:
+        assert_grad(g3, o3, f"{case} dPhi3")
+    if o4 is not None:
+        assert_grad(g4, o4, f"{case} dPhi4")
+
+
+def test_backward_chunking_and_passes(ctx):
+    """Chunk sizes change only the summation grouping; the 8-atom cell has more
+    adjoint tiles than one pass holds."""
+    cfg = small_config(2, n3=0, n4=200, cell="conv")
+    rows = row_modes(cfg)[::17]
+    lists = oracle_lists(cfg, (fp.FP_4PM,), rows, cfg["sigma"])
+    T = [300.0]
+    dLdG = np.random.default_rng(5).uniform(0.5, 1.5, size=(1, cfg["omega"].size))
+    _, a = gpu_grad(ctx, cfg, lists, T, dLdG, chunk=256)
+    _, b = gpu_grad(ctx, cfg, lists, T, dLdG, chunk=8192)
+    _, o = oracle_grad(cfg, lists, T, dLdG)
+    assert_grad(a, o, "8-atom chunk 256")
+    assert_grad(b, o, "8-atom chunk 8192")
+
+
+@pytest.mark.slow
+def test_kappa_gradient_against_central_differences(ctx):
+    """d kappa_RTA(300 K)/dPhi on the 8^3 adjoint workload (3ph + 4ph), through the
+    autograd wrappers, against central differences (h = 1e-6 eV/A^m) on 64 seeded
+    components: <= 1e-6 relative."""
+    import torch
+    from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists, rates_autograd
+    cfg = make_config("fcc8_adjoint")
+    say("fcc8_adjoint: enumerating")
+    lists = host_lists(cfg, TYPES3 + TYPES4)
+    path = RatePath(cfg, ctx=ctx)
+    path.set_lists(lists)
+    say("records 4ph", path.n_proc4, "3ph", path.n_proc3)
+    Rates, KappaRTA = rates_autograd()
+    T = [300.0]
+    phi3 = path.phi3.clone().requires_grad_(True)
+    phi4 = path.phi4.clone().requires_grad_(True)
+    kap = KappaRTA.apply(Rates.apply(phi3, phi4, path, T), path, T)
+    kap.sum().backward()
+    g3, g4 = phi3.grad.cpu().numpy(), phi4.grad.cpu().numpy()
+    say(f"kappa_RTA = {float(kap):.6e} W/mK")
+
+    def kappa_at(p3, p4):
+        with torch.no_grad():
+            return float(KappaRTA.apply(Rates.apply(p3, p4, path, T), path, T))
+
+    rng = np.random.default_rng(251000518 + 3)
+    h = 1e-6
+    gmax = max(np.abs(g3).max(), np.abs(g4).max())
+    worst = 0.0
+    for n in range(64):
+        order = 3 if n % 2 == 0 else 4
+        base = phi3.detach() if order == 3 else phi4.detach()
+        t, k = int(rng.integers(base.shape[0])), int(rng.integers(base.shape[1]))
+        vals = []
+        for sgn in (1, -1):
+            pert = base.clone()
+            pert[t, k] += sgn * h
+            vals.append(kappa_at(pert, phi4.detach()) if order == 3 else kappa_at(phi3.detach(), pert))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        g = (g3 if order == 3 else g4)[t, k]
+        rel = abs(g - fd) / max(abs(fd), 1e-3 * gmax)
+        worst = max(worst, rel)
+    say(f"kappa gradient vs central differences: worst relative error {worst:.2e} over 64 components")
+    assert worst <= 1e-6

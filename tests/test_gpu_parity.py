@@ -79,7 +79,7 @@ def gpu_rates(ctx, cfg, lists, T, sigma=None, knobs=None):
     fp.fp_check(ctx)
     torch.cuda.synchronize()
     for k in (knobs or {}):
-        fp.fp_set_knob(ctx, k, {"ppl": 2, "blocks_per_cu": 2}[k])
+        fp.fp_set_knob(ctx, k, {"ppl": 2, "blocks_per_cu": 0, "variant": 1}[k])
     return gam.cpu().numpy(), wp.cpu().numpy()
 
 
@@ -105,15 +105,16 @@ def test_fcc4_three_phonon(ctx):
         assert np.all(g[:, inactive] == 0.0)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("mesh,sigma,stride", [(4, None, 5), (4, 10.0, 17), (3, 4.0, 3)])
-def test_four_phonon_small(ctx, mesh, sigma, stride):
+def test_four_phonon_small(ctx, mesh, sigma, stride, variant):
     cfg = small_config(mesh)
     sig = cfg["sigma"] if sigma is None else sigma
     rows = row_modes(cfg)[::stride]
     lists = oracle_lists(cfg, (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM), rows, sig)
     say(f"4ph {mesh}^3 sigma={sig}: records", {t: int(v[1][-1]) for t, v in lists.items()})
     T = [300.0, 1200.0]
-    g, w = gpu_rates(ctx, cfg, lists, T, sigma=sig)
+    g, w = gpu_rates(ctx, cfg, lists, T, sigma=sig, knobs={"variant": variant})
     go, wo = oracle_mode_rates(cfg, lists, T, sig)
     assert_parity(g, go, f"Gamma4 {mesh}^3")
     assert_parity(w, wo, f"WP4 {mesh}^3")
@@ -125,21 +126,23 @@ def test_launch_knobs_do_not_change_results(ctx):
     lists = oracle_lists(cfg, (fp.FP_4PM, fp.FP_4MM), rows, 6.0)
     go, _ = oracle_mode_rates(cfg, lists, [300.0], 6.0)
     ref = None
-    for ppl, bpc in ((1, 1), (2, 2), (3, 1), (8, 2), (64, 1)):
-        g, _ = gpu_rates(ctx, cfg, lists, [300.0], sigma=6.0, knobs={"ppl": ppl, "blocks_per_cu": bpc})
-        assert_parity(g, go, f"ppl={ppl} blocks/CU={bpc}")
+    for variant, ppl, bpc in ((0, 1, 1), (0, 2, 0), (1, 3, 1), (2, 3, 0), (3, 8, 2), (2, 64, 1), (1, 2, 0)):
+        g, _ = gpu_rates(ctx, cfg, lists, [300.0], sigma=6.0,
+                         knobs={"variant": variant, "ppl": ppl, "blocks_per_cu": bpc})
+        assert_parity(g, go, f"variant={variant} ppl={ppl} blocks/CU={bpc}")
         if ref is not None:
             np.testing.assert_allclose(g, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
         ref = g
 
 
-def test_eight_atom_cell(ctx):
+@pytest.mark.parametrize("variant", [0, 2])
+def test_eight_atom_cell(ctx, variant):
     cfg = small_config(2, n3=0, n4=200, cell="conv")
     rows = row_modes(cfg)[::13]
     lists = oracle_lists(cfg, (fp.FP_4PM,), rows, cfg["sigma"])
     say("8-atom 2^3: records", int(lists[fp.FP_4PM][1][-1]), "groups of terms over 8 atoms")
     T = [300.0, 600.0, 700.0, 800.0, 900.0]  # five temperatures: the 8-wide temperature variant
-    g, w = gpu_rates(ctx, cfg, lists, T)
+    g, w = gpu_rates(ctx, cfg, lists, T, knobs={"variant": variant})
     go, wo = oracle_mode_rates(cfg, lists, T, cfg["sigma"])
     assert_parity(g, go, "Gamma4 8-atom")
     assert_parity(w, wo, "WP4 8-atom")

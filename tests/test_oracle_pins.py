@@ -429,3 +429,53 @@ def test_enumerated_records_conserve_energy_and_momentum(ptype, mesh, sig):
             same = {T3P: [], T3M: [1, 2], T4PP: [1, 2], T4PM: [2, 3], T4MM: [1, 2, 3]}[ptype]
             assert all(g[a] <= g[b] for a, b in zip(same, same[1:]))
     assert total > 0
+
+
+# ---------------------------------------------------------------- gradient
+
+def _grad_case(ptype, mesh, sigma, stride):
+    cfg = small_config(mesh)
+    S = oracle.System(cfg)
+    rows = row_modes(cfg)[::stride]
+    recs = [S.enumerate_row(ptype, g, sigma) for g in rows]
+    off = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
+    rec = np.concatenate(recs).astype(np.uint64)
+    return cfg, S, rows, off, rec
+
+
+@pytest.mark.parametrize("ptype,mesh,sigma,stride", [(T3P, 3, 2.0, 2), (T3M, 3, 2.0, 2), (T4PM, 3, 2.0, 11),
+                                                     (T4PP, 4, 10.0, 41), (T4MM, 4, 10.0, 41)])
+def test_gradient_against_central_differences(ptype, mesh, sigma, stride):
+    """Gamma is quadratic in the force constants, so a central difference is exact up to rounding."""
+    cfg, S, rows, off, rec = _grad_case(ptype, mesh, sigma, stride)
+    T = [300.0, 800.0]
+    rng = np.random.default_rng(ptype + 17)
+    dLdG = rng.uniform(0.5, 1.5, size=(len(rows), len(T)))
+    key = "ifc3" if oracle.ORDER[ptype] == 3 else "ifc4"
+    phi = cfg[key]["phi"]
+    grad = S.grad(ptype, rows, T, sigma, off, rec, dLdG)
+    h = 1e-3
+    for _ in range(6):
+        t, k = int(rng.integers(phi.shape[0])), int(rng.integers(phi.shape[1]))
+        vals = []
+        for sgn in (1, -1):
+            pp = phi.copy()
+            pp[t, k] += sgn * h
+            Sp = oracle.System(cfg, **{("phi3" if key == "ifc3" else "phi4"): pp})
+            g, _, _, _ = Sp.rates(ptype, rows, T, sigma, row_off=off, rec=rec)
+            vals.append(np.sum(dLdG * g))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert grad[t, k] == pytest.approx(fd, rel=1e-7, abs=1e-9 * np.abs(grad).max())
+
+
+@pytest.mark.parametrize("ptype", [T3P, T4PM])
+def test_gradient_euler_identity(ptype):
+    """L = sum dLdG Gamma is homogeneous of degree 2 in the force constants: sum Phi dL/dPhi = 2 L."""
+    cfg, S, rows, off, rec = _grad_case(ptype, 3, 2.0, 3)
+    T = [300.0]
+    dLdG = np.random.default_rng(4).uniform(0.5, 1.5, size=(len(rows), 1))
+    key = "ifc3" if oracle.ORDER[ptype] == 3 else "ifc4"
+    grad = S.grad(ptype, rows, T, 2.0, off, rec, dLdG)
+    g, _, _, _ = S.rates(ptype, rows, T, 2.0, row_off=off, rec=rec)
+    L = np.sum(dLdG * g)
+    assert np.sum(cfg[key]["phi"] * grad) == pytest.approx(2 * L, rel=1e-11)
