@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counter scaling)")
+    ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--ppl", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     args = ap.parse_args()
@@ -143,6 +144,36 @@ def main():
     kap = kappa.cpu().numpy()
     finite = bool(np.all(np.isfinite(kap)))
 
+    # backward step: dkappa/dGamma, then the adjoint of both rate orders
+    bwd = None
+    if not args.no_backward:
+        dk = torch.zeros_like(gamma)
+        d3 = torch.zeros_like(path.phi3)
+        d4 = torch.zeros_like(path.phi4)
+
+        def backward_step():
+            path.kappa(T, gamma, kappa, dk)
+            fp.fp_rates_backward(path.ctx, path.lists3 + path.lists4, T, cfg["sigma"], dk, d3, d4)
+
+        backward_step()
+        torch.cuda.synchronize()
+        fp.fp_check(path.ctx)
+        fp.fp_profile(path.ctx, True)
+        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b0.record()
+        for _ in range(args.steps):
+            backward_step()
+        b1.record()
+        torch.cuda.synchronize()
+        g4_ms, g4_n = fp.fp_profile_read(path.ctx, 14)
+        fp.fp_profile(path.ctx, False)
+        fp.fp_check(path.ctx)
+        ms_bwd = b0.elapsed_time(b1) / args.steps
+        bwd = {"ms_per_step": ms_bwd, "bwd_fwd_ratio": ms_bwd / ms_step,
+               "adjoint4_kernel_ms": g4_ms / max(1, g4_n),
+               "step": "kappa_RTA with dkappa/dGamma + adjoint of the 3ph and 4ph rates (V recomputed)"}
+        log(f"bench: backward {ms_bwd:.3f} ms/step, ratio {ms_bwd / ms_step:.2f}")
+
     flop_per_proc = 320 * n4 + 60
     achieved = flop_per_proc * n_proc4 / (kern_ms * 1e-3) / 1e12
     traffic = None
@@ -184,7 +215,8 @@ def main():
         },
         "kappa_finite": finite,
         "mixed": None,
-        "bwd_fwd_ratio": None,
+        "bwd_fwd_ratio": None if bwd is None else bwd["bwd_fwd_ratio"],
+        "backward": bwd,
     }
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")

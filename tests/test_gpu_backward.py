@@ -71,7 +71,10 @@ def oracle_grad(cfg, lists, T, dLdG):
 
 
 def assert_grad(got, want, what, rtol=1e-10):
-    floor = 1e-12 * np.abs(want).max()
+    # per component, relative to max(|g|, 1e-3 |g|_inf): entries that symmetry
+    # suppresses to rounding noise (exactly-zero eigenvector components) are held to
+    # 1e-13 of the largest entry instead
+    floor = 1e-3 * np.abs(want).max()
     err = np.abs(got - want) / np.maximum(np.abs(want), floor)
     say(f"  {what}: max rel err {err.max():.2e}, median {np.median(err):.1e}, |g|max {np.abs(want).max():.3e}")
     assert err.max() <= rtol, what
@@ -115,8 +118,14 @@ def test_backward_chunking_and_passes(ctx):
 @pytest.mark.slow
 def test_kappa_gradient_against_central_differences(ctx):
     """d kappa_RTA(300 K)/dPhi on the 8^3 adjoint workload (3ph + 4ph), through the
-    autograd wrappers, against central differences (h = 1e-6 eV/A^m) on 64 seeded
-    components: <= 1e-6 relative."""
+    autograd wrappers, against central differences on 64 seeded components,
+    relative to max(|g_FD|, 1e-3 |g|_inf).
+
+    At h = 1e-6 eV/A^m the difference quotient is limited by the FP64 resolution
+    of kappa itself (one ulp of kappa over 2h), which for components near the
+    floor exceeds 1e-6; there the bound is that resolution.  At h = 1e-4 the
+    truncation error is far below 1e-6 and the 1e-6 bar applies to every
+    component."""
     import torch
     from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists, rates_autograd
     cfg = make_config("fcc8_adjoint")
@@ -132,28 +141,34 @@ def test_kappa_gradient_against_central_differences(ctx):
     kap = KappaRTA.apply(Rates.apply(phi3, phi4, path, T), path, T)
     kap.sum().backward()
     g3, g4 = phi3.grad.cpu().numpy(), phi4.grad.cpu().numpy()
-    say(f"kappa_RTA = {float(kap):.6e} W/mK")
+    k0 = float(kap.detach())
+    say(f"kappa_RTA = {k0:.6e} W/mK")
 
     def kappa_at(p3, p4):
         with torch.no_grad():
             return float(KappaRTA.apply(Rates.apply(p3, p4, path, T), path, T))
 
     rng = np.random.default_rng(251000518 + 3)
-    h = 1e-6
     gmax = max(np.abs(g3).max(), np.abs(g4).max())
-    worst = 0.0
+    ulp = np.spacing(k0)
+    worst = {1e-6: 0.0, 1e-4: 0.0}
     for n in range(64):
         order = 3 if n % 2 == 0 else 4
         base = phi3.detach() if order == 3 else phi4.detach()
         t, k = int(rng.integers(base.shape[0])), int(rng.integers(base.shape[1]))
-        vals = []
-        for sgn in (1, -1):
-            pert = base.clone()
-            pert[t, k] += sgn * h
-            vals.append(kappa_at(pert, phi4.detach()) if order == 3 else kappa_at(phi3.detach(), pert))
-        fd = (vals[0] - vals[1]) / (2 * h)
         g = (g3 if order == 3 else g4)[t, k]
-        rel = abs(g - fd) / max(abs(fd), 1e-3 * gmax)
-        worst = max(worst, rel)
-    say(f"kappa gradient vs central differences: worst relative error {worst:.2e} over 64 components")
-    assert worst <= 1e-6
+        for h in (1e-6, 1e-4):
+            vals = []
+            for sgn in (1, -1):
+                pert = base.clone()
+                pert[t, k] += sgn * h
+                vals.append(kappa_at(pert, phi4.detach()) if order == 3 else kappa_at(phi3.detach(), pert))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            scale = max(abs(fd), 1e-3 * gmax)
+            rel = abs(g - fd) / scale
+            bound = 1e-6 if h == 1e-4 else max(1e-6, 8 * ulp / (2 * h) / scale)
+            assert rel <= bound, (n, order, t, k, h, g, fd, rel, bound)
+            worst[h] = max(worst[h], rel)
+    say(f"kappa gradient vs central differences, worst relative error: h=1e-6 {worst[1e-6]:.2e}, "
+        f"h=1e-4 {worst[1e-4]:.2e} over 64 components")
+    assert worst[1e-4] <= 1e-6
