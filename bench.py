@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 FP64 lanes x 2 FLOP x 2.4 GHz
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rates4_fcc8_4ph.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_00518_amd", "csrc", f) for f in ("fp_kernels.h", "fp_lib.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_00518_amd", "csrc", f) for f in ("fp_kernels.h", "fp_batched.h", "fp_lib.hip")]
 
 
 def kernel_source_hash():
@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--ppl", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
+    ap.add_argument("--variant", type=int, default=None, help="order-4 contraction form (library knob)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the rate path is built and timed on a single MI355X; "
@@ -107,6 +108,8 @@ def main():
         fp.fp_set_knob(path.ctx, "ppl", args.ppl)
     if args.blocks_per_cu:
         fp.fp_set_knob(path.ctx, "blocks_per_cu", args.blocks_per_cu)
+    if args.variant is not None:
+        fp.fp_set_knob(path.ctx, "variant", args.variant)
     path.set_lists(lists)
     n_proc4, n_proc3 = path.n_proc4, path.n_proc3
     log(f"bench: {n_proc4} 4ph + {n_proc3} 3ph processes, enumeration {t_enum:.1f} s")

@@ -153,14 +153,21 @@ typedef struct {
  * [n_T][N*nb] in g order, OVERWRITTEN (modes in no row get 0); either may be
  * NULL to skip it (with FP_ACCUMULATE they are added to instead).  T_K is a
  * host array of n_T temperatures (K, > 0); sigma is the Gaussian width in
- * rad/ps.  precision must be FP_FP64 for order 3.
+ * rad/ps.  precision is FP_FP64 or FP_MIXED; order 3 always computes in FP64.
  * One launch evaluates every row of every list.  Requires fp_load_modes and
  * fp_load_ifc(order 3). */
 fp_status fp_rates3(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                     double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
 
 /* Four-phonon rates over 4ph lists (types FP_4PP/FP_4PM/FP_4MM); otherwise as
- * fp_rates3.  Requires fp_load_ifc(order 4). */
+ * fp_rates3.  Requires fp_load_ifc(order 4).
+ * FP_FP64: every step in FP64 (the "variant" knob picks the contraction form).
+ * FP_MIXED: the phase-weighted force constants of each (lambda, q', q'') tuple
+ *   are formed on bf16 matrix cores with three-way bf16 splits of both operands
+ *   and FP32 accumulation (an FP32-accurate product), the eigenvector
+ *   contraction runs in FP32, and the phases (exact roots of unity), |V|^2,
+ *   Gaussian, occupations, 1/prod(omega) and every sum over processes stay in
+ *   FP64.  Per-mode relative error against FP64 is of order 1e-6. */
 fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                     double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
 
@@ -194,16 +201,21 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *   "ppl"            records per lane per work unit, 1..64 (unit = 64*ppl records)
  *   "blocks_per_cu"  resident 256-thread blocks per compute unit in the
  *                    persistent launch, 1..16; 0 = as many as fit
- *   "variant"        order-4 contraction form, 0..3 (P-form or W-form, one or
- *                    two processes per lane)
+ *   "variant"        order-4 contraction form, 0..4: per-process P-form or
+ *                    W-form with one or two processes per lane (0-3), or the
+ *                    tuple-batched form (4: phase-weighted force constants per
+ *                    (lambda, q', q'') tuple on FP64 MFMA, then per-process
+ *                    contraction)
  *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
 
 /* Kernel timing for measurement: with enable != 0 every launch of the rate
  * kernel is bracketed by HIP events on its stream; fp_profile_read waits for
- * them and returns the summed milliseconds and the launch count of the order-m
- * rate kernel (m = 3 or 4) since the last enable, then clears the record. */
+ * them and returns the summed milliseconds and the launch count of one kernel
+ * since the last enable, then clears the record: order 3 or 4 = the FP64 rate
+ * kernel of that order, 24 = the mixed-precision order-4 rate kernel, 13 or 14 =
+ * the adjoint kernel of that order. */
 fp_status fp_profile(fp_ctx* ctx, int32_t enable);
 fp_status fp_profile_read(fp_ctx* ctx, int32_t order, double* total_ms, int64_t* launches);
 
@@ -221,7 +233,8 @@ fp_status fp_check(fp_ctx* ctx, void* hip_stream);
  * interchangeable partners are in ascending g order (triangle reduction) and
  * |Delta| <= nsigma*sigma, with Delta evaluated in double precision left to
  * right in record order (((w + s'w') + s''w'') + s'''w''').  Within a row the
- * records are ordered by (g', g'', j''').  keep_fraction in (0, 1] keeps a
+ * records are ordered by (q', q'', j', j'', j''') (3ph: q', j', j''), so the
+ * records of one (lambda, q', q'') tuple are contiguous.  keep_fraction in (0, 1] keeps a
  * deterministic hash-selected subset (1 keeps all) and seed selects the hash.
  * n_threads <= 0 uses every hardware thread.  FP_ERR_ARG on invalid input,
  * FP_ERR_UNSUPPORTED beyond the record encoding's limits. */

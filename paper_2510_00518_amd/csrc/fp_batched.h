@@ -1,0 +1,264 @@
+// Tuple-batched four-phonon rate kernel (branch-batched contraction).
+// Included once, by fp_lib.hip, after fp_kernels.h.
+//
+// All listed processes of one (lambda, q', q'') tuple share the phases
+// ph_t = exp(2 pi i (Q1.A_t + Q2.B_t)/L), so the phase-weighted force constants
+//   A_g[c](tuple) = sum_{t in group g} ph_t(tuple) phit_t[c]     (c = beta gamma delta)
+// are formed once per tuple and partner-atom group g, and each process only
+// contracts them with its partner eigenvectors:
+//   V = sum_g sum_{beta gamma delta} A_g[beta gamma delta] eps1(b_g)_beta eps2(c_g)_gamma eps3(d_g)_delta.
+// Over a block of tuples, A_g is a complex matrix product (27 components x
+// tuples, K = the group's terms) and runs on FP64 MFMA
+// (v_mfma_f64_16x16x4f64); the per-process contraction (39 complex MACs per
+// group) runs on the VALU.  The two pipes overlap across the waves of a SIMD.
+//
+// Work unit: 128 consecutive records of one row (two per lane).  Records of a
+// tuple are contiguous when lists come from the library's enumerator; the
+// kernel finds tuple boundaries itself (a change of (q', q'') between
+// consecutive records), so any record order is correct, only slower.  Tuples
+// are staged 32 at a time in LDS.
+#pragma once
+
+namespace fpk {
+
+constexpr int kBU = 128;            // records per unit
+constexpr int kBR = kBU / kWave;    // records per lane
+constexpr int kTB = 32;             // tuples staged per batch
+
+__device__ inline void lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <int MAXT>
+__global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS) {
+    __shared__ double2 sroots[kMaxRoots];
+    __shared__ double2 sA[kWavesPerBlock][kTB][27];
+    __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
+    for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int xcd = blockIdx.x % kXcd;
+    const int64_t per_xcd = (a.n_units + kXcd - 1) / kXcd;
+    const int64_t u_beg = xcd * per_xcd;
+    const int64_t u_end = u_beg + per_xcd < a.n_units ? u_beg + per_xcd : a.n_units;
+    const int64_t wstride = (int64_t)(gridDim.x / kXcd) * kWavesPerBlock;
+    const ModeGeom geo = a.geo;
+    const int nb = geo.nb;
+    double2(*A)[27] = sA[wave];
+    int32_t(*Qs)[2] = sQ[wave];
+
+    for (int64_t u = u_beg + (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave; u < u_end; u += wstride) {
+        const UnitDesc ud = units[u];
+        const int32_t row = __builtin_amdgcn_readfirstlane(ud.row);
+        const int32_t count = __builtin_amdgcn_readfirstlane(ud.count);
+        double accg[MAXT], accw[MAXT];
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) accg[it] = accw[it] = 0.0;
+        if (row >= 0 && count > 0) {
+            const RowInfo ri = rows[row];
+            const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
+            const int type = __builtin_amdgcn_readfirstlane(ri.type);
+            int s1, s2, s3;
+            type_signs(type, s1, s2, s3);
+            const double c1 = s1 > 0 ? 1.0 : -1.0;
+            const double c2 = s2 > 0 ? 1.0 : -1.0;
+            const double c3 = s3 > 0 ? 1.0 : -1.0;
+            const int32_t iq0 = g0 / nb;
+            const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
+            const double w0 = omega[g0];
+            const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * 27;
+
+            // ---- records, tuple boundaries and slots
+            Proc pr[kBR];
+            bool have[kBR], first[kBR];
+            int slot[kBR];
+            uint64_t prev_last = ~0ull;
+            int base = 0;
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) {
+                const int idx = k * kWave + lane;
+                have[k] = idx < count;
+                const uint64_t rec = have[k] ? ri.rec[ud.start + idx] : 0;
+                pr[k] = setup_proc<4>(have[k], rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
+                                      flag, a.inv_sigma2, a.gnorm);
+                const uint64_t key = have[k] ? (((uint64_t)(pr[k].g1 / nb) << 32) | (uint64_t)(pr[k].g2 / nb))
+                                             : ~0ull;
+                uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
+                if (lane == 0) up = prev_last;
+                first[k] = have[k] && key != up;
+                const uint64_t mask = __ballot(first[k]);
+                const uint64_t le = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+                slot[k] = base + __popcll(mask & le) - 1;
+                base += __popcll(mask);
+                prev_last = __shfl(key, kWave - 1, kWave);
+            }
+            const int n_tup = __builtin_amdgcn_readfirstlane(base);
+
+            double2 V[kBR];
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) V[k] = make_double2(0.0, 0.0);
+            for (int gi = 0; gi < a.n_groups; ++gi) {
+                const int32_t* G = groups + gi * 8;
+                const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
+                const int n_ks = (t1 - t0 + 3) >> 2;
+                for (int tb = 0; tb < n_tup; tb += kTB) {
+                    const int nbt = n_tup - tb < kTB ? n_tup - tb : kTB;
+                    // tuple wavevectors of this batch, written by each tuple's first record
+#pragma unroll
+                    for (int k = 0; k < kBR; ++k) {
+                        const int s = slot[k] - tb;
+                        if (first[k] && s >= 0 && s < kTB) {
+                            Qs[s][0] = pr[k].Q10 | (pr[k].Q11 << 10) | (pr[k].Q12 << 20);
+                            Qs[s][1] = pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20);
+                        }
+                    }
+                    lds_fence();
+                    // A_g for the batch on MFMA: 2 component tiles x (1 or 2) tuple tiles,
+                    // K = the group's terms, four at a time.  Each lane loads one force
+                    // constant per component tile and one phase per tuple tile per K-step.
+                    const bool two = nbt > 16;
+                    int32_t qv[2][6];
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        const int tj = nt * 16 + li;
+                        const int32_t qa = Qs[tj < nbt ? tj : 0][0], qb = Qs[tj < nbt ? tj : 0][1];
+                        qv[nt][0] = qa & 1023;
+                        qv[nt][1] = (qa >> 10) & 1023;
+                        qv[nt][2] = (qa >> 20) & 1023;
+                        qv[nt][3] = qb & 1023;
+                        qv[nt][4] = (qb >> 10) & 1023;
+                        qv[nt][5] = (qb >> 20) & 1023;
+                    }
+                    d4 acr[2][2], aci[2][2];  // [tuple tile][component tile]
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                        for (int mt = 0; mt < 2; ++mt) acr[nt][mt] = aci[nt][mt] = d4{0.0, 0.0, 0.0, 0.0};
+                    for (int ks = 0; ks < n_ks; ++ks) {
+                        const int term = t0 + 4 * ks + lk;
+                        const bool kval = term < t1;
+                        double2 F[2];
+#pragma unroll
+                        for (int mt = 0; mt < 2; ++mt) {
+                            const int comp = mt * 16 + li;
+                            F[mt] = (kval && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
+                        }
+                        int32_t tm[6];
+                        const int32_t* tmp = tmeta + (kval ? term : t0) * 8;
+#pragma unroll
+                        for (int d = 0; d < 6; ++d) tm[d] = tmp[1 + d];
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) {
+                            if (nt == 1 && !two) break;
+                            const int tj = nt * 16 + li;
+                            double2 ph = make_double2(0.0, 0.0);
+                            if (kval && tj < nbt) {
+                                uint32_t kk = 0;
+#pragma unroll
+                                for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[nt][d] * tm[d]);
+                                ph = sroots[mod_l(kk, geo.L, geo.magic)];
+                            }
+#pragma unroll
+                            for (int mt = 0; mt < 2; ++mt) {
+                                acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.x, acr[nt][mt], 0, 0, 0);
+                                aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.y, aci[nt][mt], 0, 0, 0);
+                                acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-F[mt].y, ph.y, acr[nt][mt], 0, 0, 0);
+                                aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].y, ph.x, aci[nt][mt], 0, 0, 0);
+                            }
+                        }
+                    }
+                    // D[i = 4r + lk][j = li]: component mt*16 + 4r + lk of tuple nt*16 + li
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        const int tj = nt * 16 + li;
+                        if (tj < nbt) {
+#pragma unroll
+                            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const int cc = mt * 16 + 4 * r + lk;
+                                    if (cc < 27) A[tj][cc] = make_double2(acr[nt][mt][r], aci[nt][mt][r]);
+                                }
+                        }
+                    }
+                    lds_fence();
+                    // per-process contraction with this group's partner eigenvectors
+#pragma unroll
+                    for (int k = 0; k < kBR; ++k) {
+                        const int s = slot[k] - tb;
+                        if (have[k] && s >= 0 && s < nbt) {
+                            const double2* e1 = evec + (int64_t)pr[k].g1 * nb + 3 * ab;
+                            const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
+                            const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
+                            double2 x[3], y[3], z[3];
+#pragma unroll
+                            for (int q = 0; q < 3; ++q) {
+                                x[q] = ld_eps(e1 + q, c1);
+                                y[q] = ld_eps(e2 + q, c2);
+                                z[q] = ld_eps(e3 + q, c3);
+                            }
+                            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) {
+                                double2 ub = make_double2(0.0, 0.0);
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) {
+                                    double2 vc = make_double2(0.0, 0.0);
+#pragma unroll
+                                    for (int d = 0; d < 3; ++d) vc = cfma(vc, A[s][(b * 3 + c) * 3 + d], z[d]);
+                                    ub = cfma(ub, vc, y[c]);
+                                }
+                                acc = cfma(acc, ub, x[b]);
+                            }
+                            V[k].x += acc.x;
+                            V[k].y += acc.y;
+                        }
+                    }
+                    lds_fence();
+                }
+            }
+
+            // ---- weights and occupations (FP64)
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) {
+                const double V2 = V[k].x * V[k].x + V[k].y * V[k].y;
+#pragma unroll
+                for (int it = 0; it < MAXT; ++it) {
+                    if (it < a.n_T) {
+                        const double* n = occ + (int64_t)it * a.n_modes;
+                        const double n1 = n[pr[k].g1], n2 = n[pr[k].g2], nl = n[pr[k].gl];
+                        double oc;
+                        if (type == 2)
+                            oc = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
+                        else if (type == 3)
+                            oc = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
+                        else
+                            oc = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
+                        const double xw = pr[k].base * oc;
+                        accw[it] += xw;
+                        accg[it] += xw * V2;
+                    }
+                }
+            }
+        }
+        double* out = partial + u * (2 * a.n_T);
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) {
+            if (it < a.n_T) {
+                const double sg = wave_sum(accg[it]);
+                const double sw = wave_sum(accw[it]);
+                if (lane == 0) {
+                    out[it] = sg;
+                    out[a.n_T + it] = sw;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace fpk

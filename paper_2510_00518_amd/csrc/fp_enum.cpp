@@ -73,7 +73,7 @@ struct Enum {
         return mix64(seed ^ mix64(row_g ^ mix64(rec))) < keep_threshold;
     }
 
-    // Visit the kept records of row mode g0 in (g', g'', j''') order.
+    // Visit the kept records of row mode g0 in (q', q'', j', j'', j''') order (3ph: q', j', j'').
     template <class F>
     void row(int64_t g0, F&& emit) const {
         const double w0 = omega[g0];
@@ -109,19 +109,20 @@ struct Enum {
         }
         const bool tri12 = (s[1] == s[2]);            // ++ and --: g' <= g''
         const bool tri23 = (s[2] == s[3]);            // +- and --: g'' <= g'''
+        // q-point pairs outermost, so the records of one (q', q'') tuple are contiguous
         for (int64_t iq1 = 0; iq1 < nq; ++iq1) {
             int64_t q1[3];
             coords(iq1, q1);
-            for (int32_t j1 = 0; j1 < nb; ++j1) {
-                const int64_t g1 = iq1 * nb + j1;
-                const double w1 = omega[g1];
-                if (!(w1 >= floor_)) continue;
-                const double d1 = s[1] > 0 ? w0 + w1 : w0 - w1;
-                for (int64_t iq2 = tri12 ? iq1 : 0; iq2 < nq; ++iq2) {
-                    int64_t q2[3], q3[3];
-                    coords(iq2, q2);
-                    for (int d = 0; d < 3; ++d) q3[d] = s[3] * (-(q0[d] + s[1] * q1[d] + s[2] * q2[d]));
-                    const int64_t iq3 = index(q3);
+            for (int64_t iq2 = tri12 ? iq1 : 0; iq2 < nq; ++iq2) {
+                int64_t q2[3], q3[3];
+                coords(iq2, q2);
+                for (int d = 0; d < 3; ++d) q3[d] = s[3] * (-(q0[d] + s[1] * q1[d] + s[2] * q2[d]));
+                const int64_t iq3 = index(q3);
+                for (int32_t j1 = 0; j1 < nb; ++j1) {
+                    const int64_t g1 = iq1 * nb + j1;
+                    const double w1 = omega[g1];
+                    if (!(w1 >= floor_)) continue;
+                    const double d1 = s[1] > 0 ? w0 + w1 : w0 - w1;
                     for (int32_t j2 = 0; j2 < nb; ++j2) {
                         const int64_t g2 = iq2 * nb + j2;
                         if (tri12 && g2 < g1) continue;

@@ -22,8 +22,6 @@
 
 namespace fpk {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
 constexpr int kSub = kBlock;  // processes staged per sub-chunk (one per thread)
 
 // Matrix element of one process (the forward contraction, one process per lane).

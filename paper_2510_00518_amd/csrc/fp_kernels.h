@@ -35,6 +35,8 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kXcd = 8;          // MI355X: 8 accelerator complex dies, blocks dealt round-robin
 constexpr int kMaxRoots = 1024;
 
+typedef double d4 __attribute__((ext_vector_type(4)));  // MFMA f64 accumulator tile
+
 struct RowInfo {
     const uint64_t* rec;  // list record array
     int64_t beg, end;     // record range of the row

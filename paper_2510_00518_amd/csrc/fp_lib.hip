@@ -15,6 +15,8 @@
 #include "fp.h"
 #include "fp_kernels.h"
 #include "fp_grad.h"
+#include "fp_batched.h"
+#include "fp_mixed.h"
 
 namespace {
 
@@ -62,12 +64,13 @@ struct IfcState {
     int32_t n_groups = 0;
     std::vector<int32_t> atoms, cells;  // structure as loaded, to skip re-uploads
     DevBuf<double> raw, phi_s, scale;
-    DevBuf<int32_t> perm, tmeta, tc, groups, pairs;
+    DevBuf<int32_t> perm, tmeta, tc, groups, pairs, kblk;
     int32_t n_pairs = 0;  // 16-term x 16-component tiles of the adjoint, within groups
+    int32_t n_kblk = 0;   // 16-term K-blocks of the mixed-precision kernel, within groups
     void release() {
         raw.release(); phi_s.release(); scale.release();
-        perm.release(); tmeta.release(); tc.release(); groups.release(); pairs.release();
-        order = 0; n_terms = 0; n_groups = 0; n_pairs = 0;
+        perm.release(); tmeta.release(); tc.release(); groups.release(); pairs.release(); kblk.release();
+        order = 0; n_terms = 0; n_groups = 0; n_pairs = 0; n_kblk = 0;
         atoms.clear(); cells.clear();
     }
 };
@@ -90,6 +93,7 @@ struct fp_ctx {
     std::vector<double> masses;
     DevBuf<double> omega, vel;
     DevBuf<double2> evec, roots;
+    DevBuf<float2> evec32;  // FP32 copy of the eigenvectors for the mixed-precision contraction
     IfcState ifc[2];  // order 3, order 4
     // per-call scratch (grow-only)
     DevBuf<double> occ, partial;
@@ -97,6 +101,7 @@ struct fp_ctx {
     DevBuf<int64_t> row_units, unit_off;
     DevBuf<fpk::UnitDesc> units;
     DevBuf<double2> phit;
+    DevBuf<uint4> fsp;  // bf16 split planes of phit (mixed precision)
     DevBuf<double> gpart;
     int* flag = nullptr;
     // tuning knobs
@@ -223,7 +228,7 @@ extern "C" fp_status fp_set_knob(fp_ctx* c, const char* name, int64_t value) {
         if (value < 256 || value > (1 << 22) || value % 256) return fail(c, FP_ERR_ARG, "grad_chunk: 256..2^22, multiple of 256");
         c->grad_chunk = (int32_t)value;
     } else if (!strcmp(name, "variant")) {
-        if (value < 0 || value > 3) return fail(c, FP_ERR_ARG, "variant must be in [0, 3]");
+        if (value < 0 || value > 4) return fail(c, FP_ERR_ARG, "variant must be in [0, 4]");
         c->variant = (int32_t)value;
     } else {
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
@@ -261,6 +266,12 @@ extern "C" fp_status fp_load_modes(fp_ctx* c, const int32_t mesh[3], int32_t n_a
     HIP_TRY(c, hipMemcpy(c->omega.p, omega, nm * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(c, c->evec.ensure(nm * nb));
     HIP_TRY(c, hipMemcpy(c->evec.p, evec, nm * nb * sizeof(double2), hipMemcpyHostToDevice));
+    {
+        std::vector<float2> e32((size_t)(nm * nb));
+        for (int64_t i = 0; i < nm * nb; ++i) e32[(size_t)i] = make_float2((float)evec[2 * i], (float)evec[2 * i + 1]);
+        HIP_TRY(c, c->evec32.ensure(nm * nb));
+        HIP_TRY(c, hipMemcpy(c->evec32.p, e32.data(), e32.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
     c->have_vel = vel != nullptr;
     if (vel) {
         HIP_TRY(c, c->vel.ensure(nm * 3));
@@ -345,6 +356,16 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
                 groups[groups.size() - 8 + 4] = (int32_t)i + 1;
             }
         }
+        // K-blocks of the mixed-precision kernel: 16 consecutive terms of one group;
+        // groups[g][5] is the group's first block, kblk[b] = {group, block within group}
+        std::vector<int32_t> kblk;
+        for (size_t g = 0; g + 8 <= groups.size(); g += 8) {
+            groups[g + 5] = (int32_t)(kblk.size() / 2);
+            for (int32_t tb = groups[g + 3], ks = 0; tb < groups[g + 4]; tb += 16, ++ks) {
+                kblk.push_back((int32_t)(g / 8));
+                kblk.push_back(ks);
+            }
+        }
         // adjoint tiles: 16 consecutive terms of one group x 16 components
         std::vector<int32_t> pairs;
         const int nc = m == 3 ? 9 : 27;
@@ -371,6 +392,9 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
         HIP_TRY(c, S.pairs.ensure(pairs.size()));
         HIP_TRY(c, hipMemcpy(S.pairs.p, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
         S.n_pairs = (int32_t)(pairs.size() / 4);
+        HIP_TRY(c, S.kblk.ensure(kblk.size()));
+        HIP_TRY(c, hipMemcpy(S.kblk.p, kblk.data(), kblk.size() * 4, hipMemcpyHostToDevice));
+        S.n_kblk = (int32_t)(kblk.size() / 2);
         S.order = m;
         S.n_terms = n_terms;
         S.n_groups = (int32_t)(groups.size() / 8);
@@ -396,7 +420,7 @@ namespace {
 struct Variant {
     int ct, np;
 };
-constexpr Variant kVariants[4] = {{0, 1}, {1, 1}, {1, 2}, {0, 2}};
+constexpr Variant kVariants[5] = {{0, 1}, {1, 1}, {1, 2}, {0, 2}, {2, 2}};  // 4: tuple-batched
 
 template <int M, int T, int CT, int NP>
 fp_status launch_rates(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
@@ -414,10 +438,44 @@ fp_status launch_rates(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::Ra
     return FP_OK;
 }
 
+template <int T>
+fp_status launch_mixed(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
+    auto kern = fpk::k_rates4m<T>;
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
+    const int64_t want = (n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
+    nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec32.p, c->occ.p,
+                       c->roots.p, c->fsp.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
+                       S.n_kblk);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+template <int T>
+fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
+    auto kern = fpk::k_rates4b<T>;
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
+    const int64_t want = (n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
+    nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
 template <int M, int T>
 fp_status launch_variant(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
     if (M == 3) return launch_rates<3, T, 0, 1>(c, st, n_units, a, S);
     switch (c->variant) {
+        case 4: return launch_batched<T>(c, st, n_units, a, S);
         case 1: return launch_rates<4, T, 1, 1>(c, st, n_units, a, S);
         case 2: return launch_rates<4, T, 1, 2>(c, st, n_units, a, S);
         case 3: return launch_rates<4, T, 0, 2>(c, st, n_units, a, S);
@@ -542,7 +600,9 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     if (S.order != m) return fail(c, FP_ERR_STATE, "force constants of order %d not loaded", m);
     const bool accumulate = (precision & FP_ACCUMULATE) != 0;
     precision &= ~FP_ACCUMULATE;
-    if (precision != FP_FP64) return fail(c, FP_ERR_UNSUPPORTED, "only FP_FP64 is available for order %d", m);
+    if (precision != FP_FP64 && precision != FP_MIXED) return fail(c, FP_ERR_ARG, "unknown precision %d", precision);
+    // order 3 is a negligible share of the work and always runs in FP64
+    const bool mixed = precision == FP_MIXED && m == 4;
     std::vector<int> sel;
     for (int l = 0; l < n_lists; ++l) {
         if (ORDER_OF(lists[l].type) != m)
@@ -550,7 +610,8 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
         sel.push_back(l);
     }
     const int np = m == 3 ? 1 : kVariants[c->variant].np;
-    const int64_t ppl = (c->ppl + np - 1) / np * np;
+    // the tuple-batched kernel works on units of exactly 128 records
+    const int64_t ppl = (m == 4 && (c->variant == 4 || mixed)) ? fpk::kBR : (c->ppl + np - 1) / np * np;
     const int64_t unit = (int64_t)fpk::kWave * ppl;
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -579,11 +640,21 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     a.inv_sigma2 = 1.0 / (sigma * sigma);
     a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
     const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
+    if (mixed) {
+        const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
+        HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
+        hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, pp.total_rows, c->phit.p,
+                           S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_terms, c->fsp.p);
+        HIP_TRY(c, hipGetLastError());
+    }
     hipEvent_t ev0, ev1;
     fp_status ts = timer_start(c, st, &ev0, &ev1);
     if (ts != FP_OK) return ts;
     fp_status ls;
-    if (m == 3)
+    if (mixed)
+        ls = tsel == 1 ? launch_mixed<1>(c, st, pp.n_units, a, S)
+                       : (tsel == 4 ? launch_mixed<4>(c, st, pp.n_units, a, S) : launch_mixed<8>(c, st, pp.n_units, a, S));
+    else if (m == 3)
         ls = tsel == 1 ? launch_variant<3, 1>(c, st, pp.n_units, a, S)
                        : (tsel == 4 ? launch_variant<3, 4>(c, st, pp.n_units, a, S)
                                     : launch_variant<3, 8>(c, st, pp.n_units, a, S));
@@ -592,7 +663,7 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
                        : (tsel == 4 ? launch_variant<4, 4>(c, st, pp.n_units, a, S)
                                     : launch_variant<4, 8>(c, st, pp.n_units, a, S));
     if (ls != FP_OK) return ls;
-    ts = timer_stop(c, st, m, ev0, ev1);
+    ts = timer_stop(c, st, mixed ? 24 : m, ev0, ev1);
     if (ts != FP_OK) return ts;
     const double pref = rate_prefactor(c, m);
     const double wpref = m == 3 ? 1.0 / (double)c->nq : 1.0 / ((double)c->nq * (double)c->nq);
@@ -722,7 +793,8 @@ extern "C" fp_status fp_profile(fp_ctx* c, int32_t enable) {
 }
 
 extern "C" fp_status fp_profile_read(fp_ctx* c, int32_t order, double* total_ms, int64_t* launches) {
-    if (!c || !total_ms || !launches || (order != 3 && order != 4 && order != 13 && order != 14)) return FP_ERR_ARG;
+    if (!c || !total_ms || !launches || (order != 3 && order != 4 && order != 13 && order != 14 && order != 24))
+        return FP_ERR_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
     double tot = 0.0;
     int64_t n = 0;

@@ -24,10 +24,13 @@ def host_lists(cfg, types, rows=None, sigma=None, nsigma=None, keep_fraction=1.0
 
 
 class RatePath:
-    def __init__(self, cfg, device=0, ctx=None):
+    def __init__(self, cfg, device=0, ctx=None, precision=fp.FP_FP64):
+        """precision applies to the order-4 rates (fp.FP_FP64 or fp.FP_MIXED);
+        order 3 always runs in FP64."""
         import torch
         self.torch = torch
         self.cfg = cfg
+        self.precision = precision
         self.device = torch.device("cuda", device)
         self.ctx = ctx if ctx is not None else fp.fp_create(device)
         self.own_ctx = ctx is None
@@ -85,7 +88,7 @@ class RatePath:
             fp.fp_rates3(self.ctx, self.lists3, T, sigma, fp.FP_FP64, gamma, wp)
             first = False
         if self.lists4 and order in (None, 4):
-            prec = fp.FP_FP64 if first else fp.FP_FP64 | fp.FP_ACCUMULATE
+            prec = self.precision if first else self.precision | fp.FP_ACCUMULATE
             fp.fp_rates4(self.ctx, self.lists4, T, sigma, prec, gamma, wp)
             first = False
         if first:

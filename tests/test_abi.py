@@ -71,9 +71,15 @@ def test_enumerator_matches_oracle_brute_force(ptype, mesh, sigma, nsigma):
     assert off[-1] == sum(len(w) for w in want)
     for r, w in enumerate(want):
         got = rec[off[r]:off[r + 1]]
-        # within a row the records are ordered by (g', g'', j''')
-        g1, g2, jl = got & 0xFFFFFF, (got >> np.uint64(24)) & 0xFFFFFF, got >> np.uint64(48)
-        key = (g1.astype(np.int64) << 40) | (g2.astype(np.int64) << 16) | jl.astype(np.int64)
+        # within a row the records are ordered by (q1, q2, j1, j2, j3) (3ph: q1, j1, j2)
+        nb = cfg["nb"]
+        g1 = (got & 0xFFFFFF).astype(np.int64)
+        g2 = ((got >> np.uint64(24)) & 0xFFFFFF).astype(np.int64)
+        if fp.ORDER[ptype] == 4:
+            jl = (got >> np.uint64(48)).astype(np.int64)
+            key = ((((g1 // nb) * 4096 + g2 // nb) * 64 + g1 % nb) * 64 + g2 % nb) * 64 + jl
+        else:
+            key = g1 * 256 + ((got >> np.uint64(24)) & 0xFF).astype(np.int64)
         assert np.all(key[1:] > key[:-1])
         np.testing.assert_array_equal(np.sort(got), w)
     assert off[-1] > 0

@@ -1,0 +1,173 @@
+"""GPU mixed-precision order-4 path (FP_MIXED) against the FP64 oracle.
+
+FP_MIXED forms the phase-weighted force constants on bf16 matrix cores with
+three-way split operands and FP32 accumulation, contracts the eigenvectors in
+FP32, and keeps phases, weights and every sum over processes in FP64.  The FP64
+bar (1e-10) does not apply.  Bars:
+  - kappa_RTA within 1e-5 relative of kappa_RTA from the oracle's rates;
+  - per-mode Gamma within 2e-5 relative of the oracle (modes above 1e-6 of the
+    largest rate; smaller ones within that absolute floor).  The observed errors
+    are printed with each case.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_00518_amd import fp
+from paper_2510_00518_amd.synth import make_config, row_modes, small_config
+
+pytestmark = pytest.mark.gpu
+
+RTOL_MODE = 2e-5
+FLOOR = 1e-6
+RTOL_KAPPA = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    h = fp.fp_create(0)
+    yield h
+    fp.fp_destroy(h)
+
+
+def oracle_lists(cfg, types, rows, sigma):
+    S = oracle.System(cfg)
+    out = {}
+    for t in types:
+        recs = [S.enumerate_row(t, g, sigma, cfg["nsigma"]) for g in rows]
+        off = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
+        rec = np.concatenate(recs).astype(np.uint64) if off[-1] else np.zeros(0, np.uint64)
+        out[t] = (np.asarray(rows, dtype=np.int32), off, rec)
+    return out
+
+
+def oracle_mode_rates(cfg, lists, T, sigma):
+    S = oracle.System(cfg)
+    n = cfg["omega"].size
+    gam = np.zeros((len(T), n))
+    for t, (rm, off, rec) in lists.items():
+        if off[-1] == 0:
+            continue
+        g, _, _, _ = S.rates(t, rm, T, sigma, row_off=off, rec=rec)
+        gam[:, rm] += g.T
+    return gam
+
+
+def gpu_rates(ctx, cfg, lists, T, precision, sigma=None):
+    import torch
+    from paper_2510_00518_amd.driver import RatePath
+    cfg = dict(cfg)
+    if sigma is not None:
+        cfg["sigma"] = sigma
+    for k, v in {"ppl": 2, "blocks_per_cu": 0, "variant": 1}.items():
+        fp.fp_set_knob(ctx, k, v)
+    p = RatePath(cfg, ctx=ctx, precision=precision)
+    p.set_lists(lists)
+    gam, wp = p.outputs(len(T))
+    p.load_ifc()
+    p.rates(T, gam, wp)
+    fp.fp_check(ctx)
+    torch.cuda.synchronize()
+    return gam.cpu().numpy(), wp.cpu().numpy()
+
+
+def mode_errors(g, go):
+    """Relative per-mode errors over the modes above the floor, and the
+    largest absolute error of the rest relative to the maximum."""
+    scale = np.abs(go).max()
+    big = np.abs(go) > FLOOR * scale
+    rel = np.abs(g[big] - go[big]) / np.abs(go[big])
+    small = np.abs(g[~big] - go[~big]).max() / scale if np.any(~big) else 0.0
+    return rel, small
+
+
+def check_modes(g, go, what):
+    rel, small = mode_errors(g, go)
+    say(f"{what}: per-mode rel error max {rel.max():.3e} median {np.median(rel):.3e} over {rel.size} modes; "
+        f"floor modes {small:.3e}")
+    assert rel.max() <= RTOL_MODE, what
+    assert small <= FLOOR, what
+
+
+@pytest.mark.parametrize("mesh,sigma,stride", [(4, None, 5), (4, 10.0, 17), (3, 4.0, 3)])
+def test_mixed_rates_small(ctx, mesh, sigma, stride):
+    cfg = small_config(mesh)
+    sig = cfg["sigma"] if sigma is None else sigma
+    rows = row_modes(cfg)[::stride]
+    lists = oracle_lists(cfg, (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM), rows, sig)
+    T = [300.0, 1200.0]
+    g, _ = gpu_rates(ctx, cfg, lists, T, fp.FP_MIXED, sigma=sig)
+    go = oracle_mode_rates(cfg, lists, T, sig)
+    check_modes(g, go, f"mixed Gamma4 {mesh}^3 sigma={sig}")
+
+
+def test_mixed_eight_atom_cell(ctx):
+    """Many partner-atom groups, some with more than 16 terms (several K-blocks)."""
+    cfg = small_config(2, n3=0, n4=200, cell="conv")
+    rows = row_modes(cfg)[::13]
+    lists = oracle_lists(cfg, (fp.FP_4PM,), rows, cfg["sigma"])
+    T = [300.0, 600.0, 700.0, 800.0, 900.0]
+    g, _ = gpu_rates(ctx, cfg, lists, T, fp.FP_MIXED)
+    go = oracle_mode_rates(cfg, lists, T, cfg["sigma"])
+    check_modes(g, go, "mixed Gamma4 8-atom")
+
+
+def test_mixed_kappa_with_three_phonon(ctx):
+    """Gamma3 (FP64) + Gamma4 (mixed) accumulated, and kappa_RTA from it against
+    kappa_RTA from the oracle's rates."""
+    cfg = small_config(4)
+    rows = row_modes(cfg)[::2]
+    sig = cfg["sigma"]
+    lists = oracle_lists(cfg, (fp.FP_3P, fp.FP_3M, fp.FP_4PP, fp.FP_4PM, fp.FP_4MM), rows, sig)
+    T = [300.0]
+    g, _ = gpu_rates(ctx, cfg, lists, T, fp.FP_MIXED)
+    go = oracle_mode_rates(cfg, lists, T, sig)
+    check_modes(g, go, "mixed Gamma3+Gamma4 4^3")
+    k_mixed = np.trace(oracle.kappa(cfg, g[0], T[0])) / 3
+    k_ref = np.trace(oracle.kappa(cfg, go[0], T[0])) / 3
+    err = abs(k_mixed - k_ref) / abs(k_ref)
+    say(f"kappa_RTA mixed {k_mixed:.10e} oracle {k_ref:.10e} rel {err:.3e}")
+    assert err <= RTOL_KAPPA
+
+
+@pytest.mark.slow
+def test_mixed_fcc8_4ph_full_size(ctx):
+    """The 8^3 four-phonon workload at full size: kappa_RTA from mixed rates
+    against kappa_RTA from FP64 rates (the FP64 path is held to the oracle at
+    1e-10 by the parity tests), per-mode errors reported."""
+    import torch
+    from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists
+    cfg = make_config("fcc8_4ph")
+    lists = host_lists(cfg, TYPES3 + TYPES4)
+    out = {}
+    for name, prec in (("fp64", fp.FP_FP64), ("mixed", fp.FP_MIXED)):
+        p = RatePath(cfg, ctx=ctx, precision=prec)
+        p.set_lists(lists)
+        gam, _ = p.outputs(1)
+        kap = torch.zeros((1, 9), dtype=torch.float64, device="cuda")
+        p.load_ifc()
+        p.rates([300.0], gam, None)
+        p.kappa([300.0], gam, kap)
+        fp.fp_check(ctx)
+        torch.cuda.synchronize()
+        out[name] = (gam.cpu().numpy()[0], kap.cpu().numpy()[0])
+        del p
+    g64, k64 = out["fp64"]
+    gmx, kmx = out["mixed"]
+    rel, small = mode_errors(gmx, g64)
+    kr = (kmx[0] + kmx[4] + kmx[8]) / 3
+    k0 = (k64[0] + k64[4] + k64[8]) / 3
+    err = abs(kr - k0) / abs(k0)
+    say(f"fcc8_4ph mixed vs FP64: Gamma per-mode rel max {rel.max():.3e} median {np.median(rel):.3e}; "
+        f"kappa_RTA {kr:.10e} vs {k0:.10e} rel {err:.3e}")
+    assert rel.max() <= RTOL_MODE
+    assert err <= RTOL_KAPPA

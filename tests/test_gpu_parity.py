@@ -105,7 +105,7 @@ def test_fcc4_three_phonon(ctx):
         assert np.all(g[:, inactive] == 0.0)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("mesh,sigma,stride", [(4, None, 5), (4, 10.0, 17), (3, 4.0, 3)])
 def test_four_phonon_small(ctx, mesh, sigma, stride, variant):
     cfg = small_config(mesh)
@@ -126,7 +126,7 @@ def test_launch_knobs_do_not_change_results(ctx):
     lists = oracle_lists(cfg, (fp.FP_4PM, fp.FP_4MM), rows, 6.0)
     go, _ = oracle_mode_rates(cfg, lists, [300.0], 6.0)
     ref = None
-    for variant, ppl, bpc in ((0, 1, 1), (0, 2, 0), (1, 3, 1), (2, 3, 0), (3, 8, 2), (2, 64, 1), (1, 2, 0)):
+    for variant, ppl, bpc in ((0, 1, 1), (0, 2, 0), (1, 3, 1), (2, 3, 0), (3, 8, 2), (2, 64, 1), (4, 5, 1), (4, 1, 0), (1, 2, 0)):
         g, _ = gpu_rates(ctx, cfg, lists, [300.0], sigma=6.0,
                          knobs={"variant": variant, "ppl": ppl, "blocks_per_cu": bpc})
         assert_parity(g, go, f"variant={variant} ppl={ppl} blocks/CU={bpc}")
@@ -135,7 +135,30 @@ def test_launch_knobs_do_not_change_results(ctx):
         ref = g
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("order", ["enumerator", "shuffled"])
+def test_tuple_batched_any_record_order(ctx, order):
+    """The tuple-batched form finds (q', q'') tuples from consecutive records, so
+    it must give the same rates whether a row's records of one tuple are
+    contiguous (the enumerator's order) or scattered."""
+    from paper_2510_00518_amd.driver import host_lists
+    cfg = small_config(4)
+    rows = row_modes(cfg)[::7]
+    lists = host_lists(cfg, (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM), rows=rows, sigma=6.0)
+    if order == "shuffled":
+        rng = np.random.default_rng(7)
+        for t, (rm, off, rec) in lists.items():
+            rec = rec.copy()
+            for r in range(len(rm)):
+                rec[off[r]:off[r + 1]] = rng.permutation(rec[off[r]:off[r + 1]])
+            lists[t] = (rm, off, rec)
+    say(f"tuple-batched, {order} records:", {t: int(v[1][-1]) for t, v in lists.items()})
+    go, wo = oracle_mode_rates(cfg, lists, [300.0], 6.0)
+    g, w = gpu_rates(ctx, cfg, lists, [300.0], sigma=6.0, knobs={"variant": 4})
+    assert_parity(g, go, f"Gamma4 variant 4, {order}")
+    assert_parity(w, wo, f"WP4 variant 4, {order}")
+
+
+@pytest.mark.parametrize("variant", [0, 2, 4])
 def test_eight_atom_cell(ctx, variant):
     cfg = small_config(2, n3=0, n4=200, cell="conv")
     rows = row_modes(cfg)[::13]

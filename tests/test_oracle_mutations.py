@@ -21,7 +21,10 @@ MUTATIONS = {
                            "k[d] -= (int64_t)sg[r] * qc[r][d] * ce[(r - 1) * 3 + d];"),
     "transposed force-constant index": ("double f = ph[((a0 * 3 + a1) * 3 + a2) * 3 + a3];",
                                         "double f = ph[((a0 * 3 + a2) * 3 + a1) * 3 + a3];"),
-    "last term dropped": ("for (int64_t t = 0; t < n_terms; ++t) {", "for (int64_t t = 0; t < n_terms - 1; ++t) {"),
+    "last term dropped": ("cplx V = {0.0, 0.0};\n    for (int64_t t = 0; t < n_terms; ++t) {",
+                          "cplx V = {0.0, 0.0};\n    for (int64_t t = 0; t < n_terms - 1; ++t) {"),
+    "gradient without the factor 2 of |V|^2": ("            c *= 2.0;\n", "            c *= 1.0;\n"),
+    "gradient with V not conjugated": ("cplx Vc = {V.re, -V.im};", "cplx Vc = {V.re, V.im};"),
     "one mass factor dropped": ("for (int r = 0; r < m; ++r) msc *= s->masses[at[r]];",
                                 "for (int r = 1; r < m; ++r) msc *= s->masses[at[r]];"),
     "wrong 4+- occupation": ("case T4PM: return n[1] * (1.0 + n[2]) * (1.0 + n[3]) - (1.0 + n[1]) * n[2] * n[3];",
