@@ -7,7 +7,9 @@ the host by the library and uploaded before timing.  One step is the whole hot
 path: force-constant load (order 3 and 4, device-resident values), 3ph and 4ph
 rates accumulated into Gamma = Gamma3 + Gamma4, and kappa_RTA.
 
-Prints one JSON line.  value = 4ph processes per second of the whole step.
+Prints one JSON line.  value = 4ph processes per second of the whole FP64 step;
+"mixed" holds the same step with the order-4 rates in mixed precision (bf16
+split MFMA, FP32 contraction, FP64 weights) and its errors against FP64.
 roofline: the dominant kernel (the order-4 rate kernel) timed with HIP events
 on its own stream, algorithmic FLOP = (320 n4 + 60) per process, against the
 FP64 vector peak.  cpu_baseline: the FP64 oracle (list mode) on a bounded
@@ -25,9 +27,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 FP64 lanes x 2 FLOP x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 FP64 lanes x 2 FLOP x 2.4 GHz (vector; FP64 MFMA the same)
+PEAK_BF16_TFLOPS = 2500.0  # dense bf16 MFMA
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rates4_fcc8_4ph.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_00518_amd", "csrc", f) for f in ("fp_kernels.h", "fp_batched.h", "fp_lib.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_00518_amd", "csrc", f)
+                  for f in ("fp_kernels.h", "fp_batched.h", "fp_mixed.h", "fp_lib.hip")]
 
 
 def kernel_source_hash():
@@ -67,6 +71,59 @@ def cpu_baseline(cfg, lists, seconds, seed=251000518 + 6):
                       f"benchmark's lists, FP64 list mode, {spent:.1f} s"}
 
 
+def tuple_stats(lists, nb, unit=128):
+    """Distinct (lambda, q', q'') tuples of the 4ph lists, and the tuples the
+    tuple-batched kernels form (a tuple split by a 128-record unit boundary
+    counts once per unit)."""
+    from paper_2510_00518_amd import fp
+    n_tup = n_unit_tup = 0
+    for t, (rm, off, rec) in lists.items():
+        if fp.ORDER[t] != 4 or len(rec) == 0:
+            continue
+        q1 = (rec & np.uint64(0xFFFFFF)).astype(np.int64) // nb
+        q2 = ((rec >> np.uint64(24)) & np.uint64(0xFFFFFF)).astype(np.int64) // nb
+        key = q1 * (1 << 24) + q2
+        del q1, q2
+        row_start = np.zeros(len(rec), dtype=bool)
+        row_start[off[:-1][np.diff(off) > 0]] = True
+        new = row_start.copy()
+        new[1:] |= key[1:] != key[:-1]
+        n_tup += int(new.sum())
+        pos = np.arange(len(rec), dtype=np.int64) - np.repeat(off[:-1], np.diff(off))
+        n_unit_tup += int((new | (pos % unit == 0)).sum())
+    return n_tup, n_unit_tup
+
+
+def partner_groups(ifc):
+    """Partner-atom groups of a force-constant list (distinct atoms of slots 1..m-1)."""
+    return len({tuple(a[1:]) for a in np.asarray(ifc["atoms"]).tolist()})
+
+
+def run_forward(path, T, steps, warmup, tag, torch, fp):
+    """Warm up, then time `steps` whole steps; returns ms/step, the tagged
+    kernel's ms/launch, and the last step's Gamma and kappa (host copies)."""
+    gamma = torch.zeros((len(T), path.n_modes), dtype=torch.float64, device="cuda")
+    kappa = torch.zeros((len(T), 9), dtype=torch.float64, device="cuda")
+    for i in range(warmup):
+        path.step(T, gamma, kappa)
+        torch.cuda.synchronize()
+        log(f"bench: warmup step {i + 1}/{warmup} done")
+    fp.fp_check(path.ctx)
+    fp.fp_profile(path.ctx, True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        path.step(T, gamma, kappa)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    k_ms, launches = fp.fp_profile_read(path.ctx, tag)
+    fp.fp_profile(path.ctx, False)
+    fp.fp_check(path.ctx)
+    return ms_step, k_ms / max(1, launches), gamma, kappa
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +134,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counter scaling)")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--ppl", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None, help="order-4 contraction form (library knob)")
@@ -98,11 +156,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cfg = make_config("fcc8_4ph")
     n4 = int(cfg["ifc4"]["n_terms"])
+    n_groups = partner_groups(cfg["ifc4"])
     T = [float(x) for x in cfg["T"]]
     log("bench: enumerating lists on the host")
     t0 = time.perf_counter()
     lists = host_lists(cfg, TYPES3 + TYPES4)
     t_enum = time.perf_counter() - t0
+    n_tup, n_unit_tup = tuple_stats(lists, cfg["nb"])
     path = RatePath(cfg, device=0)
     if args.ppl:
         fp.fp_set_knob(path.ctx, "ppl", args.ppl)
@@ -110,11 +170,11 @@ def main():
         fp.fp_set_knob(path.ctx, "blocks_per_cu", args.blocks_per_cu)
     if args.variant is not None:
         fp.fp_set_knob(path.ctx, "variant", args.variant)
+    variant = fp.fp_get_knob(path.ctx, "variant")
     path.set_lists(lists)
     n_proc4, n_proc3 = path.n_proc4, path.n_proc3
-    log(f"bench: {n_proc4} 4ph + {n_proc3} 3ph processes, enumeration {t_enum:.1f} s")
-    gamma = torch.zeros((len(T), path.n_modes), dtype=torch.float64, device="cuda")
-    kappa = torch.zeros((len(T), 9), dtype=torch.float64, device="cuda")
+    log(f"bench: {n_proc4} 4ph + {n_proc3} 3ph processes in {n_tup} (lambda, q', q'') tuples, "
+        f"enumeration {t_enum:.1f} s")
 
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -124,30 +184,68 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for i in range(args.warmup):
-        path.step(T, gamma, kappa)
-        torch.cuda.synchronize()
-        log(f"bench: warmup step {i + 1}/{args.warmup} done")
-    fp.fp_check(path.ctx)
-    fp.fp_profile(path.ctx, True)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        path.step(T, gamma, kappa)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
-    rates_ms, launches = fp.fp_profile_read(path.ctx, 4)
-    fp.fp_profile(path.ctx, False)
-    fp.fp_check(path.ctx)
-    ms_step = ms_total / args.steps
-    kern_ms = rates_ms / max(1, launches)
-    log(f"bench: {args.steps} steps, {ms_step:.3f} ms/step, order-4 rate kernel {kern_ms:.3f} ms/launch")
-    kap = kappa.cpu().numpy()
-    finite = bool(np.all(np.isfinite(kap)))
+    # ---- FP64 forward
+    ms_step, kern_ms, gamma, kappa = run_forward(path, T, args.steps, args.warmup, 4, torch, fp)
+    log(f"bench: FP64 {args.steps} steps, {ms_step:.3f} ms/step, order-4 rate kernel {kern_ms:.3f} ms/launch")
+    g64 = gamma.cpu().numpy()
+    k64 = kappa.cpu().numpy()
+    finite = bool(np.all(np.isfinite(k64)))
 
-    # backward step: dkappa/dGamma, then the adjoint of both rate orders
+    # algorithmic work of the order-4 kernel, per formulation
+    f4 = (320 * n4 + 60) * n_proc4                  # per-process form: 320 n4 + 60 FLOP per process
+    f_build = 216 * n4 * n_tup                      # tuple form: phase-weighted constants, 216 n4 per tuple
+    f_contract = (312 * n_groups + 60) * n_proc4    # tuple form: 39 complex MACs per group, + weights
+    sec = kern_ms * 1e-3
+    if variant == 4:
+        roof = {"bound": "mfma", "achieved": f_build / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "kernel": "k_rates4b (tuple-batched, FP64 MFMA + FP64 VALU)",
+                "work": f"216*n4 FLOP per (lambda, q', q'') tuple on FP64 MFMA, n4 = {n4}, {n_tup} tuples",
+                "valu_achieved": f_contract / sec / 1e12}
+    else:
+        roof = {"bound": "alu", "achieved": f4 / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "kernel": f"k_rates<4,...> variant {variant} (per-process, FP64 VALU)",
+                "work": f"320*n4 + 60 FLOP per process, n4 = {n4}"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel_ms"] = kern_ms
+    roof["per_process_form_equivalent_tflops"] = f4 / sec / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("variant") == variant:
+            traffic = tr.get("hbm_bytes_per_launch")
+    roof["traffic"] = traffic
+
+    # ---- mixed-precision forward (order 4 on bf16-split MFMA + FP32 contraction)
+    mixed = None
+    if not args.no_mixed:
+        path.precision = fp.FP_MIXED
+        ms_m, kern_m, gam_m, kap_m = run_forward(path, T, args.steps, 1, 24, torch, fp)
+        path.precision = fp.FP_FP64
+        gm = gam_m.cpu().numpy()
+        km = kap_m.cpu().numpy()
+        big = np.abs(g64) > 1e-6 * np.abs(g64).max()
+        rel = np.abs(gm[big] - g64[big]) / np.abs(g64[big])
+        kr = (km[:, 0] + km[:, 4] + km[:, 8]) / 3
+        k0 = (k64[:, 0] + k64[:, 4] + k64[:, 8]) / 3
+        sec_m = kern_m * 1e-3
+        mixed = {
+            "value": n_proc4 / (ms_m * 1e-3), "unit": "processes/s", "ms_per_step": ms_m,
+            "speedup_vs_fp64": ms_step / ms_m,
+            "kappa_rel_err": float(np.max(np.abs(kr - k0) / np.abs(k0))),
+            "gamma_rel_err_max": float(rel.max()), "gamma_rel_err_median": float(np.median(rel)),
+            "error_reference": "the FP64 GPU path of this run (held to the oracle at 1e-10 per mode by the tests)",
+            "roofline": {"bound": "mfma", "achieved": 6 * f_build / sec_m / 1e12, "peak": PEAK_BF16_TFLOPS,
+                         "unit": "TFLOP/s", "frac": 6 * f_build / sec_m / 1e12 / PEAK_BF16_TFLOPS,
+                         "kernel": "k_rates4m (bf16 split MFMA + FP32 VALU)", "kernel_ms": kern_m,
+                         "work": "6 bf16 products per FP32-accurate product, 216*n4 FLOP per tuple",
+                         "fp32_equivalent_tflops": f_build / sec_m / 1e12,
+                         "valu_achieved": f_contract / sec_m / 1e12,
+                         "per_process_form_equivalent_tflops": f4 / sec_m / 1e12},
+        }
+        log(f"bench: mixed {ms_m:.3f} ms/step (kernel {kern_m:.3f} ms), kappa rel err {mixed['kappa_rel_err']:.2e}, "
+            f"Gamma rel err max {mixed['gamma_rel_err_max']:.2e}")
+
+    # ---- backward: dkappa/dGamma, then the adjoint of both rate orders
     bwd = None
     if not args.no_backward:
         dk = torch.zeros_like(gamma)
@@ -177,13 +275,6 @@ def main():
                "step": "kappa_RTA with dkappa/dGamma + adjoint of the 3ph and 4ph rates (V recomputed)"}
         log(f"bench: backward {ms_bwd:.3f} ms/step, ratio {ms_bwd / ms_step:.2f}")
 
-    flop_per_proc = 320 * n4 + 60
-    achieved = flop_per_proc * n_proc4 / (kern_ms * 1e-3) / 1e12
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_source_hash") == kernel_source_hash():
-            traffic = tr.get("hbm_bytes_per_launch")
     out = {
         "metric": "4ph processes/sec at 1 GPU, FP64 vs mixed (rel err vs oracle); bwd/fwd time ratio",
         "value": n_proc4 / (ms_step * 1e-3),
@@ -202,22 +293,16 @@ def main():
                         f"32 cubic + {n4} quartic terms, sigma 0.1 THz, |Delta| <= 3 sigma, T = 300 K",
             "processes_4ph": n_proc4,
             "processes_3ph": n_proc3,
+            "tuples_4ph": n_tup,
+            "tuples_4ph_per_unit": n_unit_tup,
+            "partner_groups_4ph": n_groups,
+            "variant": variant,
             "step": "load_ifc(3,4) + rates3 + rates4 (Gamma3+Gamma4) + kappa_RTA",
             "host_enumeration_s": round(t_enum, 2),
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": traffic,
-            "kernel": "k_rates<4,1> (order-4 rate kernel)",
-            "kernel_ms": kern_ms,
-            "flop_per_process": flop_per_proc,
-        },
+        "roofline": roof,
         "kappa_finite": finite,
-        "mixed": None,
+        "mixed": mixed,
         "bwd_fwd_ratio": None if bwd is None else bwd["bwd_fwd_ratio"],
         "backward": bwd,
     }

@@ -210,6 +210,32 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
 
+/* One measured candidate of fp_autotune. */
+typedef struct {
+    int32_t variant, ppl, blocks_per_cu, reserved;
+    double ms;  /* mean time of one fp_rates call with these knobs */
+} fp_tune_entry;
+
+/* Autotuner of the persistent launch (work distribution and tile shape): runs
+ * the order-`order` rates of these lists (arguments as fp_rates3/fp_rates4)
+ * under every candidate launch configuration and leaves the fastest in the
+ * context's knobs.  Candidates for FP64 order 4: variant 0-4 x records per lane
+ * {1, 2, 4} (per-process forms; two-process forms {2, 4}; the tuple-batched
+ * form fixes it) x blocks_per_cu {0, 1}; for FP_MIXED order 4 and for order 3
+ * the knobs that apply.  Each candidate gets one untimed call and `reps`
+ * (1..100) timed ones, bracketed by HIP events on `hip_stream`; outputs go to a
+ * library-owned scratch buffer, so the caller's arrays are untouched.
+ * Synchronous.  Writes up to n_report entries to `report` (may be NULL with
+ * n_report 0) and their number to *n_written (may be NULL).  On an error the
+ * previous knobs are restored. */
+fp_status fp_autotune(fp_ctx* ctx, int32_t order, const fp_plist* lists, int32_t n_lists, int32_t n_T,
+                      const double* T_K, double sigma, int32_t precision, int32_t reps, fp_tune_entry* report,
+                      int32_t n_report, int32_t* n_written, void* hip_stream);
+
+/* Current value of a launch knob (names as for fp_set_knob) in *value.
+ * FP_ERR_ARG for an unknown name or a NULL pointer. */
+fp_status fp_get_knob(fp_ctx* ctx, const char* name, int64_t* value);
+
 /* Kernel timing for measurement: with enable != 0 every launch of the rate
  * kernel is bracketed by HIP events on its stream; fp_profile_read waits for
  * them and returns the summed milliseconds and the launch count of one kernel
@@ -234,8 +260,10 @@ fp_status fp_check(fp_ctx* ctx, void* hip_stream);
  * |Delta| <= nsigma*sigma, with Delta evaluated in double precision left to
  * right in record order (((w + s'w') + s''w'') + s'''w''').  Within a row the
  * records are ordered by (q', q'', j', j'', j''') (3ph: q', j', j''), so the
- * records of one (lambda, q', q'') tuple are contiguous.  keep_fraction in (0, 1] keeps a
- * deterministic hash-selected subset (1 keeps all) and seed selects the hash.
+ * records of one (lambda, q', q'') tuple are contiguous.  keep_fraction in
+ * (0, 1] keeps a deterministic hash-selected subset of each row's (q', q'')
+ * pairs (3ph: of its q'), each with all of its records that pass the filter (1
+ * keeps all); seed selects the hash.
  * n_threads <= 0 uses every hardware thread.  FP_ERR_ARG on invalid input,
  * FP_ERR_UNSUPPORTED beyond the record encoding's limits. */
 fp_status fp_enumerate_count(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,

@@ -31,8 +31,12 @@ __device__ inline void lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <int MAXT>
-__global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS) {
+// GRAD = true: the first half of the adjoint.  Instead of the rate partials,
+// write h_p = c_p conj(V_p) for every record, with c_p = 2 pref w G occ-weighted
+// by dL/dGamma of the row (sum over temperatures), to hbuf[hbase + record].
+template <int MAXT, bool GRAD>
+__global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS, const double* __restrict__ dldg, double pref,
+                                                      double2* __restrict__ hbuf) {
     __shared__ double2 sroots[kMaxRoots];
     __shared__ double2 sA[kWavesPerBlock][kTB][27];
     __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
@@ -224,9 +228,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS) {
             }
 
             // ---- weights and occupations (FP64)
+            double dl[MAXT];
+#pragma unroll
+            for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
 #pragma unroll
             for (int k = 0; k < kBR; ++k) {
                 const double V2 = V[k].x * V[k].x + V[k].y * V[k].y;
+                double cw = 0.0;
 #pragma unroll
                 for (int it = 0; it < MAXT; ++it) {
                     if (it < a.n_T) {
@@ -242,10 +250,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS) {
                         const double xw = pr[k].base * oc;
                         accw[it] += xw;
                         accg[it] += xw * V2;
+                        cw += dl[it] * oc;
                     }
+                }
+                if (GRAD && have[k]) {
+                    cw *= 2.0 * pref * pr[k].base;
+                    hbuf[ri.hbase + ud.start + k * kWave + lane] = make_double2(cw * V[k].x, -cw * V[k].y);
                 }
             }
         }
+        if (GRAD) continue;
         double* out = partial + u * (2 * a.n_T);
 #pragma unroll
         for (int it = 0; it < MAXT; ++it) {

@@ -68,9 +68,11 @@ struct Enum {
     int64_t index(const int64_t c[3]) const {
         return (wrapi(c[0], N[0]) * N[1] + wrapi(c[1], N[1])) * N[2] + wrapi(c[2], N[2]);
     }
-    bool keep(uint64_t row_g, uint64_t rec) const {
+    // keep_fraction samples whole (q', q'') pairs (3ph: q'), so a subsampled list
+    // holds every branch combination of the pairs it keeps, like a full list
+    bool keep(uint64_t row_g, uint64_t iq1, uint64_t iq2) const {
         if (keep_all) return true;
-        return mix64(seed ^ mix64(row_g ^ mix64(rec))) < keep_threshold;
+        return mix64(seed ^ mix64(row_g ^ mix64((iq1 << 32) | iq2))) < keep_threshold;
     }
 
     // Visit the kept records of row mode g0 in (q', q'', j', j'', j''') order (3ph: q', j', j'').
@@ -83,6 +85,7 @@ struct Enum {
         const int* s = ti.s;
         if (ti.order == 3) {
             for (int64_t iq1 = 0; iq1 < nq; ++iq1) {
+                if (!keep((uint64_t)g0, (uint64_t)iq1, 0)) continue;
                 int64_t q1[3], q2[3];
                 coords(iq1, q1);
                 // s2 q2 = -(q0 + s1 q1)
@@ -100,8 +103,7 @@ struct Enum {
                         if (!(w2 >= floor_)) continue;
                         const double delta = s[2] > 0 ? d1 + w2 : d1 - w2;
                         if (!(std::fabs(delta) <= cut)) continue;
-                        const uint64_t rec = (uint64_t)g1 | ((uint64_t)j2 << 24);
-                        if (keep((uint64_t)g0, rec)) emit(rec);
+                        emit((uint64_t)g1 | ((uint64_t)j2 << 24));
                     }
                 }
             }
@@ -114,6 +116,7 @@ struct Enum {
             int64_t q1[3];
             coords(iq1, q1);
             for (int64_t iq2 = tri12 ? iq1 : 0; iq2 < nq; ++iq2) {
+                if (!keep((uint64_t)g0, (uint64_t)iq1, (uint64_t)iq2)) continue;
                 int64_t q2[3], q3[3];
                 coords(iq2, q2);
                 for (int d = 0; d < 3; ++d) q3[d] = s[3] * (-(q0[d] + s[1] * q1[d] + s[2] * q2[d]));
@@ -136,8 +139,7 @@ struct Enum {
                             if (!(w3 >= floor_)) continue;
                             const double delta = s[3] > 0 ? d2 + w3 : d2 - w3;
                             if (!(std::fabs(delta) <= cut)) continue;
-                            const uint64_t rec = (uint64_t)g1 | ((uint64_t)g2 << 24) | ((uint64_t)j3 << 48);
-                            if (keep((uint64_t)g0, rec)) emit(rec);
+                            emit((uint64_t)g1 | ((uint64_t)g2 << 24) | ((uint64_t)j3 << 48));
                         }
                     }
                 }

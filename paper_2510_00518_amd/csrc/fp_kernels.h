@@ -40,6 +40,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));  // MFMA f64 accumulator 
 struct RowInfo {
     const uint64_t* rec;  // list record array
     int64_t beg, end;     // record range of the row
+    int64_t hbase;        // index of the list's first record among all records of the call
     int32_t mode;         // global mode of lambda, -1 if the row is invalid
     int32_t type;         // fp_ptype
 };
@@ -53,7 +54,7 @@ struct UnitDesc {
 struct ListArg {
     int32_t type;
     int32_t pad;
-    int64_t n_rows, row_base, n_rec;
+    int64_t n_rows, row_base, n_rec, rec_base;
     const int32_t* row_mode;
     const int64_t* row_off;
     const uint64_t* rec;
@@ -116,6 +117,7 @@ __global__ void k_rows(ListsArg la, int64_t n_modes, int64_t unit, RowInfo* __re
         }
         RowInfo ri;
         ri.rec = L.rec;
+        ri.hbase = L.rec_base;
         ri.beg = beg;
         ri.end = end;
         ri.mode = mode;

@@ -103,6 +103,8 @@ struct fp_ctx {
     DevBuf<double2> phit;
     DevBuf<uint4> fsp;  // bf16 split planes of phit (mixed precision)
     DevBuf<double> gpart;
+    DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
+    DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
     int* flag = nullptr;
     // tuning knobs
     int32_t ppl = 2;
@@ -233,6 +235,21 @@ extern "C" fp_status fp_set_knob(fp_ctx* c, const char* name, int64_t value) {
     } else {
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
     }
+    return FP_OK;
+}
+
+extern "C" fp_status fp_get_knob(fp_ctx* c, const char* name, int64_t* value) {
+    if (!c || !name || !value) return FP_ERR_ARG;
+    if (!strcmp(name, "ppl"))
+        *value = c->ppl;
+    else if (!strcmp(name, "blocks_per_cu"))
+        *value = c->blocks_per_cu;
+    else if (!strcmp(name, "grad_chunk"))
+        *value = c->grad_chunk;
+    else if (!strcmp(name, "variant"))
+        *value = c->variant;
+    else
+        return fail(c, FP_ERR_ARG, "unknown knob %s", name);
     return FP_OK;
 }
 
@@ -457,7 +474,7 @@ fp_status launch_mixed(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::Ra
 
 template <int T>
 fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
-    auto kern = fpk::k_rates4b<T>;
+    auto kern = fpk::k_rates4b<T, false>;
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
     if (occ < 1) occ = 1;
@@ -466,7 +483,27 @@ fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
-                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a);
+                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
+                       (const double*)nullptr, 0.0, (double2*)nullptr);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+// First half of the order-4 adjoint: h_p = c_p conj(V_p) per record, by the
+// tuple-batched kernel over units of 128 records.
+template <int T>
+fp_status launch_batched_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S,
+                           const double* dldg, double pref) {
+    auto kern = fpk::k_rates4b<T, true>;
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int64_t want = (n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * occ, want);
+    nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
+                       dldg, pref, c->hbuf.p);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -522,9 +559,11 @@ fp_status prepare(fp_ctx* c, int m, const fp_plist* lists, const std::vector<int
     fpk::ListsArg& la = pp->la;
     memset(&la, 0, sizeof la);
     la.n_lists = (int32_t)sel.size();
-    int64_t total_rows = 0, n_units = 0;
+    int64_t total_rows = 0, n_units = 0, rec_base = 0;
     for (size_t k = 0; k < sel.size(); ++k) {
         const fp_plist& P = lists[sel[k]];
+        la.l[k].rec_base = rec_base;
+        rec_base += P.n_rec;
         la.l[k].type = P.type;
         la.l[k].n_rows = P.n_rows;
         la.l[k].row_base = total_rows;
@@ -678,10 +717,10 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     return FP_OK;
 }
 
-template <int M, int T, int MAXP>
+template <int M, int T, int MAXP, bool HIN>
 fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
                       const double* dldg, double* dphi, bool accumulate) {
-    auto kern = fpk::k_grad<M, T, MAXP>;
+    auto kern = fpk::k_grad<M, T, MAXP, HIN>;
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
     if (occ < 1) occ = 1;
@@ -692,7 +731,7 @@ fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::
     hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(nblk * per)), dim3(256), 0, st, c->gpart.p, nblk * per, 0.0);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.tc.p, S.groups.p, S.pairs.p, S.scale.p, c->rows.p,
-                       c->units.p, dldg, c->gpart.p, c->flag, a);
+                       c->units.p, dldg, c->gpart.p, c->flag, a, HIN ? c->hbuf.p : nullptr);
     hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, nblk, S.n_terms, ncomp,
                        S.perm.p, accumulate ? 1 : 0, dphi);
     HIP_TRY(c, hipGetLastError());
@@ -702,8 +741,10 @@ fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::
 template <int M, int T>
 fp_status launch_grad_p(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
                         const double* dldg, double* dphi, bool accumulate) {
-    if (S.n_pairs <= 16) return launch_grad<M, T, 4>(c, st, pp, a, S, dldg, dphi, accumulate);
-    return launch_grad<M, T, 8>(c, st, pp, a, S, dldg, dphi, accumulate);
+    // order 4: h_p comes from the tuple-batched pass; order 3 recomputes V in place
+    constexpr bool HIN = M == 4;
+    if (S.n_pairs <= 16) return launch_grad<M, T, 4, HIN>(c, st, pp, a, S, dldg, dphi, accumulate);
+    return launch_grad<M, T, 8, HIN>(c, st, pp, a, S, dldg, dphi, accumulate);
 }
 
 }  // namespace
@@ -716,6 +757,86 @@ extern "C" fp_status fp_rates3(fp_ctx* c, const fp_plist* lists, int32_t n_lists
 extern "C" fp_status fp_rates4(fp_ctx* c, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                                double sigma, int32_t precision, double* gamma_out, double* wp_out, void* stream) {
     return run_rates(c, 4, lists, n_lists, n_T, T_K, sigma, precision, gamma_out, wp_out, stream);
+}
+
+extern "C" fp_status fp_autotune(fp_ctx* c, int32_t order, const fp_plist* lists, int32_t n_lists, int32_t n_T,
+                                 const double* T_K, double sigma, int32_t precision, int32_t reps,
+                                 fp_tune_entry* report, int32_t n_report, int32_t* n_written, void* stream) {
+    if (!c || (order != 3 && order != 4) || reps < 1 || reps > 100 || (n_report > 0 && !report) || n_report < 0)
+        return FP_ERR_ARG;
+    if (!c->modes) return fail(c, FP_ERR_STATE, "fp_load_modes has not been called");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t nm = c->n_modes;
+    if (n_T < 1 || n_T > FP_MAX_T) return fail(c, FP_ERR_ARG, "n_T must be in [1, %d]", FP_MAX_T);
+    HIP_TRY(c, c->tune_out.ensure((size_t)n_T * nm));
+    // candidates: (variant, records per lane, resident blocks per CU)
+    struct Cand { int32_t v, ppl, bpc; };
+    std::vector<Cand> cands;
+    const bool mixed4 = order == 4 && (precision & ~FP_ACCUMULATE) == FP_MIXED;
+    if (order == 3) {
+        for (int32_t ppl : {1, 2, 4})
+            for (int32_t bpc : {0, 1}) cands.push_back({c->variant, ppl, bpc});
+    } else if (mixed4) {
+        for (int32_t bpc : {0, 1}) cands.push_back({c->variant, 2, bpc});
+    } else {
+        for (int32_t v = 0; v < 5; ++v) {
+            const std::vector<int32_t> ppls = v == 4 ? std::vector<int32_t>{2}
+                                                     : (kVariants[v].np == 1 ? std::vector<int32_t>{1, 2, 4}
+                                                                             : std::vector<int32_t>{2, 4});
+            for (int32_t ppl : ppls)
+                for (int32_t bpc : {0, 1}) cands.push_back({v, ppl, bpc});
+        }
+    }
+    const int32_t keep_v = c->variant, keep_ppl = c->ppl, keep_bpc = c->blocks_per_cu;
+    const bool keep_prof = c->profile;
+    c->profile = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    double best = 1e300;
+    Cand pick = {keep_v, keep_ppl, keep_bpc};
+    int32_t written = 0;
+    fp_status bad = FP_OK;
+    for (const Cand& k : cands) {
+        c->variant = k.v;
+        c->ppl = k.ppl;
+        c->blocks_per_cu = k.bpc;
+        const int32_t prec = precision & ~FP_ACCUMULATE;
+        // one untimed launch, then `reps` timed ones
+        bad = run_rates(c, order, lists, n_lists, n_T, T_K, sigma, prec, c->tune_out.p, nullptr, stream);
+        if (bad != FP_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { bad = fail(c, FP_ERR_HIP, "event record failed"); break; }
+        for (int r = 0; r < reps && bad == FP_OK; ++r)
+            bad = run_rates(c, order, lists, n_lists, n_T, T_K, sigma, prec, c->tune_out.p, nullptr, stream);
+        if (bad != FP_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            bad = fail(c, FP_ERR_HIP, "event timing failed");
+            break;
+        }
+        const double per = ms / reps;
+        if (written < n_report) report[written++] = {k.v, k.ppl, k.bpc, 0, per};
+        if (per < best) {
+            best = per;
+            pick = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->profile = keep_prof;
+    if (n_written) *n_written = written;
+    if (bad != FP_OK) {
+        c->variant = keep_v;
+        c->ppl = keep_ppl;
+        c->blocks_per_cu = keep_bpc;
+        return bad;
+    }
+    c->variant = pick.v;
+    c->ppl = pick.ppl;
+    c->blocks_per_cu = pick.bpc;
+    return FP_OK;
 }
 
 extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t n_lists, int32_t n_T,
@@ -737,17 +858,50 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
         if (S.order != m) return fail(c, FP_ERR_STATE, "force constants of order %d not loaded", m);
         const int ncomp = m == 3 ? 27 : 81;
         std::vector<int> sel;
+        int64_t n_rec = 0, n_rows = 0;
         for (int l = 0; l < n_lists; ++l)
-            if (ORDER_OF(lists[l].type) == m) sel.push_back(l);
-        Prepared pp;
-        fp_status ps = prepare(c, m, lists, sel, n_T, T_K, c->grad_chunk, st, &pp);
-        if (ps != FP_OK) return ps;
-        if (pp.total_rows == 0) {
+            if (ORDER_OF(lists[l].type) == m) {
+                sel.push_back(l);
+                n_rec += lists[l].n_rec;
+                n_rows += lists[l].n_rows;
+            }
+        if (n_rows == 0) {
             if (!accumulate)
                 hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(S.n_terms * ncomp)), dim3(256), 0, st, dphi,
                                    S.n_terms * ncomp, 0.0);
+            HIP_TRY(c, hipGetLastError());
             continue;
         }
+        const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
+        hipEvent_t ev0, ev1;
+        fp_status ts = timer_start(c, st, &ev0, &ev1);
+        if (ts != FP_OK) return ts;
+        Prepared pp;
+        fp_status ps;
+        if (m == 4 && n_rec > 0) {
+            // first half: h_p = c_p conj(V_p) for every record (tuple-batched, units of 128)
+            ps = prepare(c, m, lists, sel, n_T, T_K, fpk::kBU, st, &pp);
+            if (ps != FP_OK) return ps;
+            HIP_TRY(c, c->hbuf.ensure((size_t)n_rec));
+            fpk::RatesArgs ra;
+            memset(&ra, 0, sizeof ra);
+            ra.n_units = pp.n_units;
+            ra.n_modes = c->n_modes;
+            ra.n_terms = (int32_t)S.n_terms;
+            ra.n_groups = S.n_groups;
+            ra.n_T = n_T;
+            ra.ppl = fpk::kBR;
+            ra.geo = pp.geo;
+            ra.inv_sigma2 = 1.0 / (sigma * sigma);
+            ra.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+            const double pref4 = rate_prefactor(c, m);
+            ps = tsel == 1 ? launch_batched_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                           : (tsel == 4 ? launch_batched_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                                        : launch_batched_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
+            if (ps != FP_OK) return ps;
+        }
+        ps = prepare(c, m, lists, sel, n_T, T_K, c->grad_chunk, st, &pp);
+        if (ps != FP_OK) return ps;
         fpk::GradArgs a;
         memset(&a, 0, sizeof a);
         a.n_units = pp.n_units;
@@ -760,10 +914,6 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
         a.inv_sigma2 = 1.0 / (sigma * sigma);
         a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
         a.pref = rate_prefactor(c, m);
-        const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
-        hipEvent_t ev0, ev1;
-        fp_status ts = timer_start(c, st, &ev0, &ev1);
-        if (ts != FP_OK) return ts;
         fp_status ls;
         if (m == 3)
             ls = tsel == 1 ? launch_grad_p<3, 1>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)

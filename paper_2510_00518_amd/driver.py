@@ -5,6 +5,9 @@ to device tensors, loads modes and force constants, and issues, in order,
 fp_load_ifc (order 3 and 4), fp_rates3, fp_rates4 (accumulating into the same
 Gamma) and fp_kappa_rta, all on one stream.
 """
+import json
+import os
+
 import numpy as np
 
 from . import fp
@@ -21,6 +24,38 @@ def host_lists(cfg, types, rows=None, sigma=None, nsigma=None, keep_fraction=1.0
         out[t] = fp.enumerate_list(t, cfg, row_mode=rows, sigma=sigma, nsigma=nsigma, keep_fraction=keep_fraction,
                                    seed=seed, n_threads=n_threads)
     return out
+
+
+def uneven_lists(cfg, types, lengths, pilot=1e-5, seed=0, n_threads=0):
+    """Lists whose length per irreducible q1 follows `lengths` (one target per
+    entry of cfg["q1"], summed over that q1's branches and the given types).
+    Each q1's rows are enumerated with the (q', q'')-pair sampling fraction that
+    a pilot pass at fraction `pilot` predicts, so every kept pair carries all of
+    its branch combinations, as in a full list.  Returns {type: (row_mode,
+    row_off, rec)} and the fraction used per q1."""
+    nb = cfg["nb"]
+    rows_all = np.asarray(row_modes(cfg))
+    per_q = [rows_all[rows_all // nb == q] for q in np.asarray(cfg["q1"])]
+    frac = []
+    for k, rows in enumerate(per_q):
+        n = sum(int(fp.enumerate_list(t, cfg, row_mode=rows, keep_fraction=pilot, seed=seed,
+                                      n_threads=n_threads)[1][-1]) for t in types) if len(rows) else 0
+        frac.append(min(1.0, float(lengths[k]) * pilot / n) if n > 0 else 1.0)
+    out = {}
+    for t in types:
+        rms, recs, offs, base = [], [], [np.zeros(1, np.int64)], 0
+        for k, rows in enumerate(per_q):
+            if len(rows) == 0:
+                continue
+            rm, off, rec = fp.enumerate_list(t, cfg, row_mode=rows, keep_fraction=frac[k], seed=seed + 1,
+                                             n_threads=n_threads)
+            rms.append(rm)
+            recs.append(rec)
+            offs.append(off[1:] + base)
+            base += int(off[-1])
+        out[t] = (np.concatenate(rms).astype(np.int32), np.concatenate(offs).astype(np.int64),
+                  np.concatenate(recs).astype(np.uint64))
+    return out, np.asarray(frac)
 
 
 class RatePath:
@@ -65,6 +100,40 @@ class RatePath:
     @property
     def n_proc3(self):
         return sum(pl.n_rec for pl in self.lists3)
+
+    def signature(self, order, n_T):
+        """Key of the autotuner cache: what the best launch depends on."""
+        lists = self.lists3 if order == 3 else self.lists4
+        return "|".join(str(x) for x in (order, self.precision if order == 4 else fp.FP_FP64, n_T,
+                                          self.cfg["nb"], self.n_modes, len(lists),
+                                          sum(pl.n_rows for pl in lists), sum(pl.n_rec for pl in lists)))
+
+    def autotune(self, T, order=4, cache=None, reps=2):
+        """Pick the launch knobs for this workload with the library's autotuner.
+        With `cache` (a JSON file path) a previous choice for the same workload
+        signature is reused instead of measured, and new choices are stored."""
+        key = self.signature(order, len(T))
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            for k in ("variant", "ppl", "blocks_per_cu"):
+                fp.fp_set_knob(self.ctx, k, table[key][k])
+            return table[key], []
+        lists = self.lists3 if order == 3 else self.lists4
+        self.load_ifc()
+        prec = self.precision if order == 4 else fp.FP_FP64
+        report = fp.fp_autotune(self.ctx, order, lists, T, self.cfg["sigma"], prec, reps=reps)
+        best = {k: fp.fp_get_knob(self.ctx, k) for k in ("variant", "ppl", "blocks_per_cu")}
+        best["ms"] = min(r["ms"] for r in report) if report else None
+        if cache:
+            table[key] = best
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return best, report
 
     def outputs(self, n_T):
         t = self.torch

@@ -23,7 +23,7 @@ FP_MAX_T = 8
 FP_MAX_LISTS = 8
 
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
-           "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_profile", "fp_profile_read",
+           "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
            "fp_enumerate_count", "fp_enumerate_fill"]
 
 
@@ -37,6 +37,11 @@ class fp_plist(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_rows", ctypes.c_int64),
                 ("n_rec", ctypes.c_int64), ("row_mode", ctypes.c_void_p), ("row_off", ctypes.c_void_p),
                 ("rec", ctypes.c_void_p)]
+
+
+class fp_tune_entry(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("ppl", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -63,6 +68,9 @@ def lib():
         L.fp_kappa_rta.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
         L.fp_check.argtypes = [vp, vp]
         L.fp_set_knob.argtypes = [vp, ctypes.c_char_p, i64]
+        L.fp_get_knob.argtypes = [vp, ctypes.c_char_p, vp]
+        L.fp_autotune.argtypes = [vp, i32, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, i32,
+                                  ctypes.POINTER(fp_tune_entry), i32, vp, vp]
         L.fp_profile.argtypes = [vp, i32]
         L.fp_profile_read.argtypes = [vp, i32, vp, vp]
         L.fp_enumerate_count.argtypes = [i32, vp, i32, vp, dbl, i64, vp, dbl, dbl, dbl, u64, i32, vp]
@@ -120,6 +128,12 @@ def fp_last_error(ctx):
 
 def fp_set_knob(ctx, name, value):
     _check(ctx, lib().fp_set_knob(ctx, name.encode(), int(value)))
+
+
+def fp_get_knob(ctx, name):
+    v = ctypes.c_int64(0)
+    _check(ctx, lib().fp_get_knob(ctx, name.encode(), ctypes.byref(v)))
+    return int(v.value)
 
 
 def fp_load_modes(ctx, mesh, n_atoms, lattice, masses, omega, evec, vel, omega_floor):
@@ -188,6 +202,19 @@ def fp_rates3(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=No
 
 def fp_rates4(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=None, stream=None):
     _rates(lib().fp_rates4, ctx, lists, T, sigma, precision, gamma_out, wp_out, stream)
+
+
+def fp_autotune(ctx, order, lists, T, sigma, precision=FP_FP64, reps=2, stream=None):
+    """Run the library's autotuner; returns the measured candidates as dicts
+    (the fastest is left in the context's knobs)."""
+    T = _host(np.atleast_1d(T), np.float64)
+    arr = _lists(lists)
+    rep = (fp_tune_entry * 64)()
+    n = ctypes.c_int32(0)
+    _check(ctx, lib().fp_autotune(ctx, int(order), arr, len(lists), len(T), _hp(T), float(sigma), int(precision),
+                                  int(reps), rep, 64, ctypes.byref(n), _stream(stream)))
+    return [{"variant": rep[i].variant, "ppl": rep[i].ppl, "blocks_per_cu": rep[i].blocks_per_cu, "ms": rep[i].ms}
+            for i in range(n.value)]
 
 
 def fp_rates_backward(ctx, lists, T, sigma, dL_dgamma, dphi3=None, dphi4=None, precision=FP_FP64, stream=None):

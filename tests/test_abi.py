@@ -115,8 +115,18 @@ def test_enumerator_keep_fraction_is_a_deterministic_subset():
     np.testing.assert_array_equal(half[2], again[2])
     frac = half[1][-1] / full[1][-1]
     assert 0.25 < frac < 0.35
+    nb = cfg["nb"]
+
+    def pairs(rec):
+        return ((rec & 0xFFFFFF) // nb) * 4096 + ((rec >> np.uint64(24)) & 0xFFFFFF) // nb
+
     for r in range(len(rows)):
-        assert set(half[2][half[1][r]:half[1][r + 1]]) <= set(full[2][full[1][r]:full[1][r + 1]])
+        mine = half[2][half[1][r]:half[1][r + 1]]
+        every = full[2][full[1][r]:full[1][r + 1]]
+        assert set(mine) <= set(every)
+        # whole (q', q'') pairs are kept: every record of a kept pair is present
+        kept = np.isin(pairs(every), pairs(mine))
+        np.testing.assert_array_equal(np.sort(every[kept]), np.sort(mine))
 
 
 def test_enumerator_argument_errors():
