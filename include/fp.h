@@ -171,6 +171,23 @@ fp_status fp_rates3(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t
 fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                     double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
 
+/* Four-phonon rates with the process lists generated on the GPU: enumeration
+ * (Algorithm 3) fused with the evaluation, for meshes whose lists would not fit
+ * in memory.  For every mode of row_mode (DEVICE int32 [n_rows], distinct modes)
+ * and every type selected by type_mask (bit 0 FP_4PP, bit 1 FP_4PM, bit 2
+ * FP_4MM), each (q', q'') pair and branch triple is tested on the GPU with the
+ * host enumerator's rules (frequency floor, triangle order, |Delta| <=
+ * nsigma*sigma in FP64 left to right) and the kept processes are evaluated in
+ * the FP64 tuple-batched form.  The result equals fp_rates4 over the lists that
+ * fp_enumerate_fill gives for these rows (keep_fraction 1), up to the grouping
+ * of the sums.  n_kept (DEVICE int64 [1], may be NULL) receives the number of
+ * processes evaluated.  Other arguments as fp_rates4; precision must be
+ * FP_FP64 (optionally | FP_ACCUMULATE).  Requires nb = 6 (two-atom cells):
+ * FP_ERR_UNSUPPORTED otherwise.  Asynchronous on hip_stream. */
+fp_status fp_rates4_fused(fp_ctx* ctx, int64_t n_rows, const int32_t* row_mode, int32_t type_mask, int32_t n_T,
+                          const double* T_K, double sigma, double nsigma, int32_t precision, double* gamma_out,
+                          double* wp_out, int64_t* n_kept, void* hip_stream);
+
 /* Adjoint of the rates (vector-Jacobian product): given dL/dGamma, a DEVICE
  * array [n_T][N*nb], write dL/dPhi for the raw force-constant entries,
  *   dphi3 DEVICE [n3][27] (eV/A^3 units of phi) and dphi4 DEVICE [n4][81],
@@ -205,7 +222,7 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *                    W-form with one or two processes per lane (0-3), or the
  *                    tuple-batched form (4: phase-weighted force constants per
  *                    (lambda, q', q'') tuple on FP64 MFMA, then per-process
- *                    contraction)
+ *                    contraction; the default)
  *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
@@ -240,8 +257,9 @@ fp_status fp_get_knob(fp_ctx* ctx, const char* name, int64_t* value);
  * kernel is bracketed by HIP events on its stream; fp_profile_read waits for
  * them and returns the summed milliseconds and the launch count of one kernel
  * since the last enable, then clears the record: order 3 or 4 = the FP64 rate
- * kernel of that order, 24 = the mixed-precision order-4 rate kernel, 13 or 14 =
- * the adjoint kernel of that order. */
+ * kernel of that order, 24 = the mixed-precision order-4 rate kernel, 34 = the
+ * fused-enumeration order-4 kernel, 13 or 14 = the adjoint kernels of that
+ * order. */
 fp_status fp_profile(fp_ctx* ctx, int32_t enable);
 fp_status fp_profile_read(fp_ctx* ctx, int32_t order, double* total_ms, int64_t* launches);
 

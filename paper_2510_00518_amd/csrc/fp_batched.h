@@ -31,6 +31,213 @@ __device__ inline void lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// One batch of up to 128 consecutive records of one row (two per lane, record
+// k * 64 + lane in rec[k]; `count` valid): decode, find the (q', q'') tuples,
+// build A_g per tuple and partner group on FP64 MFMA, contract per process on
+// the VALU, weight in FP64.  Adds this lane's Gamma and WP terms into
+// accg/accw; with GRAD it also writes h_p = c_p conj(V_p) to hout[k * 64 + lane]
+// for the valid records, c_p = 2 pref w G / prod(omega) sum_T dl[T] occ_T.
+// g0, type and count are wave-uniform; A and Qs are this wave's LDS staging.
+template <int MAXT, bool GRAD>
+__device__ inline void tb_batch(const uint64_t (&rec)[kBR], int count, int32_t g0, int type,
+                                const double2* __restrict__ phit_row, const double* __restrict__ omega,
+                                const double2* __restrict__ evec, const double* __restrict__ occ,
+                                const int32_t* __restrict__ tmeta, const int32_t* __restrict__ groups,
+                                int* __restrict__ flag, const RatesArgs& a, const double2* sroots, double2 (*A)[27],
+                                int32_t (*Qs)[2], double (&accg)[MAXT], double (&accw)[MAXT], const double (&dl)[MAXT],
+                                double pref, double2* __restrict__ hout) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int li = lane & 15, lk = lane >> 4;
+    const ModeGeom& geo = a.geo;
+    const int nb = geo.nb;
+    int s1, s2, s3;
+    type_signs(type, s1, s2, s3);
+    const double c1 = s1 > 0 ? 1.0 : -1.0;
+    const double c2 = s2 > 0 ? 1.0 : -1.0;
+    const double c3 = s3 > 0 ? 1.0 : -1.0;
+    const int32_t iq0 = g0 / nb;
+    const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
+    const double w0 = omega[g0];
+
+    // ---- records, tuple boundaries and slots
+    Proc pr[kBR];
+    bool have[kBR], first[kBR];
+    int slot[kBR];
+    uint64_t prev_last = ~0ull;
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < kBR; ++k) {
+        const int idx = k * kWave + lane;
+        have[k] = idx < count;
+        pr[k] = setup_proc<4>(have[k], rec[k], type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
+                              flag, a.inv_sigma2, a.gnorm);
+        const uint64_t key = have[k] ? (((uint64_t)(pr[k].g1 / nb) << 32) | (uint64_t)(pr[k].g2 / nb))
+                                     : ~0ull;
+        uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
+        if (lane == 0) up = prev_last;
+        first[k] = have[k] && key != up;
+        const uint64_t mask = __ballot(first[k]);
+        const uint64_t le = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+        slot[k] = base + __popcll(mask & le) - 1;
+        base += __popcll(mask);
+        prev_last = __shfl(key, kWave - 1, kWave);
+    }
+    const int n_tup = __builtin_amdgcn_readfirstlane(base);
+
+    double2 V[kBR];
+#pragma unroll
+    for (int k = 0; k < kBR; ++k) V[k] = make_double2(0.0, 0.0);
+    for (int gi = 0; gi < a.n_groups; ++gi) {
+        const int32_t* G = groups + gi * 8;
+        const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
+        const int n_ks = (t1 - t0 + 3) >> 2;
+        for (int tb = 0; tb < n_tup; tb += kTB) {
+            const int nbt = n_tup - tb < kTB ? n_tup - tb : kTB;
+            // tuple wavevectors of this batch, written by each tuple's first record
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) {
+                const int s = slot[k] - tb;
+                if (first[k] && s >= 0 && s < kTB) {
+                    Qs[s][0] = pr[k].Q10 | (pr[k].Q11 << 10) | (pr[k].Q12 << 20);
+                    Qs[s][1] = pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20);
+                }
+            }
+            lds_fence();
+            // A_g for the batch on MFMA: 2 component tiles x (1 or 2) tuple tiles,
+            // K = the group's terms, four at a time.  Each lane loads one force
+            // constant per component tile and one phase per tuple tile per K-step.
+            const bool two = nbt > 16;
+            int32_t qv[2][6];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int tj = nt * 16 + li;
+                const int32_t qa = Qs[tj < nbt ? tj : 0][0], qb = Qs[tj < nbt ? tj : 0][1];
+                qv[nt][0] = qa & 1023;
+                qv[nt][1] = (qa >> 10) & 1023;
+                qv[nt][2] = (qa >> 20) & 1023;
+                qv[nt][3] = qb & 1023;
+                qv[nt][4] = (qb >> 10) & 1023;
+                qv[nt][5] = (qb >> 20) & 1023;
+            }
+            d4 acr[2][2], aci[2][2];  // [tuple tile][component tile]
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) acr[nt][mt] = aci[nt][mt] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < n_ks; ++ks) {
+                const int term = t0 + 4 * ks + lk;
+                const bool kval = term < t1;
+                double2 F[2];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    const int comp = mt * 16 + li;
+                    F[mt] = (kval && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
+                }
+                int32_t tm[6];
+                const int32_t* tmp = tmeta + (kval ? term : t0) * 8;
+#pragma unroll
+                for (int d = 0; d < 6; ++d) tm[d] = tmp[1 + d];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    if (nt == 1 && !two) break;
+                    const int tj = nt * 16 + li;
+                    double2 ph = make_double2(0.0, 0.0);
+                    if (kval && tj < nbt) {
+                        uint32_t kk = 0;
+#pragma unroll
+                        for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[nt][d] * tm[d]);
+                        ph = sroots[mod_l(kk, geo.L, geo.magic)];
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.x, acr[nt][mt], 0, 0, 0);
+                        aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.y, aci[nt][mt], 0, 0, 0);
+                        acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-F[mt].y, ph.y, acr[nt][mt], 0, 0, 0);
+                        aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].y, ph.x, aci[nt][mt], 0, 0, 0);
+                    }
+                }
+            }
+            // D[i = 4r + lk][j = li]: component mt*16 + 4r + lk of tuple nt*16 + li
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int tj = nt * 16 + li;
+                if (tj < nbt) {
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int cc = mt * 16 + 4 * r + lk;
+                            if (cc < 27) A[tj][cc] = make_double2(acr[nt][mt][r], aci[nt][mt][r]);
+                        }
+                }
+            }
+            lds_fence();
+            // per-process contraction with this group's partner eigenvectors
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) {
+                const int s = slot[k] - tb;
+                if (have[k] && s >= 0 && s < nbt) {
+                    const double2* e1 = evec + (int64_t)pr[k].g1 * nb + 3 * ab;
+                    const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
+                    const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
+                    double2 x[3], y[3], z[3];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        x[q] = ld_eps(e1 + q, c1);
+                        y[q] = ld_eps(e2 + q, c2);
+                        z[q] = ld_eps(e3 + q, c3);
+                    }
+                    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        double2 ub = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double2 vc = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) vc = cfma(vc, A[s][(b * 3 + c) * 3 + d], z[d]);
+                            ub = cfma(ub, vc, y[c]);
+                        }
+                        acc = cfma(acc, ub, x[b]);
+                    }
+                    V[k].x += acc.x;
+                    V[k].y += acc.y;
+                }
+            }
+            lds_fence();
+        }
+    }
+
+    // ---- weights and occupations (FP64)
+#pragma unroll
+    for (int k = 0; k < kBR; ++k) {
+        const double V2 = V[k].x * V[k].x + V[k].y * V[k].y;
+        double cw = 0.0;
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) {
+            if (it < a.n_T) {
+                const double* n = occ + (int64_t)it * a.n_modes;
+                const double n1 = n[pr[k].g1], n2 = n[pr[k].g2], nl = n[pr[k].gl];
+                double oc;
+                if (type == 2)
+                    oc = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
+                else if (type == 3)
+                    oc = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
+                else
+                    oc = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
+                const double xw = pr[k].base * oc;
+                accw[it] += xw;
+                accg[it] += xw * V2;
+                cw += dl[it] * oc;
+            }
+        }
+        if (GRAD && have[k]) {
+            cw *= 2.0 * pref * pr[k].base;
+            hout[k * kWave + lane] = make_double2(cw * V[k].x, -cw * V[k].y);
+        }
+    }
+}
+
 // GRAD = true: the first half of the adjoint.  Instead of the rate partials,
 // write h_p = c_p conj(V_p) for every record, with c_p = 2 pref w G occ-weighted
 // by dL/dGamma of the row (sum over temperatures), to hbuf[hbase + record].
@@ -45,16 +252,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS, const do
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int li = lane & 15, lk = lane >> 4;
     const int xcd = blockIdx.x % kXcd;
     const int64_t per_xcd = (a.n_units + kXcd - 1) / kXcd;
     const int64_t u_beg = xcd * per_xcd;
     const int64_t u_end = u_beg + per_xcd < a.n_units ? u_beg + per_xcd : a.n_units;
     const int64_t wstride = (int64_t)(gridDim.x / kXcd) * kWavesPerBlock;
-    const ModeGeom geo = a.geo;
-    const int nb = geo.nb;
-    double2(*A)[27] = sA[wave];
-    int32_t(*Qs)[2] = sQ[wave];
 
     for (int64_t u = u_beg + (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave; u < u_end; u += wstride) {
         const UnitDesc ud = units[u];
@@ -67,197 +269,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS, const do
             const RowInfo ri = rows[row];
             const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
             const int type = __builtin_amdgcn_readfirstlane(ri.type);
-            int s1, s2, s3;
-            type_signs(type, s1, s2, s3);
-            const double c1 = s1 > 0 ? 1.0 : -1.0;
-            const double c2 = s2 > 0 ? 1.0 : -1.0;
-            const double c3 = s3 > 0 ? 1.0 : -1.0;
-            const int32_t iq0 = g0 / nb;
-            const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
-            const double w0 = omega[g0];
-            const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * 27;
-
-            // ---- records, tuple boundaries and slots
-            Proc pr[kBR];
-            bool have[kBR], first[kBR];
-            int slot[kBR];
-            uint64_t prev_last = ~0ull;
-            int base = 0;
+            uint64_t rec[kBR];
 #pragma unroll
             for (int k = 0; k < kBR; ++k) {
                 const int idx = k * kWave + lane;
-                have[k] = idx < count;
-                const uint64_t rec = have[k] ? ri.rec[ud.start + idx] : 0;
-                pr[k] = setup_proc<4>(have[k], rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
-                                      flag, a.inv_sigma2, a.gnorm);
-                const uint64_t key = have[k] ? (((uint64_t)(pr[k].g1 / nb) << 32) | (uint64_t)(pr[k].g2 / nb))
-                                             : ~0ull;
-                uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
-                if (lane == 0) up = prev_last;
-                first[k] = have[k] && key != up;
-                const uint64_t mask = __ballot(first[k]);
-                const uint64_t le = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
-                slot[k] = base + __popcll(mask & le) - 1;
-                base += __popcll(mask);
-                prev_last = __shfl(key, kWave - 1, kWave);
+                rec[k] = idx < count ? ri.rec[ud.start + idx] : 0;
             }
-            const int n_tup = __builtin_amdgcn_readfirstlane(base);
-
-            double2 V[kBR];
-#pragma unroll
-            for (int k = 0; k < kBR; ++k) V[k] = make_double2(0.0, 0.0);
-            for (int gi = 0; gi < a.n_groups; ++gi) {
-                const int32_t* G = groups + gi * 8;
-                const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
-                const int n_ks = (t1 - t0 + 3) >> 2;
-                for (int tb = 0; tb < n_tup; tb += kTB) {
-                    const int nbt = n_tup - tb < kTB ? n_tup - tb : kTB;
-                    // tuple wavevectors of this batch, written by each tuple's first record
-#pragma unroll
-                    for (int k = 0; k < kBR; ++k) {
-                        const int s = slot[k] - tb;
-                        if (first[k] && s >= 0 && s < kTB) {
-                            Qs[s][0] = pr[k].Q10 | (pr[k].Q11 << 10) | (pr[k].Q12 << 20);
-                            Qs[s][1] = pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20);
-                        }
-                    }
-                    lds_fence();
-                    // A_g for the batch on MFMA: 2 component tiles x (1 or 2) tuple tiles,
-                    // K = the group's terms, four at a time.  Each lane loads one force
-                    // constant per component tile and one phase per tuple tile per K-step.
-                    const bool two = nbt > 16;
-                    int32_t qv[2][6];
-#pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) {
-                        const int tj = nt * 16 + li;
-                        const int32_t qa = Qs[tj < nbt ? tj : 0][0], qb = Qs[tj < nbt ? tj : 0][1];
-                        qv[nt][0] = qa & 1023;
-                        qv[nt][1] = (qa >> 10) & 1023;
-                        qv[nt][2] = (qa >> 20) & 1023;
-                        qv[nt][3] = qb & 1023;
-                        qv[nt][4] = (qb >> 10) & 1023;
-                        qv[nt][5] = (qb >> 20) & 1023;
-                    }
-                    d4 acr[2][2], aci[2][2];  // [tuple tile][component tile]
-#pragma unroll
-                    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                        for (int mt = 0; mt < 2; ++mt) acr[nt][mt] = aci[nt][mt] = d4{0.0, 0.0, 0.0, 0.0};
-                    for (int ks = 0; ks < n_ks; ++ks) {
-                        const int term = t0 + 4 * ks + lk;
-                        const bool kval = term < t1;
-                        double2 F[2];
-#pragma unroll
-                        for (int mt = 0; mt < 2; ++mt) {
-                            const int comp = mt * 16 + li;
-                            F[mt] = (kval && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
-                        }
-                        int32_t tm[6];
-                        const int32_t* tmp = tmeta + (kval ? term : t0) * 8;
-#pragma unroll
-                        for (int d = 0; d < 6; ++d) tm[d] = tmp[1 + d];
-#pragma unroll
-                        for (int nt = 0; nt < 2; ++nt) {
-                            if (nt == 1 && !two) break;
-                            const int tj = nt * 16 + li;
-                            double2 ph = make_double2(0.0, 0.0);
-                            if (kval && tj < nbt) {
-                                uint32_t kk = 0;
-#pragma unroll
-                                for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[nt][d] * tm[d]);
-                                ph = sroots[mod_l(kk, geo.L, geo.magic)];
-                            }
-#pragma unroll
-                            for (int mt = 0; mt < 2; ++mt) {
-                                acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.x, acr[nt][mt], 0, 0, 0);
-                                aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.y, aci[nt][mt], 0, 0, 0);
-                                acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-F[mt].y, ph.y, acr[nt][mt], 0, 0, 0);
-                                aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].y, ph.x, aci[nt][mt], 0, 0, 0);
-                            }
-                        }
-                    }
-                    // D[i = 4r + lk][j = li]: component mt*16 + 4r + lk of tuple nt*16 + li
-#pragma unroll
-                    for (int nt = 0; nt < 2; ++nt) {
-                        const int tj = nt * 16 + li;
-                        if (tj < nbt) {
-#pragma unroll
-                            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) {
-                                    const int cc = mt * 16 + 4 * r + lk;
-                                    if (cc < 27) A[tj][cc] = make_double2(acr[nt][mt][r], aci[nt][mt][r]);
-                                }
-                        }
-                    }
-                    lds_fence();
-                    // per-process contraction with this group's partner eigenvectors
-#pragma unroll
-                    for (int k = 0; k < kBR; ++k) {
-                        const int s = slot[k] - tb;
-                        if (have[k] && s >= 0 && s < nbt) {
-                            const double2* e1 = evec + (int64_t)pr[k].g1 * nb + 3 * ab;
-                            const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
-                            const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
-                            double2 x[3], y[3], z[3];
-#pragma unroll
-                            for (int q = 0; q < 3; ++q) {
-                                x[q] = ld_eps(e1 + q, c1);
-                                y[q] = ld_eps(e2 + q, c2);
-                                z[q] = ld_eps(e3 + q, c3);
-                            }
-                            double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-                            for (int b = 0; b < 3; ++b) {
-                                double2 ub = make_double2(0.0, 0.0);
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) {
-                                    double2 vc = make_double2(0.0, 0.0);
-#pragma unroll
-                                    for (int d = 0; d < 3; ++d) vc = cfma(vc, A[s][(b * 3 + c) * 3 + d], z[d]);
-                                    ub = cfma(ub, vc, y[c]);
-                                }
-                                acc = cfma(acc, ub, x[b]);
-                            }
-                            V[k].x += acc.x;
-                            V[k].y += acc.y;
-                        }
-                    }
-                    lds_fence();
-                }
-            }
-
-            // ---- weights and occupations (FP64)
             double dl[MAXT];
 #pragma unroll
             for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
-#pragma unroll
-            for (int k = 0; k < kBR; ++k) {
-                const double V2 = V[k].x * V[k].x + V[k].y * V[k].y;
-                double cw = 0.0;
-#pragma unroll
-                for (int it = 0; it < MAXT; ++it) {
-                    if (it < a.n_T) {
-                        const double* n = occ + (int64_t)it * a.n_modes;
-                        const double n1 = n[pr[k].g1], n2 = n[pr[k].g2], nl = n[pr[k].gl];
-                        double oc;
-                        if (type == 2)
-                            oc = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
-                        else if (type == 3)
-                            oc = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
-                        else
-                            oc = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
-                        const double xw = pr[k].base * oc;
-                        accw[it] += xw;
-                        accg[it] += xw * V2;
-                        cw += dl[it] * oc;
-                    }
-                }
-                if (GRAD && have[k]) {
-                    cw *= 2.0 * pref * pr[k].base;
-                    hbuf[ri.hbase + ud.start + k * kWave + lane] = make_double2(cw * V[k].x, -cw * V[k].y);
-                }
-            }
+            tb_batch<MAXT, GRAD>(rec, count, g0, type, phit + (int64_t)row * a.n_terms * 27, omega, evec, occ, tmeta,
+                                 groups, flag, a, sroots, sA[wave], sQ[wave], accg, accw, dl, pref,
+                                 GRAD ? hbuf + ri.hbase + ud.start : nullptr);
         }
         if (GRAD) continue;
         double* out = partial + u * (2 * a.n_T);

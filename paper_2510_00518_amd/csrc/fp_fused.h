@@ -1,0 +1,254 @@
+// Four-phonon rates with the process lists generated on the GPU.
+// Included once, by fp_lib.hip, after fp_batched.h.
+//
+// The host enumerator (Appendix, Algorithm 3) walks every (q', q'') pair of a
+// row and keeps the branch triples that pass the energy filter; at a 16^3 mesh
+// its lists no longer fit in memory.  Here the walk runs on the GPU and feeds
+// the tuple-batched evaluation directly, so no list is ever stored:
+//   - a work unit is (type, row lambda, q'); a wave takes 64 values of q'' at a
+//     time, one per lane, and closes q''' by momentum;
+//   - each lane tests its nb^3 branch triples with exactly the host's rules
+//     (FP64 mismatch left to right, no contraction, "<=", frequency floor,
+//     triangle order on the global mode index) into a bit mask;
+//   - a wave-wide prefix sum of the mask popcounts orders the kept records by
+//     (q'', j', j'', j''') -- the enumerator's order -- and each batch of 128
+//     records is decoded from the masks (binary search over the prefix, select
+//     the n-th set bit; masks and prefixes are read across lanes by shuffles,
+//     so the kernel needs no more LDS than the list-driven one) and evaluated
+//     by tb_batch;
+//   - the rates of a unit go to one partial per unit, summed per row by
+//     k_finalize in unit order.
+// Compiled for nb = 6 (two-atom cells): the 216 candidate bits of a lane are
+// then compile-time positions in four 64-bit registers.
+#pragma once
+
+namespace fpk {
+
+constexpr int kFusedNb = 6;
+
+struct FusedArgs {
+    int64_t n_units;  // n_types * n_rows * Nq
+    int64_t n_rows;
+    int32_t n_types;
+    int32_t types[3];
+    double floor_, cut;
+};
+
+// Row and unit tables of a fused call: fused row fr = ti * n_rows + r.
+__global__ void k_fused_rows(const int32_t* __restrict__ row_mode, FusedArgs f, int64_t nq, int64_t n_modes,
+                             RowInfo* __restrict__ rows, int64_t* __restrict__ unit_off, int* flag) {
+    const int64_t n = (int64_t)f.n_types * f.n_rows;
+    for (int64_t fr = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; fr <= n; fr += (int64_t)gridDim.x * blockDim.x) {
+        unit_off[fr] = fr * nq;
+        if (fr == n) continue;
+        const int32_t ti = (int32_t)(fr / f.n_rows);
+        int32_t mode = row_mode[fr % f.n_rows];
+        if (mode < 0 || mode >= n_modes) {
+            raise_flag(flag);
+            mode = -1;
+        }
+        RowInfo ri;
+        ri.rec = nullptr;
+        ri.beg = ri.end = 0;
+        ri.hbase = 0;
+        ri.mode = mode;
+        ri.type = f.types[ti];
+        rows[fr] = ri;
+    }
+}
+
+// n-th (0-based) set bit of w; w has more than n set bits.
+__device__ inline int select_bit(uint64_t w, int n) {
+    int pos = 0;
+#pragma unroll
+    for (int half = 32; half >= 1; half >>= 1) {
+        const uint64_t lo = w & ((1ull << half) - 1);
+        const int c = __popcll(lo);
+        if (n >= c) {
+            n -= c;
+            w >>= half;
+            pos += half;
+        }
+    }
+    return pos;
+}
+
+template <int MAXT>
+__global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
+                                                     const double* __restrict__ occ, const double2* __restrict__ roots,
+                                                     const double2* __restrict__ phit,
+                                                     const int32_t* __restrict__ tmeta,
+                                                     const int32_t* __restrict__ groups,
+                                                     const RowInfo* __restrict__ rows, double* __restrict__ partial,
+                                                     int64_t* __restrict__ unit_kept, int* __restrict__ flag,
+                                                     RatesArgs a, FusedArgs f) {
+    constexpr int NB = kFusedNb;
+    __shared__ double2 sroots[kMaxRoots];
+    __shared__ double2 sA[kWavesPerBlock][kTB][27];
+    __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
+    for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xcd = blockIdx.x % kXcd;
+    const int64_t per_xcd = (f.n_units + kXcd - 1) / kXcd;
+    const int64_t u_beg = xcd * per_xcd;
+    const int64_t u_end = u_beg + per_xcd < f.n_units ? u_beg + per_xcd : f.n_units;
+    const int64_t wstride = (int64_t)(gridDim.x / kXcd) * kWavesPerBlock;
+    const ModeGeom geo = a.geo;
+    const int32_t N0 = geo.N0, N1 = geo.N1, N2 = geo.N2;
+    const int32_t nq = N0 * N1 * N2;
+    double dl[MAXT];
+#pragma unroll
+    for (int it = 0; it < MAXT; ++it) dl[it] = 0.0;
+
+    for (int64_t u = u_beg + (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave; u < u_end; u += wstride) {
+        const int32_t iq1 = (int32_t)(u % nq);
+        const int64_t fr = u / nq;
+        const RowInfo ri = rows[fr];
+        const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
+        const int type = __builtin_amdgcn_readfirstlane(ri.type);
+        double accg[MAXT], accw[MAXT];
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) accg[it] = accw[it] = 0.0;
+        int64_t kept = 0;
+        const double w0 = g0 >= 0 ? omega[g0] : 0.0;
+        if (g0 >= 0 && w0 >= f.floor_) {
+            int s1, s2, s3;
+            type_signs(type, s1, s2, s3);
+            const bool tri12 = s1 == s2, tri23 = s2 == s3;
+            const int32_t iq0 = g0 / NB;
+            const int32_t q00 = iq0 / (N1 * N2), q01 = (iq0 / N2) % N1, q02 = iq0 % N2;
+            const int32_t q10 = iq1 / (N1 * N2), q11 = (iq1 / N2) % N1, q12 = iq1 % N2;
+            const double2* __restrict__ phit_row = phit + fr * a.n_terms * 27;
+            double w1[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) w1[j] = omega[iq1 * NB + j];
+
+            for (int32_t start = tri12 ? iq1 : 0; start < nq; start += kWave) {
+                // ---- candidate masks: lane = q''
+                const int32_t iq2 = start + lane;
+                const bool qv = iq2 < nq;
+                uint64_t m[4] = {0, 0, 0, 0};
+                if (qv) {
+                    const int32_t q20 = iq2 / (N1 * N2), q21 = (iq2 / N2) % N1, q22 = iq2 % N2;
+                    // s3 q''' = -(q + s1 q' + s2 q'')
+                    const int32_t iq3 = (wrapn(s3 * -(q00 + s1 * q10 + s2 * q20), N0) * N1 +
+                                         wrapn(s3 * -(q01 + s1 * q11 + s2 * q21), N1)) * N2 +
+                                        wrapn(s3 * -(q02 + s1 * q12 + s2 * q22), N2);
+                    double w2[NB], w3[NB];
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        w2[j] = omega[iq2 * NB + j];
+                        w3[j] = omega[iq3 * NB + j];
+                    }
+#pragma unroll
+                    for (int j1 = 0; j1 < NB; ++j1) {
+                        const int32_t g1 = iq1 * NB + j1;
+                        const bool ok1 = w1[j1] >= f.floor_;
+                        const double d1 = s1 > 0 ? w0 + w1[j1] : w0 - w1[j1];
+#pragma unroll
+                        for (int j2 = 0; j2 < NB; ++j2) {
+                            const int32_t g2 = iq2 * NB + j2;
+                            const bool ok2 = ok1 && !(tri12 && g2 < g1) && w2[j2] >= f.floor_;
+                            const double d2 = s2 > 0 ? d1 + w2[j2] : d1 - w2[j2];
+#pragma unroll
+                            for (int j3 = 0; j3 < NB; ++j3) {
+                                const int32_t g3 = iq3 * NB + j3;
+                                const double delta = s3 > 0 ? d2 + w3[j3] : d2 - w3[j3];
+                                const bool keep = ok2 && !(tri23 && g3 < g2) && w3[j3] >= f.floor_ &&
+                                                  fabs(delta) <= f.cut;
+                                const int c = (j1 * NB + j2) * NB + j3;
+                                if (keep) m[c >> 6] |= 1ull << (c & 63);
+                            }
+                        }
+                    }
+                }
+                const int cnt = __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]);
+                // inclusive prefix over the wave
+                int incl = cnt;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const int v = __shfl_up(incl, d, kWave);
+                    if (lane >= d) incl += v;
+                }
+                const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+                const int excl = incl - cnt;
+                kept += total;
+                // ---- batches of 128 kept records, in (q'', j', j'', j''') order
+                for (int b0 = 0; b0 < total; b0 += kBU) {
+                    const int count = total - b0 < kBU ? total - b0 : kBU;
+                    uint64_t rec[kBR];
+#pragma unroll
+                    for (int k = 0; k < kBR; ++k) {
+                        // every lane decodes (clamped), so the shuffles see the whole wave
+                        const int p = b0 + k * kWave + lane;
+                        const int pc = p < total ? p : total - 1;
+                        int lo = 0, hi = kWave - 1;  // largest lane s with excl[s] <= pc
+#pragma unroll
+                        for (int it = 0; it < 6; ++it) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (__shfl(excl, mid, kWave) <= pc)
+                                lo = mid;
+                            else
+                                hi = mid - 1;
+                        }
+                        int n = pc - __shfl(excl, lo, kWave);
+                        uint64_t w[4];
+#pragma unroll
+                        for (int x = 0; x < 4; ++x) w[x] = __shfl(m[x], lo, kWave);
+                        // word holding the n-th set bit, then the bit within it
+                        uint64_t ww = w[0];
+                        int word = 0;
+#pragma unroll
+                        for (int x = 0; x < 3; ++x) {
+                            const int c = __popcll(ww);
+                            if (word == x && n >= c) {
+                                n -= c;
+                                word = x + 1;
+                                ww = w[x + 1];
+                            }
+                        }
+                        const int c = word * 64 + select_bit(ww, n);
+                        const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
+                        const uint64_t g1 = (uint64_t)(iq1 * NB + j1);
+                        const uint64_t g2 = (uint64_t)((start + lo) * NB + j2);
+                        rec[k] = p < total ? (g1 | (g2 << 24) | ((uint64_t)j3 << 48)) : 0;
+                    }
+                    tb_batch<MAXT, false>(rec, count, g0, type, phit_row, omega, evec, occ, tmeta, groups, flag, a,
+                                          sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
+                }
+            }
+        }
+        double* out = partial + u * (2 * a.n_T);
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) {
+            if (it < a.n_T) {
+                const double sg = wave_sum(accg[it]);
+                const double sw = wave_sum(accw[it]);
+                if (lane == 0) {
+                    out[it] = sg;
+                    out[a.n_T + it] = sw;
+                }
+            }
+        }
+        if (lane == 0) unit_kept[u] = kept;
+    }
+}
+
+// out[0] = sum of v[0..n), one block, fixed order.
+__global__ void k_sum_i64(const int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ out) {
+    __shared__ int64_t red[kBlock];
+    int64_t s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) s += v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace fpk

@@ -17,6 +17,7 @@
 #include "fp_grad.h"
 #include "fp_batched.h"
 #include "fp_mixed.h"
+#include "fp_fused.h"
 
 namespace {
 
@@ -105,11 +106,12 @@ struct fp_ctx {
     DevBuf<double> gpart;
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
+    DevBuf<int64_t> unit_kept;  // fused enumeration: kept records per unit
     int* flag = nullptr;
     // tuning knobs
     int32_t ppl = 2;
     int32_t blocks_per_cu = 0;  // 0: as many resident blocks as the kernel's occupancy allows
-    int32_t variant = 1;        // order-4 contraction variant (see k_rates)
+    int32_t variant = 4;        // order-4 contraction form: 0-3 per-process (k_rates), 4 tuple-batched
     int32_t grad_chunk = 8192;  // records per adjoint chunk (a multiple of 256)
     // kernel timing
     bool profile = false;
@@ -759,6 +761,115 @@ extern "C" fp_status fp_rates4(fp_ctx* c, const fp_plist* lists, int32_t n_lists
     return run_rates(c, 4, lists, n_lists, n_T, T_K, sigma, precision, gamma_out, wp_out, stream);
 }
 
+namespace {
+
+template <int T>
+fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const fpk::FusedArgs& f,
+                       const IfcState& S) {
+    auto kern = fpk::k_fused4<T>;
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
+    const int64_t want = (f.n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
+    nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->partial.p, c->unit_kept.p, c->flag,
+                       a, f);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+}  // namespace
+
+extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* row_mode, int32_t type_mask,
+                                     int32_t n_T, const double* T_K, double sigma, double nsigma, int32_t precision,
+                                     double* gamma_out, double* wp_out, int64_t* n_kept, void* stream) {
+    if (!c) return FP_ERR_ARG;
+    if (!c->modes) return fail(c, FP_ERR_STATE, "fp_load_modes has not been called");
+    IfcState& S = c->ifc[1];
+    if (S.order != 4) return fail(c, FP_ERR_STATE, "force constants of order 4 not loaded");
+    if (c->nb != fpk::kFusedNb) return fail(c, FP_ERR_UNSUPPORTED, "the fused path is built for nb = 6 (two atoms)");
+    if (n_rows < 0 || (n_rows > 0 && !row_mode)) return fail(c, FP_ERR_ARG, "bad row list");
+    if (type_mask < 1 || type_mask > 7) return fail(c, FP_ERR_ARG, "type_mask must be in [1, 7]");
+    if (n_T < 1 || n_T > FP_MAX_T || !T_K) return fail(c, FP_ERR_ARG, "n_T must be in [1, %d]", FP_MAX_T);
+    for (int i = 0; i < n_T; ++i)
+        if (!(T_K[i] > 0.0)) return fail(c, FP_ERR_ARG, "temperatures must be positive");
+    if (!(sigma > 0.0) || !(nsigma > 0.0)) return fail(c, FP_ERR_ARG, "sigma and nsigma must be positive");
+    const bool accumulate = (precision & FP_ACCUMULATE) != 0;
+    if ((precision & ~FP_ACCUMULATE) != FP_FP64) return fail(c, FP_ERR_UNSUPPORTED, "the fused path is FP_FP64 only");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t nm = c->n_modes;
+    if (gamma_out && !accumulate)
+        hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, gamma_out, n_T * nm, 0.0);
+    if (wp_out && !accumulate)
+        hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, wp_out, n_T * nm, 0.0);
+    if (n_rows == 0) {
+        if (n_kept) hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, (const int64_t*)nullptr,
+                                       (int64_t)0, n_kept);
+        HIP_TRY(c, hipGetLastError());
+        return FP_OK;
+    }
+    fpk::FusedArgs f;
+    memset(&f, 0, sizeof f);
+    for (int t = 0; t < 3; ++t)
+        if (type_mask & (1 << t)) f.types[f.n_types++] = FP_4PP + t;
+    f.n_rows = n_rows;
+    f.n_units = (int64_t)f.n_types * n_rows * c->nq;
+    f.floor_ = c->floor_;
+    f.cut = nsigma * sigma;
+    const int64_t n_frows = (int64_t)f.n_types * n_rows;
+    HIP_TRY(c, c->occ.ensure((size_t)n_T * nm));
+    HIP_TRY(c, c->rows.ensure((size_t)n_frows));
+    HIP_TRY(c, c->unit_off.ensure((size_t)n_frows + 1));
+    HIP_TRY(c, c->phit.ensure((size_t)n_frows * S.n_terms * 27));
+    HIP_TRY(c, c->partial.ensure((size_t)f.n_units * 2 * n_T));
+    HIP_TRY(c, c->unit_kept.ensure((size_t)f.n_units));
+    fpk::Temps tx;
+    for (int i = 0; i < 8; ++i) tx.x[i] = i < n_T ? kHbar / (kBoltz * T_K[i]) : 0.0;
+    hipLaunchKernelGGL(fpk::k_occ, dim3(grid_for(n_T * nm)), dim3(256), 0, st, c->omega.p, nm, n_T, tx, c->floor_,
+                       c->occ.p);
+    hipLaunchKernelGGL(fpk::k_fused_rows, dim3(grid_for(n_frows + 1)), dim3(256), 0, st, row_mode, f, (int64_t)c->nq,
+                       nm, c->rows.p, c->unit_off.p, c->flag);
+    const fpk::ModeGeom geo = geometry(c);
+    hipLaunchKernelGGL(fpk::k_precontract<4>, dim3(grid_for(n_frows * S.n_terms * 27)), dim3(256), 0, st, c->rows.p,
+                       n_frows, c->evec.p, c->roots.p, geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+    HIP_TRY(c, hipGetLastError());
+    fpk::RatesArgs a;
+    memset(&a, 0, sizeof a);
+    a.n_units = f.n_units;
+    a.n_modes = nm;
+    a.n_terms = (int32_t)S.n_terms;
+    a.n_groups = S.n_groups;
+    a.n_T = n_T;
+    a.ppl = fpk::kBR;
+    a.geo = geo;
+    a.inv_sigma2 = 1.0 / (sigma * sigma);
+    a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+    const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
+    hipEvent_t ev0, ev1;
+    fp_status ts = timer_start(c, st, &ev0, &ev1);
+    if (ts != FP_OK) return ts;
+    fp_status ls = tsel == 1 ? launch_fused<1>(c, st, a, f, S)
+                             : (tsel == 4 ? launch_fused<4>(c, st, a, f, S) : launch_fused<8>(c, st, a, f, S));
+    if (ls != FP_OK) return ls;
+    ts = timer_stop(c, st, 34, ev0, ev1);
+    if (ts != FP_OK) return ts;
+    const double pref = rate_prefactor(c, 4);
+    const double wpref = 1.0 / ((double)c->nq * (double)c->nq);
+    if (n_kept)
+        hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->unit_kept.p, f.n_units, n_kept);
+    // one finalize launch per type: rows of one mode in different types add into the same outputs
+    for (int ti = 0; ti < f.n_types; ++ti)
+        hipLaunchKernelGGL(fpk::k_finalize, dim3((unsigned)n_rows), dim3(fpk::kBlock), 0, st, c->partial.p,
+                           c->unit_off.p, c->rows.p, (int64_t)ti * n_rows, n_T, pref, wpref, gamma_out, wp_out, nm);
+    HIP_TRY(c, hipGetLastError());
+    if (c->validate) return fp_check(c, stream);
+    return FP_OK;
+}
+
 extern "C" fp_status fp_autotune(fp_ctx* c, int32_t order, const fp_plist* lists, int32_t n_lists, int32_t n_T,
                                  const double* T_K, double sigma, int32_t precision, int32_t reps,
                                  fp_tune_entry* report, int32_t n_report, int32_t* n_written, void* stream) {
@@ -943,7 +1054,8 @@ extern "C" fp_status fp_profile(fp_ctx* c, int32_t enable) {
 }
 
 extern "C" fp_status fp_profile_read(fp_ctx* c, int32_t order, double* total_ms, int64_t* launches) {
-    if (!c || !total_ms || !launches || (order != 3 && order != 4 && order != 13 && order != 14 && order != 24))
+    if (!c || !total_ms || !launches || (order != 3 && order != 4 && order != 13 && order != 14 && order != 24 &&
+                                               order != 34))
         return FP_ERR_ARG;
     HIP_TRY(c, hipSetDevice(c->device));
     double tot = 0.0;

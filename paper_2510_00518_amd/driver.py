@@ -78,6 +78,8 @@ class RatePath:
             self.phi3 = torch.as_tensor(cfg["ifc3"]["phi"]).to(self.device)
         if cfg.get("ifc4") is not None:
             self.phi4 = torch.as_tensor(cfg["ifc4"]["phi"]).to(self.device)
+        self.fused_rows = None
+        self.fused_mask = 0
         self.q1 = torch.as_tensor(np.ascontiguousarray(cfg["q1"], dtype=np.int32)).to(self.device)
         self.q1w = torch.as_tensor(np.ascontiguousarray(cfg["q1_weight"], dtype=np.float64)).to(self.device)
 
@@ -92,6 +94,16 @@ class RatePath:
         for t, (rm, off, rec) in sorted(lists.items()):
             pl = fp.PList.from_host(t, rm, off, rec, self.device)
             (self.lists3 if fp.ORDER[t] == 3 else self.lists4).append(pl)
+
+    def set_fused(self, rows=None, type_mask=7):
+        """Evaluate the order-4 rates with GPU-side enumeration (fp_rates4_fused)
+        over `rows` (default: every active mode of the q1 set) instead of lists."""
+        torch = self.torch
+        rows = row_modes(self.cfg) if rows is None else rows
+        self.fused_rows = torch.as_tensor(np.ascontiguousarray(rows, dtype=np.int32)).to(self.device)
+        self.fused_mask = type_mask
+        self.lists4 = []
+        self.kept = torch.zeros(1, dtype=torch.int64, device=self.device)
 
     @property
     def n_proc4(self):
@@ -142,6 +154,8 @@ class RatePath:
 
     def load_ifc(self, phi3=None, phi4=None):
         cfg = self.cfg
+        if self.fused_rows is not None and phi4 is None:
+            phi4 = self.phi4
         if self.lists3 or phi3 is not None:
             p = self.phi3 if phi3 is None else phi3
             fp.fp_load_ifc(self.ctx, 3, cfg["ifc3"]["atoms"], cfg["ifc3"]["cells"], p)
@@ -159,6 +173,11 @@ class RatePath:
         if self.lists4 and order in (None, 4):
             prec = self.precision if first else self.precision | fp.FP_ACCUMULATE
             fp.fp_rates4(self.ctx, self.lists4, T, sigma, prec, gamma, wp)
+            first = False
+        if self.fused_rows is not None and order in (None, 4):
+            prec = fp.FP_FP64 if first else fp.FP_FP64 | fp.FP_ACCUMULATE
+            fp.fp_rates4_fused(self.ctx, self.fused_rows, self.fused_mask, T, sigma, self.cfg["nsigma"], prec, gamma, wp,
+                               n_kept=self.kept)
             first = False
         if first:
             gamma.zero_()

@@ -23,7 +23,7 @@ FP_MAX_T = 8
 FP_MAX_LISTS = 8
 
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
-           "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
+           "fp_rates4_fused", "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
            "fp_enumerate_count", "fp_enumerate_fill"]
 
 
@@ -64,6 +64,7 @@ def lib():
         L.fp_load_ifc.argtypes = [vp, i32, i64, vp, vp, vp, i32, vp]
         for f in (L.fp_rates3, L.fp_rates4):
             f.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp]
+        L.fp_rates4_fused.argtypes = [vp, i64, vp, i32, i32, vp, dbl, dbl, i32, vp, vp, vp, vp]
         L.fp_rates_backward.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp, vp]
         L.fp_kappa_rta.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
         L.fp_check.argtypes = [vp, vp]
@@ -202,6 +203,15 @@ def fp_rates3(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=No
 
 def fp_rates4(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=None, stream=None):
     _rates(lib().fp_rates4, ctx, lists, T, sigma, precision, gamma_out, wp_out, stream)
+
+
+def fp_rates4_fused(ctx, row_mode, type_mask, T, sigma, nsigma, precision=FP_FP64, gamma_out=None, wp_out=None,
+                    n_kept=None, stream=None):
+    """row_mode: int32 device tensor of distinct modes; n_kept: int64 device tensor [1] or None."""
+    T = _host(np.atleast_1d(T), np.float64)
+    _check(ctx, lib().fp_rates4_fused(ctx, int(row_mode.numel()), _dp(row_mode), int(type_mask), len(T), _hp(T),
+                                      float(sigma), float(nsigma), int(precision), _dp(gamma_out), _dp(wp_out),
+                                      _dp(n_kept), _stream(stream)))
 
 
 def fp_autotune(ctx, order, lists, T, sigma, precision=FP_FP64, reps=2, stream=None):
