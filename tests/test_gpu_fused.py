@@ -54,16 +54,24 @@ def fused_rates(ctx, cfg, rows, T, mask=7, sigma=None):
 
 
 def oracle_rows(cfg, types, rows, T, sigma):
+    """The oracle's canonical (triangle-reduced) enumeration of each row, its
+    list-mode rates, and the number of listed processes."""
     S = oracle.System(cfg)
     n = cfg["omega"].size
     gam = np.zeros((len(T), n))
     wp = np.zeros((len(T), n))
     kept = 0
+    rows = np.asarray(rows, np.int32)
     for t in types:
-        g, w, k, _ = S.rates(t, np.asarray(rows, np.int32), T, sigma, cfg["nsigma"])
+        recs = [S.enumerate_row(t, int(g), sigma, cfg["nsigma"]) for g in rows]
+        off = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
+        kept += int(off[-1])
+        if off[-1] == 0:
+            continue
+        rec = np.concatenate(recs).astype(np.uint64)
+        g, w, _, _ = S.rates(t, rows, T, sigma, cfg["nsigma"], row_off=off, rec=rec)
         gam[:, rows] += g.T
         wp[:, rows] += w.T
-        kept += int(k.sum())
     return gam, wp, kept
 
 
