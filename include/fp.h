@@ -218,11 +218,12 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *   "ppl"            records per lane per work unit, 1..64 (unit = 64*ppl records)
  *   "blocks_per_cu"  resident 256-thread blocks per compute unit in the
  *                    persistent launch, 1..16; 0 = as many as fit
- *   "variant"        order-4 contraction form, 0..4: per-process P-form or
+ *   "variant"        order-4 contraction form, 0..5: per-process P-form or
  *                    W-form with one or two processes per lane (0-3), or the
- *                    tuple-batched form (4: phase-weighted force constants per
+ *                    tuple-batched form (phase-weighted force constants per
  *                    (lambda, q', q'') tuple on FP64 MFMA, then per-process
- *                    contraction; the default)
+ *                    contraction) with two records per lane (4, the default)
+ *                    or one (5)
  *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
@@ -236,9 +237,9 @@ typedef struct {
 /* Autotuner of the persistent launch (work distribution and tile shape): runs
  * the order-`order` rates of these lists (arguments as fp_rates3/fp_rates4)
  * under every candidate launch configuration and leaves the fastest in the
- * context's knobs.  Candidates for FP64 order 4: variant 0-4 x records per lane
+ * context's knobs.  Candidates for FP64 order 4: variant 0-5 x records per lane
  * {1, 2, 4} (per-process forms; two-process forms {2, 4}; the tuple-batched
- * form fixes it) x blocks_per_cu {0, 1}; for FP_MIXED order 4 and for order 3
+ * forms fix it) x blocks_per_cu {0, 1}; for FP_MIXED order 4 and for order 3
  * the knobs that apply.  Each candidate gets one untimed call and `reps`
  * (1..100) timed ones, bracketed by HIP events on `hip_stream`; outputs go to a
  * library-owned scratch buffer, so the caller's arrays are untouched.

@@ -24,12 +24,8 @@ namespace fpk {
 constexpr int kBU = 128;            // records per unit
 constexpr int kBR = kBU / kWave;    // records per lane
 constexpr int kTB = 32;             // tuples staged per batch
+constexpr int kMaxKs = 4;           // K-steps of four terms per partner group (groups hold <= 16 terms)
 
-__device__ inline void lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // One batch of up to 128 consecutive records of one row (two per lane, record
 // k * 64 + lane in rec[k]; `count` valid): decode, find the (q', q'') tuples,
@@ -38,8 +34,8 @@ __device__ inline void lds_fence() {
 // accg/accw; with GRAD it also writes h_p = c_p conj(V_p) to hout[k * 64 + lane]
 // for the valid records, c_p = 2 pref w G / prod(omega) sum_T dl[T] occ_T.
 // g0, type and count are wave-uniform; A and Qs are this wave's LDS staging.
-template <int MAXT, bool GRAD>
-__device__ inline void tb_batch(const uint64_t (&rec)[kBR], int count, int32_t g0, int type,
+template <int MAXT, bool GRAD, int BR = kBR, int TB = kTB>
+__device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0, int type,
                                 const double2* __restrict__ phit_row, const double* __restrict__ omega,
                                 const double2* __restrict__ evec, const double* __restrict__ occ,
                                 const int32_t* __restrict__ tmeta, const int32_t* __restrict__ groups,
@@ -60,13 +56,13 @@ __device__ inline void tb_batch(const uint64_t (&rec)[kBR], int count, int32_t g
     const double w0 = omega[g0];
 
     // ---- records, tuple boundaries and slots
-    Proc pr[kBR];
-    bool have[kBR], first[kBR];
-    int slot[kBR];
+    Proc pr[BR];
+    bool have[BR], first[BR];
+    int slot[BR];
     uint64_t prev_last = ~0ull;
     int base = 0;
 #pragma unroll
-    for (int k = 0; k < kBR; ++k) {
+    for (int k = 0; k < BR; ++k) {
         const int idx = k * kWave + lane;
         have[k] = idx < count;
         pr[k] = setup_proc<4>(have[k], rec[k], type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
@@ -84,108 +80,138 @@ __device__ inline void tb_batch(const uint64_t (&rec)[kBR], int count, int32_t g
     }
     const int n_tup = __builtin_amdgcn_readfirstlane(base);
 
-    double2 V[kBR];
+    double2 V[BR];
 #pragma unroll
-    for (int k = 0; k < kBR; ++k) V[k] = make_double2(0.0, 0.0);
+    for (int k = 0; k < BR; ++k) V[k] = make_double2(0.0, 0.0);
     for (int gi = 0; gi < a.n_groups; ++gi) {
         const int32_t* G = groups + gi * 8;
         const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
-        const int n_ks = (t1 - t0 + 3) >> 2;
-        for (int tb = 0; tb < n_tup; tb += kTB) {
-            const int nbt = n_tup - tb < kTB ? n_tup - tb : kTB;
+        const int n_ks = (t1 - t0 + 3) >> 2;  // <= kMaxKs: groups hold at most 16 terms
+        // this group's force constants and phase vectors for every K-step, one load
+        double2 Fk[kMaxKs][2];
+        int32_t tmk[kMaxKs][6];
+        bool kv[kMaxKs];
+#pragma unroll
+        for (int ks = 0; ks < kMaxKs; ++ks) {
+            const int term = t0 + 4 * ks + lk;
+            kv[ks] = ks < n_ks && term < t1;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const int comp = mt * 16 + li;
+                Fk[ks][mt] = (kv[ks] && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
+            }
+            const int32_t* tmp = tmeta + (kv[ks] ? term : t0) * 8;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) tmk[ks][d] = tmp[1 + d];
+        }
+        // with one record per lane, this group's partner eigenvector components are
+        // loaded here, together with the force constants, so that one memory
+        // round trip per group covers both
+        double2 xs[BR][3], ys[BR][3], zs[BR][3];
+        if (BR == 1) {
+#pragma unroll
+            for (int k = 0; k < BR; ++k) {
+                const double2* e1 = evec + (int64_t)pr[k].g1 * nb + 3 * ab;
+                const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
+                const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    xs[k][q] = ld_eps(e1 + q, c1);
+                    ys[k][q] = ld_eps(e2 + q, c2);
+                    zs[k][q] = ld_eps(e3 + q, c3);
+                }
+            }
+        }
+        for (int tb = 0; tb < n_tup; tb += TB) {
+            const int nbt = n_tup - tb < TB ? n_tup - tb : TB;
             // tuple wavevectors of this batch, written by each tuple's first record
 #pragma unroll
-            for (int k = 0; k < kBR; ++k) {
+            for (int k = 0; k < BR; ++k) {
                 const int s = slot[k] - tb;
-                if (first[k] && s >= 0 && s < kTB) {
+                if (first[k] && s >= 0 && s < TB) {
                     Qs[s][0] = pr[k].Q10 | (pr[k].Q11 << 10) | (pr[k].Q12 << 20);
                     Qs[s][1] = pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20);
                 }
             }
             lds_fence();
             // A_g for the batch on MFMA: 2 component tiles x (1 or 2) tuple tiles,
-            // K = the group's terms, four at a time.  Each lane loads one force
-            // constant per component tile and one phase per tuple tile per K-step.
-            const bool two = nbt > 16;
-            int32_t qv[2][6];
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
+            // one tuple tile at a time, K = the group's terms (at most 16), four
+            // at a time.  The group's force constants and phase vectors were
+            // loaded once for all its K-steps.  Complex products take three real
+            // MFMAs (Karatsuba):
+            //   k1 = (Fr + Fi) pr,  k2 = Fr (pi - pr),  k3 = Fi (pr + pi),
+            //   Re = k1 - k3,  Im = k1 + k2.
+            const int n_nt = (nbt + 15) >> 4;  // <= TB / 16
+            for (int nt = 0; nt < n_nt; ++nt) {
                 const int tj = nt * 16 + li;
-                const int32_t qa = Qs[tj < nbt ? tj : 0][0], qb = Qs[tj < nbt ? tj : 0][1];
-                qv[nt][0] = qa & 1023;
-                qv[nt][1] = (qa >> 10) & 1023;
-                qv[nt][2] = (qa >> 20) & 1023;
-                qv[nt][3] = qb & 1023;
-                qv[nt][4] = (qb >> 10) & 1023;
-                qv[nt][5] = (qb >> 20) & 1023;
-            }
-            d4 acr[2][2], aci[2][2];  // [tuple tile][component tile]
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) acr[nt][mt] = aci[nt][mt] = d4{0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < n_ks; ++ks) {
-                const int term = t0 + 4 * ks + lk;
-                const bool kval = term < t1;
-                double2 F[2];
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    const int comp = mt * 16 + li;
-                    F[mt] = (kval && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
+                const bool tval = tj < nbt;
+                int32_t qv[6];
+                {
+                    const int32_t qa = Qs[tval ? tj : 0][0], qb = Qs[tval ? tj : 0][1];
+                    qv[0] = qa & 1023;
+                    qv[1] = (qa >> 10) & 1023;
+                    qv[2] = (qa >> 20) & 1023;
+                    qv[3] = qb & 1023;
+                    qv[4] = (qb >> 10) & 1023;
+                    qv[5] = (qb >> 20) & 1023;
                 }
-                int32_t tm[6];
-                const int32_t* tmp = tmeta + (kval ? term : t0) * 8;
+                d4 k1[2], k2[2], k3[2];  // [component tile]
 #pragma unroll
-                for (int d = 0; d < 6; ++d) tm[d] = tmp[1 + d];
+                for (int mt = 0; mt < 2; ++mt) k1[mt] = k2[mt] = k3[mt] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    if (nt == 1 && !two) break;
-                    const int tj = nt * 16 + li;
+                for (int ks = 0; ks < kMaxKs; ++ks) {
+                    if (ks >= n_ks) break;
                     double2 ph = make_double2(0.0, 0.0);
-                    if (kval && tj < nbt) {
+                    if (kv[ks] && tval) {
                         uint32_t kk = 0;
 #pragma unroll
-                        for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[nt][d] * tm[d]);
+                        for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[d] * tmk[ks][d]);
                         ph = sroots[mod_l(kk, geo.L, geo.magic)];
                     }
+                    const double pd = ph.y - ph.x, ps = ph.x + ph.y;
 #pragma unroll
                     for (int mt = 0; mt < 2; ++mt) {
-                        acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.x, acr[nt][mt], 0, 0, 0);
-                        aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].x, ph.y, aci[nt][mt], 0, 0, 0);
-                        acr[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-F[mt].y, ph.y, acr[nt][mt], 0, 0, 0);
-                        aci[nt][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[mt].y, ph.x, aci[nt][mt], 0, 0, 0);
+                        const double2 F = Fk[ks][mt];
+                        k1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.x + F.y, ph.x, k1[mt], 0, 0, 0);
+                        k2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.x, pd, k2[mt], 0, 0, 0);
+                        k3[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.y, ps, k3[mt], 0, 0, 0);
                     }
                 }
-            }
-            // D[i = 4r + lk][j = li]: component mt*16 + 4r + lk of tuple nt*16 + li
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const int tj = nt * 16 + li;
-                if (tj < nbt) {
+                // D[i = 4r + lk][j = li]: component mt*16 + 4r + lk of tuple nt*16 + li
+                if (tval) {
 #pragma unroll
                     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int cc = mt * 16 + 4 * r + lk;
-                            if (cc < 27) A[tj][cc] = make_double2(acr[nt][mt][r], aci[nt][mt][r]);
+                            if (cc < 27) A[tj][cc] = make_double2(k1[mt][r] - k3[mt][r], k1[mt][r] + k2[mt][r]);
                         }
                 }
             }
             lds_fence();
             // per-process contraction with this group's partner eigenvectors
 #pragma unroll
-            for (int k = 0; k < kBR; ++k) {
+            for (int k = 0; k < BR; ++k) {
                 const int s = slot[k] - tb;
                 if (have[k] && s >= 0 && s < nbt) {
-                    const double2* e1 = evec + (int64_t)pr[k].g1 * nb + 3 * ab;
-                    const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
-                    const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
                     double2 x[3], y[3], z[3];
+                    if (BR == 1) {
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        x[q] = ld_eps(e1 + q, c1);
-                        y[q] = ld_eps(e2 + q, c2);
-                        z[q] = ld_eps(e3 + q, c3);
+                        for (int q = 0; q < 3; ++q) {
+                            x[q] = xs[k][q];
+                            y[q] = ys[k][q];
+                            z[q] = zs[k][q];
+                        }
+                    } else {
+                        const double2* e1 = evec + (int64_t)pr[k].g1 * nb + 3 * ab;
+                        const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
+                        const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            x[q] = ld_eps(e1 + q, c1);
+                            y[q] = ld_eps(e2 + q, c2);
+                            z[q] = ld_eps(e3 + q, c3);
+                        }
                     }
                     double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
@@ -210,7 +236,7 @@ __device__ inline void tb_batch(const uint64_t (&rec)[kBR], int count, int32_t g
 
     // ---- weights and occupations (FP64)
 #pragma unroll
-    for (int k = 0; k < kBR; ++k) {
+    for (int k = 0; k < BR; ++k) {
         const double V2 = V[k].x * V[k].x + V[k].y * V[k].y;
         double cw = 0.0;
 #pragma unroll
@@ -241,12 +267,13 @@ __device__ inline void tb_batch(const uint64_t (&rec)[kBR], int count, int32_t g
 // GRAD = true: the first half of the adjoint.  Instead of the rate partials,
 // write h_p = c_p conj(V_p) for every record, with c_p = 2 pref w G occ-weighted
 // by dL/dGamma of the row (sum over temperatures), to hbuf[hbase + record].
-template <int MAXT, bool GRAD>
-__global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS, const double* __restrict__ dldg, double pref,
-                                                      double2* __restrict__ hbuf) {
+// BR records per lane (units of 64 BR records), batches of TB tuples.
+template <int MAXT, bool GRAD, int BR = kBR, int TB = kTB>
+__global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS, const double* __restrict__ dldg,
+                                                                    double pref, double2* __restrict__ hbuf) {
     __shared__ double2 sroots[kMaxRoots];
-    __shared__ double2 sA[kWavesPerBlock][kTB][27];
-    __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
+    __shared__ double2 sA[kWavesPerBlock][TB][27];
+    __shared__ int32_t sQ[kWavesPerBlock][TB][2];
     for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
     __syncthreads();
 
@@ -269,16 +296,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS, const do
             const RowInfo ri = rows[row];
             const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
             const int type = __builtin_amdgcn_readfirstlane(ri.type);
-            uint64_t rec[kBR];
+            uint64_t rec[BR];
 #pragma unroll
-            for (int k = 0; k < kBR; ++k) {
+            for (int k = 0; k < BR; ++k) {
                 const int idx = k * kWave + lane;
                 rec[k] = idx < count ? ri.rec[ud.start + idx] : 0;
             }
             double dl[MAXT];
 #pragma unroll
             for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
-            tb_batch<MAXT, GRAD>(rec, count, g0, type, phit + (int64_t)row * a.n_terms * 27, omega, evec, occ, tmeta,
+            tb_batch<MAXT, GRAD, BR, TB>(rec, count, g0, type, phit + (int64_t)row * a.n_terms * 27, omega, evec, occ, tmeta,
                                  groups, flag, a, sroots, sA[wave], sQ[wave], accg, accw, dl, pref,
                                  GRAD ? hbuf + ri.hbase + ud.start : nullptr);
         }

@@ -283,6 +283,181 @@ __global__ __launch_bounds__(kBlock, HIN ? 2 : 1) void k_grad(FP_GRAD_PARAMS) {
     }
 }
 
+// Second pass of the order-4 adjoint in tuple form.  All processes of a
+// (lambda, q', q'') tuple share the phases ph_t, so per partner group g
+//   D_t[c] = sum_p h_p ph_t(p) P_p[c] = sum_tau ph_t(tau) B_tau[c],
+//   B_tau[c] = sum_{p in tau} h_p P_p[c],  h_p = c_p conj(V_p) (from the first pass).
+// A wave owns one (chunk of a row, partner group) work item.  It walks the
+// chunk 64 records at a time: stages each record's h_p and its 3 x 3 partner
+// eigenvector components for the group in LDS (one gather per record and
+// group), finds the tuples, and then each lane forms B for exactly the
+// (tuple, component) entry that it feeds to the MFMA B-operand, while the
+// A-operand carries ph_t(tau) for its (term, tuple) entry.  G = sum over tuples
+// accumulates on FP64 MFMA (three real products per complex one); after the
+// chunk it is folded with e_lambda and exp(i q.C_t) into the wave's own partial
+// dPhi, so the final block-order reduction makes the result deterministic.
+// Groups hold at most 16 terms: one 16-term A tile.
+__global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict__ evec, const double2* __restrict__ roots,
+                                                     const int32_t* __restrict__ tmeta, const int32_t* __restrict__ tc,
+                                                     const int32_t* __restrict__ groups,
+                                                     const double* __restrict__ tscale,
+                                                     const RowInfo* __restrict__ rows,
+                                                     const UnitDesc* __restrict__ units,
+                                                     const double2* __restrict__ hbuf, double* __restrict__ gpart,
+                                                     int* __restrict__ flag, GradArgs a) {
+    __shared__ double2 sroots[kMaxRoots];
+    __shared__ double2 sE[kWavesPerBlock][kWave][9];  // x(ab), y(ac), z(ad) per record
+    __shared__ double2 sH[kWavesPerBlock][kWave];
+    __shared__ int32_t sT[kWavesPerBlock][kWave + 1];  // first record of each tuple, then the end
+    __shared__ int32_t sQ[kWavesPerBlock][kWave][2];
+    for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const ModeGeom geo = a.geo;
+    const int nb = geo.nb;
+    const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wave;  // this wave's partial
+    const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
+    double* __restrict__ mypart = gpart + gw * a.n_terms * 81;
+    double2(*E)[9] = sE[wave];
+    double2* H = sH[wave];
+    int32_t* T = sT[wave];
+    int32_t(*Qs)[2] = sQ[wave];
+    const int64_t n_items = a.n_units * a.n_groups;
+
+    for (int64_t item = gw; item < n_items; item += n_waves) {
+        const int64_t chunk = item / a.n_groups;
+        const int gi = (int)(item % a.n_groups);
+        const UnitDesc ud = units[chunk];
+        const int32_t row = __builtin_amdgcn_readfirstlane(ud.row);
+        const int32_t count = __builtin_amdgcn_readfirstlane(ud.count);
+        if (row < 0 || count <= 0) continue;
+        const RowInfo ri = rows[row];
+        const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
+        if (g0 < 0) continue;
+        const int type = __builtin_amdgcn_readfirstlane(ri.type);
+        int s1, s2, s3;
+        type_signs(type, s1, s2, s3);
+        const double c1 = s1 > 0 ? 1.0 : -1.0;
+        const double c2 = s2 > 0 ? 1.0 : -1.0;
+        const double c3 = s3 > 0 ? 1.0 : -1.0;
+        const int32_t iq0 = g0 / nb;
+        const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
+        const int32_t* G = groups + gi * 8;
+        const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
+        // this lane's A-operand term and its phase vectors
+        const int term = t0 + li;
+        const bool tv = term < t1;
+        int32_t tm[6];
+        {
+            const int32_t* tp = tmeta + (tv ? term : t0) * 8;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) tm[d] = tp[1 + d];
+        }
+        d4 k1[2], k2[2], k3[2];  // [component tile]
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) k1[mt] = k2[mt] = k3[mt] = d4{0.0, 0.0, 0.0, 0.0};
+
+        for (int sub = 0; sub < count; sub += kWave) {
+            const int n_here = count - sub < kWave ? count - sub : kWave;
+            const int idx = sub + lane;
+            const bool have = lane < n_here;
+            const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
+            // decode: partners, signed wavevectors (as the forward does)
+            const Proc pr = decode4(have, rec, s1, s2, s3, g0, c00, c01, c02, geo, a.n_modes, flag);
+            const uint64_t key = have ? (((uint64_t)(pr.g1 / nb) << 32) | (uint64_t)(pr.g2 / nb)) : ~0ull;
+            const uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
+            const bool first = have && (lane == 0 || key != up);
+            const uint64_t mask = __ballot(first);
+            const uint64_t le = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+            const int slot = __popcll(mask & le) - 1;
+            const int n_tup = __builtin_amdgcn_readfirstlane(__popcll(mask));
+            if (first) {
+                T[slot] = lane;
+                Qs[slot][0] = pr.Q10 | (pr.Q11 << 10) | (pr.Q12 << 20);
+                Qs[slot][1] = pr.Q20 | (pr.Q21 << 10) | (pr.Q22 << 20);
+            }
+            if (lane == 0) T[n_tup] = n_here;
+            // h_p and the group's partner eigenvector components of this lane's record
+            H[lane] = have ? hbuf[ri.hbase + ud.start + idx] : make_double2(0.0, 0.0);
+            {
+                const double2* e1 = evec + (int64_t)pr.g1 * nb + 3 * ab;
+                const double2* e2 = evec + (int64_t)pr.g2 * nb + 3 * ac;
+                const double2* e3 = evec + (int64_t)pr.gl * nb + 3 * ad;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    E[lane][q] = ld_eps(e1 + q, c1);
+                    E[lane][3 + q] = ld_eps(e2 + q, c2);
+                    E[lane][6 + q] = ld_eps(e3 + q, c3);
+                }
+            }
+            lds_fence();
+            const int n_ks = (n_tup + 3) >> 2;
+            for (int ks = 0; ks < n_ks; ++ks) {
+                const int s = 4 * ks + lk;  // this lane's tuple (A column, B row)
+                const bool sv = s < n_tup;
+                // A-operand: ph_term(tuple)
+                double2 ph = make_double2(0.0, 0.0);
+                int r0 = 0, r1 = 0;
+                if (sv) {
+                    r0 = T[s];
+                    r1 = T[s + 1];
+                    if (tv) {
+                        const int32_t qa = Qs[s][0], qb = Qs[s][1];
+                        const uint32_t kk = (uint32_t)((qa & 1023) * tm[0] + ((qa >> 10) & 1023) * tm[1] +
+                                                       ((qa >> 20) & 1023) * tm[2] + (qb & 1023) * tm[3] +
+                                                       ((qb >> 10) & 1023) * tm[4] + ((qb >> 20) & 1023) * tm[5]);
+                        ph = sroots[mod_l(kk, geo.L, geo.magic)];
+                    }
+                }
+                const double pd_s = ph.x + ph.y;
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    // B-operand: B_tuple[c] for component c = 16 mt + li
+                    const int c = mt * 16 + li;
+                    double2 B = make_double2(0.0, 0.0);
+                    if (c < 27) {
+                        const int b = c / 9, g = (c / 3) % 3, d = c % 3;
+                        for (int r = r0; r < r1; ++r) {
+                            const double2 P = cmul(cmul(E[r][b], E[r][3 + g]), E[r][6 + d]);
+                            B = cfma(B, H[r], P);
+                        }
+                    }
+                    // G += ph B (Karatsuba: k1 = (Ar + Ai) Br, k2 = Ar (Bi - Br), k3 = Ai (Br + Bi))
+                    k1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pd_s, B.x, k1[mt], 0, 0, 0);
+                    k2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.x, B.y - B.x, k2[mt], 0, 0, 0);
+                    k3[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.y, B.x + B.y, k3[mt], 0, 0, 0);
+                }
+            }
+            lds_fence();
+        }
+        // fold: dPhi_t[a0][c] += s_t Re(e_lambda(a0_t)_a0 exp(i q.C_t) D_t[c]); D row 4 r + lk, column li
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int c = mt * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = t0 + 4 * r + lk;
+                if (t < t1 && c < 27) {
+                    const double2 D = make_double2(k1[mt][r] - k3[mt][r], k1[mt][r] + k2[mt][r]);
+                    const int32_t a0 = tmeta[t * 8];
+                    const uint32_t kq = (uint32_t)(c00 * tc[t * 4] + c01 * tc[t * 4 + 1] + c02 * tc[t * 4 + 2]);
+                    const double2 Dq = cmul(sroots[mod_l(kq, geo.L, geo.magic)], D);
+                    const double sc = tscale[t];
+                    double* out = mypart + (int64_t)t * 81 + c;
+#pragma unroll
+                    for (int al = 0; al < 3; ++al) {
+                        const double2 e = evec[(int64_t)g0 * nb + 3 * a0 + al];
+                        out[al * 27] += sc * (e.x * Dq.x - e.y * Dq.y);
+                    }
+                }
+            }
+        }
+    }
+}
+
 // dphi[perm[t]][k] (+)= sum_b gpart[b][t][k], summed in block order.
 __global__ void k_grad_reduce(const double* __restrict__ gpart, int64_t n_blocks, int64_t n_terms, int32_t ncomp,
                               const int32_t* __restrict__ perm, int accumulate, double* __restrict__ dphi) {

@@ -73,6 +73,18 @@ struct Temps {
 
 __device__ inline void raise_flag(int* flag) { atomicOr(flag, 1); }
 
+// Orders LDS writes and reads between the lanes of one wave (the staging areas
+// are per wave).  A wave's LDS operations complete in issue order, so waiting
+// for its LDS counter suffices; outstanding global loads stay in flight (a
+// workgroup-scope fence would also wait for them).  0xC07F = s_waitcnt
+// lgkmcnt(0) with vmcnt and expcnt at their maxima (gfx9 encoding).
+__device__ inline void lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- utilities
 
 __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
@@ -301,6 +313,47 @@ struct Proc {
     int32_t Q10, Q11, Q12, Q20, Q21, Q22;
     double base;
 };
+
+// Index part of setup_proc for an order-4 record: partner modes and signed
+// wavevectors, no frequencies or weight (base = 0).  Invalid or empty slots
+// point at the row's mode, like setup_proc.
+__device__ inline Proc decode4(bool have, uint64_t rec, int s1, int s2, int s3, int32_t g0, int32_t c00, int32_t c01,
+                               int32_t c02, const ModeGeom& geo, int64_t n_modes, int* __restrict__ flag) {
+    Proc p;
+    p.g1 = p.g2 = p.gl = g0;
+    p.Q10 = p.Q11 = p.Q12 = p.Q20 = p.Q21 = p.Q22 = 0;
+    p.base = 0.0;
+    if (!have) return p;
+    const int nb = geo.nb;
+    const int32_t g1 = (int32_t)(rec & 0xFFFFFFu);
+    const int32_t g2 = (int32_t)((rec >> 24) & 0xFFFFFFu);
+    const int32_t j_last = (int32_t)((rec >> 48) & 0xFFu);
+    if (g1 >= n_modes || g2 >= n_modes || j_last >= nb) {
+        raise_flag(flag);
+        return p;
+    }
+    const int32_t iq1 = g1 / nb, iq2 = g2 / nb;
+    const int32_t c10 = iq1 / (geo.N1 * geo.N2), c11 = (iq1 / geo.N2) % geo.N1, c12 = iq1 % geo.N2;
+    const int32_t c20 = iq2 / (geo.N1 * geo.N2), c21 = (iq2 / geo.N2) % geo.N1, c22 = iq2 % geo.N2;
+    p.Q10 = s1 > 0 ? c10 : wrapn(-c10, geo.N0);
+    p.Q11 = s1 > 0 ? c11 : wrapn(-c11, geo.N1);
+    p.Q12 = s1 > 0 ? c12 : wrapn(-c12, geo.N2);
+    p.Q20 = s2 > 0 ? c20 : wrapn(-c20, geo.N0);
+    p.Q21 = s2 > 0 ? c21 : wrapn(-c21, geo.N1);
+    p.Q22 = s2 > 0 ? c22 : wrapn(-c22, geo.N2);
+    int32_t ql0 = wrapn(-(c00 + p.Q10 + p.Q20), geo.N0);
+    int32_t ql1 = wrapn(-(c01 + p.Q11 + p.Q21), geo.N1);
+    int32_t ql2 = wrapn(-(c02 + p.Q12 + p.Q22), geo.N2);
+    if (s3 < 0) {
+        ql0 = wrapn(-ql0, geo.N0);
+        ql1 = wrapn(-ql1, geo.N1);
+        ql2 = wrapn(-ql2, geo.N2);
+    }
+    p.g1 = g1;
+    p.g2 = g2;
+    p.gl = ((ql0 * geo.N1 + ql1) * geo.N2 + ql2) * nb + j_last;
+    return p;
+}
 
 template <int M>
 __device__ inline Proc setup_proc(bool have, uint64_t rec, int type, int s1, int s2, int s3, int32_t g0, int32_t c00,

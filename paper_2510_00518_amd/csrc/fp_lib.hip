@@ -232,7 +232,7 @@ extern "C" fp_status fp_set_knob(fp_ctx* c, const char* name, int64_t value) {
         if (value < 256 || value > (1 << 22) || value % 256) return fail(c, FP_ERR_ARG, "grad_chunk: 256..2^22, multiple of 256");
         c->grad_chunk = (int32_t)value;
     } else if (!strcmp(name, "variant")) {
-        if (value < 0 || value > 4) return fail(c, FP_ERR_ARG, "variant must be in [0, 4]");
+        if (value < 0 || value > 5) return fail(c, FP_ERR_ARG, "variant must be in [0, 5]");
         c->variant = (int32_t)value;
     } else {
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
@@ -368,7 +368,10 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
                 tc[(size_t)i * 4 + d] = (int32_t)wrapi(-(int64_t)Rl[d] * sc[d], L);
             }
             const int64_t k = key(t);
-            if (groups.empty() || key(perm[(size_t)groups[groups.size() - 8 + 3]]) != k) {
+            // a group holds at most 16 terms (larger ones are split), so one
+            // group's operands fit the rate kernels' registers in one load
+            if (groups.empty() || key(perm[(size_t)groups[groups.size() - 8 + 3]]) != k ||
+                groups[groups.size() - 8 + 4] - groups[groups.size() - 8 + 3] >= 16) {
                 const int32_t g[8] = {at[1], at[2], m == 4 ? at[3] : 0, (int32_t)i, (int32_t)i + 1, 0, 0, 0};
                 groups.insert(groups.end(), g, g + 8);
             } else {
@@ -439,7 +442,11 @@ namespace {
 struct Variant {
     int ct, np;
 };
-constexpr Variant kVariants[5] = {{0, 1}, {1, 1}, {1, 2}, {0, 2}, {2, 2}};  // 4: tuple-batched
+// 4, 5: tuple-batched with two or one records per lane
+constexpr Variant kVariants[6] = {{0, 1}, {1, 1}, {1, 2}, {0, 2}, {2, 2}, {2, 1}};
+
+// records per lane of the tuple-batched forms (units of 64 x this many records)
+inline int batched_br(int variant) { return variant == 5 ? 1 : fpk::kBR; }
 
 template <int M, int T, int CT, int NP>
 fp_status launch_rates(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
@@ -474,9 +481,9 @@ fp_status launch_mixed(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::Ra
     return FP_OK;
 }
 
-template <int T>
+template <int T, int BR, int TB>
 fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
-    auto kern = fpk::k_rates4b<T, false>;
+    auto kern = fpk::k_rates4b<T, false, BR, TB>;
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
     if (occ < 1) occ = 1;
@@ -514,7 +521,8 @@ template <int M, int T>
 fp_status launch_variant(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
     if (M == 3) return launch_rates<3, T, 0, 1>(c, st, n_units, a, S);
     switch (c->variant) {
-        case 4: return launch_batched<T>(c, st, n_units, a, S);
+        case 4: return launch_batched<T, fpk::kBR, fpk::kTB>(c, st, n_units, a, S);
+        case 5: return launch_batched<T, 1, 16>(c, st, n_units, a, S);
         case 1: return launch_rates<4, T, 1, 1>(c, st, n_units, a, S);
         case 2: return launch_rates<4, T, 1, 2>(c, st, n_units, a, S);
         case 3: return launch_rates<4, T, 0, 2>(c, st, n_units, a, S);
@@ -652,7 +660,8 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     }
     const int np = m == 3 ? 1 : kVariants[c->variant].np;
     // the tuple-batched kernel works on units of exactly 128 records
-    const int64_t ppl = (m == 4 && (c->variant == 4 || mixed)) ? fpk::kBR : (c->ppl + np - 1) / np * np;
+    const int64_t ppl = mixed ? fpk::kBR
+                        : (m == 4 && c->variant >= 4) ? batched_br(c->variant) : (c->ppl + np - 1) / np * np;
     const int64_t unit = (int64_t)fpk::kWave * ppl;
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -735,6 +744,28 @@ fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::
                        c->roots.p, c->phit.p, S.tmeta.p, S.tc.p, S.groups.p, S.pairs.p, S.scale.p, c->rows.p,
                        c->units.p, dldg, c->gpart.p, c->flag, a, HIN ? c->hbuf.p : nullptr);
     hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, nblk, S.n_terms, ncomp,
+                       S.perm.p, accumulate ? 1 : 0, dphi);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+// Second pass of the order-4 adjoint, tuple form: one partial dPhi per wave.
+fp_status launch_grad4t(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
+                        double* dphi, bool accumulate) {
+    auto kern = fpk::k_grad4t;
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int64_t n_items = pp.n_units * (int64_t)S.n_groups;
+    const int64_t want = (n_items + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * occ, want));
+    const int64_t n_waves = nblk * fpk::kWavesPerBlock;
+    const int64_t per = (int64_t)S.n_terms * 81;
+    HIP_TRY(c, c->gpart.ensure((size_t)(n_waves * per)));
+    hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_waves * per)), dim3(256), 0, st, c->gpart.p, n_waves * per, 0.0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->evec.p, c->roots.p, S.tmeta.p, S.tc.p,
+                       S.groups.p, S.scale.p, c->rows.p, c->units.p, c->hbuf.p, c->gpart.p, c->flag, a);
+    hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, n_waves, S.n_terms, 81,
                        S.perm.p, accumulate ? 1 : 0, dphi);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
@@ -891,8 +922,8 @@ extern "C" fp_status fp_autotune(fp_ctx* c, int32_t order, const fp_plist* lists
     } else if (mixed4) {
         for (int32_t bpc : {0, 1}) cands.push_back({c->variant, 2, bpc});
     } else {
-        for (int32_t v = 0; v < 5; ++v) {
-            const std::vector<int32_t> ppls = v == 4 ? std::vector<int32_t>{2}
+        for (int32_t v = 0; v < 6; ++v) {
+            const std::vector<int32_t> ppls = v >= 4 ? std::vector<int32_t>{batched_br(v)}
                                                      : (kVariants[v].np == 1 ? std::vector<int32_t>{1, 2, 4}
                                                                              : std::vector<int32_t>{2, 4});
             for (int32_t ppl : ppls)
@@ -1031,9 +1062,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
                            : (tsel == 4 ? launch_grad_p<3, 4>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
                                         : launch_grad_p<3, 8>(c, st, pp, a, S, dL_dgamma, dphi, accumulate));
         else
-            ls = tsel == 1 ? launch_grad_p<4, 1>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
-                           : (tsel == 4 ? launch_grad_p<4, 4>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
-                                        : launch_grad_p<4, 8>(c, st, pp, a, S, dL_dgamma, dphi, accumulate));
+            ls = launch_grad4t(c, st, pp, a, S, dphi, accumulate);
         if (ls != FP_OK) return ls;
         ts = timer_stop(c, st, 10 + m, ev0, ev1);
         if (ts != FP_OK) return ts;
