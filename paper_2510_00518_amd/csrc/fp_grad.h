@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
                                                      const UnitDesc* __restrict__ units,
                                                      const double2* __restrict__ hbuf, double* __restrict__ gpart,
                                                      int* __restrict__ flag, GradArgs a) {
-    __shared__ double2 sroots[kMaxRoots];
+    extern __shared__ double2 sroots[];  // L roots of unity (dynamic: sized by the launch)
     __shared__ double2 sE[kWavesPerBlock][kWave][9];  // x(ab), y(ac), z(ad) per record
     __shared__ double2 sH[kWavesPerBlock][kWave];
     __shared__ int32_t sT[kWavesPerBlock][kWave + 1];  // first record of each tuple, then the end

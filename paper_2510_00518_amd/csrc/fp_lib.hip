@@ -753,8 +753,9 @@ fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::
 fp_status launch_grad4t(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
                         double* dphi, bool accumulate) {
     auto kern = fpk::k_grad4t;
+    const size_t shm = (size_t)c->L * sizeof(double2);  // the root table
     int occ = 0;
-    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
     const int64_t n_items = pp.n_units * (int64_t)S.n_groups;
     const int64_t want = (n_items + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
@@ -763,7 +764,7 @@ fp_status launch_grad4t(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk
     const int64_t per = (int64_t)S.n_terms * 81;
     HIP_TRY(c, c->gpart.ensure((size_t)(n_waves * per)));
     hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_waves * per)), dim3(256), 0, st, c->gpart.p, n_waves * per, 0.0);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->evec.p, c->roots.p, S.tmeta.p, S.tc.p,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->evec.p, c->roots.p, S.tmeta.p, S.tc.p,
                        S.groups.p, S.scale.p, c->rows.p, c->units.p, c->hbuf.p, c->gpart.p, c->flag, a);
     hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, n_waves, S.n_terms, 81,
                        S.perm.p, accumulate ? 1 : 0, dphi);
