@@ -11,9 +11,14 @@ Prints one JSON line.  value = 4ph processes per second of the whole FP64 step;
 "mixed" holds the same step with the order-4 rates in mixed precision (bf16
 split MFMA, FP32 contraction, FP64 weights) and its errors against FP64.
 roofline: the dominant kernel (the order-4 rate kernel) timed with HIP events
-on its own stream, algorithmic FLOP = (320 n4 + 60) per process, against the
-FP64 vector peak.  cpu_baseline: the FP64 oracle (list mode) on a bounded
-sample of the same lists on this host's cores.
+on its own stream, with the algorithmic FLOP of the form that ran: (320 n4 + 60)
+per process for the per-process forms; 216 n4 per (lambda, q', q'') tuple on
+FP64 MFMA (and 312 n_groups + 60 per process on the VALU) for the tuple-batched
+form.  backward: kappa_RTA with dkappa/dGamma and the adjoint of both orders.
+cpu_baseline: the FP64 oracle (list mode) on a bounded sample of the same lists
+on this host's cores.  --paper-scale adds the 16x16x16 two-atom cell (every row,
+three types, T = 300/600/900 K) through GPU-side enumeration; it holds the GPU
+for about a minute, so it is not part of the default run.
 """
 import argparse
 import hashlib
@@ -99,6 +104,34 @@ def partner_groups(ifc):
     return len({tuple(a[1:]) for a in np.asarray(ifc["atoms"]).tolist()})
 
 
+def paper_scale(torch, fp, RatePath):
+    """The 16^3 two-atom cell: every active row and the three four-phonon types
+    in one fp_rates4_fused call (lists generated on the GPU), T = 300/600/900 K."""
+    from paper_2510_00518_amd.synth import make_config, row_modes
+    cfg = make_config("fcc16_34ph")
+    T = [float(x) for x in cfg["T"]]
+    p = RatePath(cfg, device=0)
+    p.set_fused(row_modes(cfg), 7)
+    gam, wp = p.outputs(len(T))
+    p.load_ifc()
+    fp.fp_profile(p.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.rates(T, gam, wp, order=4)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, n = fp.fp_profile_read(p.ctx, 34)
+    fp.fp_profile(p.ctx, False)
+    fp.fp_check(p.ctx)
+    kept = int(p.kept.cpu()[0])
+    p.close()
+    log(f"bench: 16^3 fused: {kept} processes in {dt:.2f} s")
+    return {"workload": "4ph FP64, 2-atom diamond cell, 16x16x16 mesh, Oh-irreducible q1 (145), 62 cubic + "
+                        f"{int(cfg['ifc4']['n_terms'])} quartic terms, T = 300/600/900 K, lists generated on the GPU",
+            "processes_4ph": kept, "seconds": dt, "value": kept / dt, "unit": "processes/s",
+            "kernel_ms": k_ms / max(1, n), "rows": int(len(row_modes(cfg)))}
+
+
 def run_forward(path, T, steps, warmup, tag, torch, fp):
     """Warm up, then time `steps` whole steps; returns ms/step, the tagged
     kernel's ms/launch, and the last step's Gamma and kappa (host copies)."""
@@ -135,6 +168,8 @@ def main():
                     help="also run a 1 GiB device copy (reference kernel for HBM counter scaling)")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--paper-scale", action="store_true",
+                    help="also run the 16^3 two-atom cell through GPU-side enumeration (about a minute)")
     ap.add_argument("--ppl", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None, help="order-4 contraction form (library knob)")
@@ -306,6 +341,8 @@ def main():
         "bwd_fwd_ratio": None if bwd is None else bwd["bwd_fwd_ratio"],
         "backward": bwd,
     }
+    if args.paper_scale:
+        out["paper_scale"] = paper_scale(torch, fp, RatePath)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, lists, args.cpu_seconds)
