@@ -195,9 +195,11 @@ fp_status fp_rates4_fused(fp_ctx* ctx, int64_t n_rows, const int32_t* row_mode, 
  * OVERWRITTEN, or added to with FP_ACCUMULATE).  Gamma is quadratic in the
  * force constants, so dL/dPhi = sum_p c_p 2 Re(conj(V_p) dV_p/dPhi) with c_p the
  * process weight; V is recomputed from the lists, never stored.  The lists may
- * mix both orders; the other arguments are as in fp_rates3/fp_rates4.  FP64
- * only.  Deterministic: partial sums are kept per block and reduced in a fixed
- * order. */
+ * mix both orders; the other arguments are as in fp_rates3/fp_rates4.
+ * precision FP_FP64, or FP_MIXED: the order-4 V is recomputed with the
+ * mixed-precision forward (as fp_rates4 with FP_MIXED) while every sum that
+ * forms dL/dPhi stays in FP64; order 3 is FP64 either way.  Deterministic:
+ * partial sums are kept per wave and reduced in a fixed order. */
 fp_status fp_rates_backward(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                             double sigma, int32_t precision, const double* dL_dgamma, double* dphi3, double* dphi4,
                             void* hip_stream);
@@ -218,12 +220,14 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *   "ppl"            records per lane per work unit, 1..64 (unit = 64*ppl records)
  *   "blocks_per_cu"  resident 256-thread blocks per compute unit in the
  *                    persistent launch, 1..16; 0 = as many as fit
- *   "variant"        order-4 contraction form, 0..5: per-process P-form or
+ *   "variant"        order-4 contraction form, 0..7: per-process P-form or
  *                    W-form with one or two processes per lane (0-3), or the
  *                    tuple-batched form (phase-weighted force constants per
  *                    (lambda, q', q'') tuple on FP64 MFMA, then per-process
- *                    contraction) with two records per lane (4, the default)
- *                    or one (5)
+ *                    contraction) with two records per lane (4),
+ *                    one (5), or two with 24-tuple batches and three resident
+ *                    blocks per CU (6), or three records per lane (7, the
+ *                    default)
  *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
@@ -237,7 +241,7 @@ typedef struct {
 /* Autotuner of the persistent launch (work distribution and tile shape): runs
  * the order-`order` rates of these lists (arguments as fp_rates3/fp_rates4)
  * under every candidate launch configuration and leaves the fastest in the
- * context's knobs.  Candidates for FP64 order 4: variant 0-5 x records per lane
+ * context's knobs.  Candidates for FP64 order 4: variant 0-7 x records per lane
  * {1, 2, 4} (per-process forms; two-process forms {2, 4}; the tuple-batched
  * forms fix it) x blocks_per_cu {0, 1}; for FP_MIXED order 4 and for order 3
  * the knobs that apply.  Each candidate gets one untimed call and `reps`

@@ -267,11 +267,12 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
 // GRAD = true: the first half of the adjoint.  Instead of the rate partials,
 // write h_p = c_p conj(V_p) for every record, with c_p = 2 pref w G occ-weighted
 // by dL/dGamma of the row (sum over temperatures), to hbuf[hbase + record].
-// BR records per lane (units of 64 BR records), batches of TB tuples.
-template <int MAXT, bool GRAD, int BR = kBR, int TB = kTB>
-__global__ __launch_bounds__(kBlock, 2) void k_rates4b(FP_RATES_PARAMS, const double* __restrict__ dldg,
-                                                                    double pref, double2* __restrict__ hbuf) {
-    __shared__ double2 sroots[kMaxRoots];
+// BR records per lane (units of 64 BR records), batches of TB tuples, at least
+// OCC resident blocks per CU.  The root table is dynamic LDS of L entries.
+template <int MAXT, bool GRAD, int BR = kBR, int TB = kTB, int OCC = 2>
+__global__ __launch_bounds__(kBlock, OCC) void k_rates4b(FP_RATES_PARAMS, const double* __restrict__ dldg,
+                                                                      double pref, double2* __restrict__ hbuf) {
+    extern __shared__ double2 sroots[];
     __shared__ double2 sA[kWavesPerBlock][TB][27];
     __shared__ int32_t sQ[kWavesPerBlock][TB][2];
     for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];

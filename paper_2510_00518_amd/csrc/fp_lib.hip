@@ -111,7 +111,7 @@ struct fp_ctx {
     // tuning knobs
     int32_t ppl = 2;
     int32_t blocks_per_cu = 0;  // 0: as many resident blocks as the kernel's occupancy allows
-    int32_t variant = 4;        // order-4 contraction form: 0-3 per-process (k_rates), 4 tuple-batched
+    int32_t variant = 7;        // order-4 contraction form: 0-3 per-process (k_rates), 4-7 tuple-batched
     int32_t grad_chunk = 8192;  // records per adjoint chunk (a multiple of 256)
     // kernel timing
     bool profile = false;
@@ -232,7 +232,7 @@ extern "C" fp_status fp_set_knob(fp_ctx* c, const char* name, int64_t value) {
         if (value < 256 || value > (1 << 22) || value % 256) return fail(c, FP_ERR_ARG, "grad_chunk: 256..2^22, multiple of 256");
         c->grad_chunk = (int32_t)value;
     } else if (!strcmp(name, "variant")) {
-        if (value < 0 || value > 5) return fail(c, FP_ERR_ARG, "variant must be in [0, 5]");
+        if (value < 0 || value > 7) return fail(c, FP_ERR_ARG, "variant must be in [0, 7]");
         c->variant = (int32_t)value;
     } else {
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
@@ -442,11 +442,11 @@ namespace {
 struct Variant {
     int ct, np;
 };
-// 4, 5: tuple-batched with two or one records per lane
-constexpr Variant kVariants[6] = {{0, 1}, {1, 1}, {1, 2}, {0, 2}, {2, 2}, {2, 1}};
+// 4-7: tuple-batched (two records per lane; one; two with 24-tuple batches at 3 blocks per CU; three)
+constexpr Variant kVariants[8] = {{0, 1}, {1, 1}, {1, 2}, {0, 2}, {2, 2}, {2, 1}, {2, 2}, {2, 3}};
 
 // records per lane of the tuple-batched forms (units of 64 x this many records)
-inline int batched_br(int variant) { return variant == 5 ? 1 : fpk::kBR; }
+inline int batched_br(int variant) { return variant == 5 ? 1 : (variant == 7 ? 3 : fpk::kBR); }
 
 template <int M, int T, int CT, int NP>
 fp_status launch_rates(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
@@ -466,7 +466,7 @@ fp_status launch_rates(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::Ra
 
 template <int T>
 fp_status launch_mixed(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
-    auto kern = fpk::k_rates4m<T>;
+    auto kern = fpk::k_rates4m<T, false>;
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
     if (occ < 1) occ = 1;
@@ -476,22 +476,41 @@ fp_status launch_mixed(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::Ra
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec32.p, c->occ.p,
                        c->roots.p, c->fsp.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
-                       S.n_kblk);
+                       S.n_kblk, (const double*)nullptr, 0.0, (double2*)nullptr);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
 
-template <int T, int BR, int TB>
-fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
-    auto kern = fpk::k_rates4b<T, false, BR, TB>;
+// First pass of the mixed-precision order-4 adjoint (units of 128 records).
+template <int T>
+fp_status launch_mixed_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S,
+                         const double* dldg, double pref) {
+    auto kern = fpk::k_rates4m<T, true>;
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    if (occ < 1) occ = 1;
+    const int64_t want = (n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * occ, want);
+    nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec32.p, c->occ.p,
+                       c->roots.p, c->fsp.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
+                       S.n_kblk, dldg, pref, c->hbuf.p);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+template <int T, int BR, int TB, int OCC>
+fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
+    auto kern = fpk::k_rates4b<T, false, BR, TB, OCC>;
+    const size_t shm = (size_t)c->L * sizeof(double2);
+    int occ = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
     const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
     const int64_t want = (n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
                        (const double*)nullptr, 0.0, (double2*)nullptr);
     HIP_TRY(c, hipGetLastError());
@@ -503,14 +522,15 @@ fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::
 template <int T>
 fp_status launch_batched_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S,
                            const double* dldg, double pref) {
-    auto kern = fpk::k_rates4b<T, true>;
+    auto kern = fpk::k_rates4b<T, true, 3, 32, 2>;
+    const size_t shm = (size_t)c->L * sizeof(double2);
     int occ = 0;
-    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
     const int64_t want = (n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * occ, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
                        dldg, pref, c->hbuf.p);
     HIP_TRY(c, hipGetLastError());
@@ -521,8 +541,10 @@ template <int M, int T>
 fp_status launch_variant(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
     if (M == 3) return launch_rates<3, T, 0, 1>(c, st, n_units, a, S);
     switch (c->variant) {
-        case 4: return launch_batched<T, fpk::kBR, fpk::kTB>(c, st, n_units, a, S);
-        case 5: return launch_batched<T, 1, 16>(c, st, n_units, a, S);
+        case 4: return launch_batched<T, fpk::kBR, fpk::kTB, 2>(c, st, n_units, a, S);
+        case 5: return launch_batched<T, 1, 16, 2>(c, st, n_units, a, S);
+        case 6: return launch_batched<T, fpk::kBR, 24, 3>(c, st, n_units, a, S);
+        case 7: return launch_batched<T, 3, 32, 2>(c, st, n_units, a, S);
         case 1: return launch_rates<4, T, 1, 1>(c, st, n_units, a, S);
         case 2: return launch_rates<4, T, 1, 2>(c, st, n_units, a, S);
         case 3: return launch_rates<4, T, 0, 2>(c, st, n_units, a, S);
@@ -923,7 +945,7 @@ extern "C" fp_status fp_autotune(fp_ctx* c, int32_t order, const fp_plist* lists
     } else if (mixed4) {
         for (int32_t bpc : {0, 1}) cands.push_back({c->variant, 2, bpc});
     } else {
-        for (int32_t v = 0; v < 6; ++v) {
+        for (int32_t v = 0; v < 8; ++v) {
             const std::vector<int32_t> ppls = v >= 4 ? std::vector<int32_t>{batched_br(v)}
                                                      : (kVariants[v].np == 1 ? std::vector<int32_t>{1, 2, 4}
                                                                              : std::vector<int32_t>{2, 4});
@@ -990,7 +1012,8 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
     if (cs != FP_OK) return cs;
     const bool accumulate = (precision & FP_ACCUMULATE) != 0;
     precision &= ~FP_ACCUMULATE;
-    if (precision != FP_FP64) return fail(c, FP_ERR_UNSUPPORTED, "the adjoint is available in FP_FP64 only");
+    if (precision != FP_FP64 && precision != FP_MIXED) return fail(c, FP_ERR_ARG, "unknown precision %d", precision);
+    const bool mixed = precision == FP_MIXED;
     if (!dL_dgamma) return fail(c, FP_ERR_ARG, "dL_dgamma is null");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1022,8 +1045,9 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
         Prepared pp;
         fp_status ps;
         if (m == 4 && n_rec > 0) {
-            // first half: h_p = c_p conj(V_p) for every record (tuple-batched, units of 128)
-            ps = prepare(c, m, lists, sel, n_T, T_K, fpk::kBU, st, &pp);
+            // first half: h_p = c_p conj(V_p) for every record (tuple-batched, units of
+            // 192 records; mixed precision: units of 128)
+            ps = prepare(c, m, lists, sel, n_T, T_K, (mixed ? fpk::kBR : 3) * fpk::kWave, st, &pp);
             if (ps != FP_OK) return ps;
             HIP_TRY(c, c->hbuf.ensure((size_t)n_rec));
             fpk::RatesArgs ra;
@@ -1033,14 +1057,24 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
             ra.n_terms = (int32_t)S.n_terms;
             ra.n_groups = S.n_groups;
             ra.n_T = n_T;
-            ra.ppl = fpk::kBR;
+            ra.ppl = mixed ? fpk::kBR : 3;
             ra.geo = pp.geo;
             ra.inv_sigma2 = 1.0 / (sigma * sigma);
             ra.gnorm = 1.0 / (sigma * std::sqrt(kPi));
             const double pref4 = rate_prefactor(c, m);
-            ps = tsel == 1 ? launch_batched_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
-                           : (tsel == 4 ? launch_batched_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
-                                        : launch_batched_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
+            if (mixed) {
+                const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
+                HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
+                hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, pp.total_rows, c->phit.p,
+                                   S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_terms, c->fsp.p);
+                ps = tsel == 1 ? launch_mixed_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                               : (tsel == 4 ? launch_mixed_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                                            : launch_mixed_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
+            } else {
+                ps = tsel == 1 ? launch_batched_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                               : (tsel == 4 ? launch_batched_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                                            : launch_batched_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
+            }
             if (ps != FP_OK) return ps;
         }
         ps = prepare(c, m, lists, sel, n_T, T_K, c->grad_chunk, st, &pp);

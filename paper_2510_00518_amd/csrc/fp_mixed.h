@@ -110,8 +110,12 @@ __device__ inline float2 ld_eps32(const float2* __restrict__ e, float csign) {
     return v;
 }
 
-template <int MAXT>
-__global__ __launch_bounds__(kBlock, 2) void k_rates4m(FP_RATES_MIXED_PARAMS) {
+// GRAD = true: first pass of the mixed-precision adjoint.  Instead of the rate
+// partials, write h_p = c_p conj(V_p) in FP64 for every record (V from the
+// mixed-precision contraction), as the FP64 tuple-batched kernel does.
+template <int MAXT, bool GRAD>
+__global__ __launch_bounds__(kBlock, 2) void k_rates4m(FP_RATES_MIXED_PARAMS, const double* __restrict__ dldg,
+                                                      double pref, double2* __restrict__ hbuf) {
     __shared__ uint4 sroot[kMaxRoots];  // word s = bf16 split s of (Re, Im) of the root
     __shared__ float2 sA[kWavesPerBlock][kTB][27];
     __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
@@ -322,10 +326,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4m(FP_RATES_MIXED_PARAMS) {
             }
 
             // ---- weights and occupations (FP64)
+            double dl[MAXT];
+#pragma unroll
+            for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
 #pragma unroll
             for (int k = 0; k < kBR; ++k) {
                 const double vx = V[k].x, vy = V[k].y;
                 const double V2 = vx * vx + vy * vy;
+                double cw = 0.0;
 #pragma unroll
                 for (int it = 0; it < MAXT; ++it) {
                     if (it < a.n_T) {
@@ -341,10 +349,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4m(FP_RATES_MIXED_PARAMS) {
                         const double xw = pr[k].base * oc;
                         accw[it] += xw;
                         accg[it] += xw * V2;
+                        cw += dl[it] * oc;
                     }
+                }
+                if (GRAD && have[k]) {
+                    cw *= 2.0 * pref * pr[k].base;
+                    hbuf[ri.hbase + ud.start + k * kWave + lane] = make_double2(cw * vx, -cw * vy);
                 }
             }
         }
+        if (GRAD) continue;
         double* out = partial + u * (2 * a.n_T);
 #pragma unroll
         for (int it = 0; it < MAXT; ++it) {

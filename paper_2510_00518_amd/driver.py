@@ -220,7 +220,8 @@ def rates_autograd():
             d4 = torch.zeros_like(phi4) if ctx.has4 else None
             path.load_ifc(phi3=phi3.detach() if ctx.has3 else None, phi4=phi4.detach() if ctx.has4 else None)
             fp.fp_rates_backward(path.ctx, path.lists3 + path.lists4, ctx.T, path.cfg["sigma"],
-                                 grad_gamma.contiguous(), d3 if path.lists3 else None, d4 if path.lists4 else None)
+                                 grad_gamma.contiguous(), d3 if path.lists3 else None, d4 if path.lists4 else None,
+                                 precision=path.precision)
             if d3 is not None and not path.lists3:
                 d3.zero_()
             if d4 is not None and not path.lists4:

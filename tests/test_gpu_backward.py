@@ -39,7 +39,7 @@ def oracle_lists(cfg, types, rows, sigma):
     return out
 
 
-def gpu_grad(ctx, cfg, lists, T, dLdG, chunk=None):
+def gpu_grad(ctx, cfg, lists, T, dLdG, chunk=None, precision=fp.FP_FP64):
     import torch
     from paper_2510_00518_amd.driver import RatePath
     p = RatePath(cfg, ctx=ctx)
@@ -51,7 +51,7 @@ def gpu_grad(ctx, cfg, lists, T, dLdG, chunk=None):
     d3 = torch.zeros_like(p.phi3) if p.phi3 is not None else None
     d4 = torch.zeros_like(p.phi4) if p.phi4 is not None else None
     fp.fp_rates_backward(ctx, p.lists3 + p.lists4, T, cfg["sigma"], dl, d3 if p.lists3 else None,
-                         d4 if p.lists4 else None)
+                         d4 if p.lists4 else None, precision=precision)
     fp.fp_check(ctx)
     torch.cuda.synchronize()
     fp.fp_set_knob(ctx, "grad_chunk", 8192)
@@ -100,6 +100,28 @@ def test_backward_matches_oracle_gradient(ctx, case):
         assert_grad(g4, o4, f"{case} dPhi4")
 
 
+@pytest.mark.parametrize("cell", ["prim", "conv"])
+def test_backward_mixed_precision(ctx, cell):
+    """FP_MIXED: V recomputed with the mixed-precision forward (FP32-accurate),
+    dPhi summed in FP64; held to the oracle's FP64 gradient at 1e-4 per component
+    relative to max(|g|, 1e-3 |g|_inf), i.e. about 1e-7 of the largest entry for
+    the smallest ones (observed errors are printed)."""
+    if cell == "prim":
+        cfg = dict(small_config(3), sigma=2.0)
+        rows = row_modes(cfg)[::3]
+        types = (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM)
+    else:
+        cfg = small_config(2, n3=0, n4=200, cell="conv")
+        rows = row_modes(cfg)[::17]
+        types = (fp.FP_4PM,)
+    lists = oracle_lists(cfg, types, rows, cfg["sigma"])
+    T = [300.0, 900.0]
+    dLdG = np.random.default_rng(4).uniform(0.5, 1.5, size=(len(T), cfg["omega"].size))
+    _, g4 = gpu_grad(ctx, cfg, lists, T, dLdG, precision=fp.FP_MIXED)
+    _, o4 = oracle_grad(cfg, lists, T, dLdG)
+    assert_grad(g4, o4, f"mixed-precision dPhi4 ({cell})", rtol=1e-4)
+
+
 def test_backward_chunking_and_passes(ctx):
     """Chunk sizes change only the summation grouping; the 8-atom cell has more
     adjoint tiles than one pass holds."""
@@ -136,6 +158,13 @@ def test_kappa_gradient_against_central_differences(ctx):
     say("records 4ph", path.n_proc4, "3ph", path.n_proc3)
     Rates, KappaRTA = rates_autograd()
     T = [300.0]
+    # the mixed-precision backward (order-4 V from the mixed forward) on the same graph
+    path.precision = fp.FP_MIXED
+    m3 = path.phi3.clone().requires_grad_(True)
+    m4 = path.phi4.clone().requires_grad_(True)
+    KappaRTA.apply(Rates.apply(m3, m4, path, T), path, T).sum().backward()
+    gm3, gm4 = m3.grad.cpu().numpy(), m4.grad.cpu().numpy()
+    path.precision = fp.FP_FP64
     phi3 = path.phi3.clone().requires_grad_(True)
     phi4 = path.phi4.clone().requires_grad_(True)
     kap = KappaRTA.apply(Rates.apply(phi3, phi4, path, T), path, T)
@@ -152,6 +181,7 @@ def test_kappa_gradient_against_central_differences(ctx):
     gmax = max(np.abs(g3).max(), np.abs(g4).max())
     ulp = np.spacing(k0)
     worst = {1e-6: 0.0, 1e-4: 0.0}
+    worst_mixed = 0.0
     for n in range(64):
         order = 3 if n % 2 == 0 else 4
         base = phi3.detach() if order == 3 else phi4.detach()
@@ -169,6 +199,12 @@ def test_kappa_gradient_against_central_differences(ctx):
             bound = 1e-6 if h == 1e-4 else max(1e-6, 8 * ulp / (2 * h) / scale)
             assert rel <= bound, (n, order, t, k, h, g, fd, rel, bound)
             worst[h] = max(worst[h], rel)
+            if h == 1e-4:
+                gmix = (gm3 if order == 3 else gm4)[t, k]
+                worst_mixed = max(worst_mixed, abs(gmix - fd) / scale)
     say(f"kappa gradient vs central differences, worst relative error: h=1e-6 {worst[1e-6]:.2e}, "
         f"h=1e-4 {worst[1e-4]:.2e} over 64 components")
     assert worst[1e-4] <= 1e-6
+    say(f"mixed-precision kappa gradient vs the same central differences (h=1e-4): worst relative error "
+        f"{worst_mixed:.2e}")
+    assert worst_mixed <= 1e-4

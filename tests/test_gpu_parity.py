@@ -105,7 +105,7 @@ def test_fcc4_three_phonon(ctx):
         assert np.all(g[:, inactive] == 0.0)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("mesh,sigma,stride", [(4, None, 5), (4, 10.0, 17), (3, 4.0, 3)])
 def test_four_phonon_small(ctx, mesh, sigma, stride, variant):
     cfg = small_config(mesh)
@@ -126,7 +126,7 @@ def test_launch_knobs_do_not_change_results(ctx):
     lists = oracle_lists(cfg, (fp.FP_4PM, fp.FP_4MM), rows, 6.0)
     go, _ = oracle_mode_rates(cfg, lists, [300.0], 6.0)
     ref = None
-    for variant, ppl, bpc in ((0, 1, 1), (0, 2, 0), (1, 3, 1), (2, 3, 0), (3, 8, 2), (2, 64, 1), (4, 5, 1), (4, 1, 0), (5, 3, 0), (5, 1, 1), (1, 2, 0)):
+    for variant, ppl, bpc in ((0, 1, 1), (0, 2, 0), (1, 3, 1), (2, 3, 0), (3, 8, 2), (2, 64, 1), (4, 5, 1), (4, 1, 0), (5, 3, 0), (5, 1, 1), (7, 2, 0), (1, 2, 0)):
         g, _ = gpu_rates(ctx, cfg, lists, [300.0], sigma=6.0,
                          knobs={"variant": variant, "ppl": ppl, "blocks_per_cu": bpc})
         assert_parity(g, go, f"variant={variant} ppl={ppl} blocks/CU={bpc}")
