@@ -306,8 +306,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
                                                      const double2* __restrict__ hbuf, double* __restrict__ gpart,
                                                      int* __restrict__ flag, GradArgs a) {
     extern __shared__ double2 sroots[];  // L roots of unity (dynamic: sized by the launch)
-    __shared__ double2 sE[kWavesPerBlock][kWave][9];  // x(ab), y(ac), z(ad) per record
-    __shared__ double2 sH[kWavesPerBlock][kWave];
+    __shared__ double2 sU[kWavesPerBlock][kWave][3];  // h x_b per record
+    __shared__ double2 sW[kWavesPerBlock][kWave][9];  // y_g z_d per record
     __shared__ int32_t sT[kWavesPerBlock][kWave + 1];  // first record of each tuple, then the end
     __shared__ int32_t sQ[kWavesPerBlock][kWave][2];
     for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
@@ -321,8 +321,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
     const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wave;  // this wave's partial
     const int64_t n_waves = (int64_t)gridDim.x * kWavesPerBlock;
     double* __restrict__ mypart = gpart + gw * a.n_terms * 81;
-    double2(*E)[9] = sE[wave];
-    double2* H = sH[wave];
+    double2(*U)[3] = sU[wave];
+    double2(*W)[9] = sW[wave];
     int32_t* T = sT[wave];
     int32_t(*Qs)[2] = sQ[wave];
     const int64_t n_items = a.n_units * a.n_groups;
@@ -380,18 +380,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
                 Qs[slot][1] = pr.Q20 | (pr.Q21 << 10) | (pr.Q22 << 20);
             }
             if (lane == 0) T[n_tup] = n_here;
-            // h_p and the group's partner eigenvector components of this lane's record
-            H[lane] = have ? hbuf[ri.hbase + ud.start + idx] : make_double2(0.0, 0.0);
+            // this lane's record: h_p x_b and y_g z_d for the group's partner atoms
             {
+                const double2 h = have ? hbuf[ri.hbase + ud.start + idx] : make_double2(0.0, 0.0);
                 const double2* e1 = evec + (int64_t)pr.g1 * nb + 3 * ab;
                 const double2* e2 = evec + (int64_t)pr.g2 * nb + 3 * ac;
                 const double2* e3 = evec + (int64_t)pr.gl * nb + 3 * ad;
+                double2 y[3], z[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    E[lane][q] = ld_eps(e1 + q, c1);
-                    E[lane][3 + q] = ld_eps(e2 + q, c2);
-                    E[lane][6 + q] = ld_eps(e3 + q, c3);
+                    U[lane][q] = cmul(h, ld_eps(e1 + q, c1));
+                    y[q] = ld_eps(e2 + q, c2);
+                    z[q] = ld_eps(e3 + q, c3);
                 }
+#pragma unroll
+                for (int g = 0; g < 3; ++g)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) W[lane][g * 3 + d] = cmul(y[g], z[d]);
             }
             lds_fence();
             const int n_ks = (n_tup + 3) >> 2;
@@ -419,11 +424,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
                     const int c = mt * 16 + li;
                     double2 B = make_double2(0.0, 0.0);
                     if (c < 27) {
-                        const int b = c / 9, g = (c / 3) % 3, d = c % 3;
-                        for (int r = r0; r < r1; ++r) {
-                            const double2 P = cmul(cmul(E[r][b], E[r][3 + g]), E[r][6 + d]);
-                            B = cfma(B, H[r], P);
-                        }
+                        const int b = c / 9, gd = c % 9;
+                        for (int r = r0; r < r1; ++r) B = cfma(B, U[r][b], W[r][gd]);
                     }
                     // G += ph B (Karatsuba: k1 = (Ar + Ai) Br, k2 = Ar (Bi - Br), k3 = Ai (Br + Bi))
                     k1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pd_s, B.x, k1[mt], 0, 0, 0);
