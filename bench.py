@@ -231,9 +231,9 @@ def main():
     f_build = 216 * n4 * n_tup                      # tuple form: phase-weighted constants, 216 n4 per tuple
     f_contract = (312 * n_groups + 60) * n_proc4    # tuple form: 39 complex MACs per group, + weights
     sec = kern_ms * 1e-3
-    if variant == 4:
+    if variant >= 4:
         roof = {"bound": "mfma", "achieved": f_build / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "kernel": "k_rates4b (tuple-batched, FP64 MFMA + FP64 VALU)",
+                "kernel": f"k_rates4b variant {variant} (tuple-batched, FP64 MFMA + FP64 VALU)",
                 "work": f"216*n4 FLOP per (lambda, q', q'') tuple on FP64 MFMA, n4 = {n4}, {n_tup} tuples",
                 "valu_achieved": f_contract / sec / 1e12}
     else:
