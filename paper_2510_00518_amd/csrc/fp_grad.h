@@ -17,7 +17,8 @@
 // chunk; at the end of a chunk it folds them with e_lambda and exp(i q.C_t)
 // into its own partial dPhi, written by exactly one lane per entry, so the
 // result does not depend on timing.  A final kernel sums the block partials in
-// block order.
+// block order.  k_grad serves order 3 (short lists); order 4 uses the two-pass
+// tuple form below (k_rates4b in its GRAD mode, then k_grad4t).
 #pragma once
 
 namespace fpk {
@@ -109,13 +110,10 @@ struct GradArgs {
         const double2* __restrict__ roots, const double2* __restrict__ phit, const int32_t* __restrict__ tmeta,    \
         const int32_t* __restrict__ tc, const int32_t* __restrict__ groups, const int32_t* __restrict__ pairs,   \
         const double* __restrict__ tscale, const RowInfo* __restrict__ rows, const UnitDesc* __restrict__ units, \
-        const double* __restrict__ dldg, double* __restrict__ gpart, int* __restrict__ flag, GradArgs a,            \
-        const double2* __restrict__ hbuf
+        const double* __restrict__ dldg, double* __restrict__ gpart, int* __restrict__ flag, GradArgs a
 
-// HIN = true: h_p = c_p conj(V_p) comes from hbuf (written by the tuple-batched
-// kernel in its GRAD mode) instead of being recomputed here.
-template <int M, int MAXT, int MAXP, bool HIN>
-__global__ __launch_bounds__(kBlock, HIN ? 2 : 1) void k_grad(FP_GRAD_PARAMS) {
+template <int M, int MAXT, int MAXP>
+__global__ __launch_bounds__(kBlock, 1) void k_grad(FP_GRAD_PARAMS) {
     constexpr int NC = M == 3 ? 9 : 27;    // components after the mode's own index
     constexpr int NCOMP = 3 * NC;          // 3^m entries per term
     __shared__ double2 sroots[kMaxRoots];
@@ -170,9 +168,6 @@ __global__ __launch_bounds__(kBlock, HIN ? 2 : 1) void k_grad(FP_GRAD_PARAMS) {
                     const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
                     const Proc pr = setup_proc<M>(have, rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega,
                                                   a.n_modes, flag, a.inv_sigma2, a.gnorm);
-                    if (HIN) {
-                        sh_h[tid] = have ? hbuf[ri.hbase + ud.start + idx] : make_double2(0.0, 0.0);
-                    } else {
                     const double2 V = vertex_one<M>(pr, c1, c2, c3, nb, evec, phit_row, groups, a.n_groups, tmeta,
                                                     sroots, geo);
                     double cw = 0.0;
@@ -198,7 +193,6 @@ __global__ __launch_bounds__(kBlock, HIN ? 2 : 1) void k_grad(FP_GRAD_PARAMS) {
                     }
                     cw *= 2.0 * a.pref * pr.base;
                     sh_h[tid] = make_double2(cw * V.x, -cw * V.y);
-                    }
                     sh_q[tid][0] = pr.Q10 | (pr.Q11 << 10) | (pr.Q12 << 20);
                     sh_q[tid][1] = pr.Q20 | (pr.Q21 << 10) | (pr.Q22 << 20);
                     sh_g[tid][0] = pr.g1;

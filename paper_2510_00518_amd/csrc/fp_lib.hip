@@ -750,10 +750,10 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     return FP_OK;
 }
 
-template <int M, int T, int MAXP, bool HIN>
+template <int M, int T, int MAXP>
 fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
                       const double* dldg, double* dphi, bool accumulate) {
-    auto kern = fpk::k_grad<M, T, MAXP, HIN>;
+    auto kern = fpk::k_grad<M, T, MAXP>;
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
     if (occ < 1) occ = 1;
@@ -764,7 +764,7 @@ fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::
     hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(nblk * per)), dim3(256), 0, st, c->gpart.p, nblk * per, 0.0);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.tc.p, S.groups.p, S.pairs.p, S.scale.p, c->rows.p,
-                       c->units.p, dldg, c->gpart.p, c->flag, a, HIN ? c->hbuf.p : nullptr);
+                       c->units.p, dldg, c->gpart.p, c->flag, a);
     hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, nblk, S.n_terms, ncomp,
                        S.perm.p, accumulate ? 1 : 0, dphi);
     HIP_TRY(c, hipGetLastError());
@@ -797,10 +797,8 @@ fp_status launch_grad4t(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk
 template <int M, int T>
 fp_status launch_grad_p(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
                         const double* dldg, double* dphi, bool accumulate) {
-    // order 4: h_p comes from the tuple-batched pass; order 3 recomputes V in place
-    constexpr bool HIN = M == 4;
-    if (S.n_pairs <= 16) return launch_grad<M, T, 4, HIN>(c, st, pp, a, S, dldg, dphi, accumulate);
-    return launch_grad<M, T, 8, HIN>(c, st, pp, a, S, dldg, dphi, accumulate);
+    if (S.n_pairs <= 16) return launch_grad<M, T, 4>(c, st, pp, a, S, dldg, dphi, accumulate);
+    return launch_grad<M, T, 8>(c, st, pp, a, S, dldg, dphi, accumulate);
 }
 
 }  // namespace
