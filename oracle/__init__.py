@@ -26,6 +26,8 @@ class _Sys(ctypes.Structure):
         ("omega_floor", ctypes.c_double),
         ("n3", ctypes.c_int64), ("atoms3", ctypes.c_void_p), ("cells3", ctypes.c_void_p), ("phi3", ctypes.c_void_p),
         ("n4", ctypes.c_int64), ("atoms4", ctypes.c_void_p), ("cells4", ctypes.c_void_p), ("phi4", ctypes.c_void_p),
+        ("adaptive", ctypes.c_int32), ("factor", ctypes.c_double), ("vel", ctypes.c_void_p),
+        ("recip", ctypes.c_double * 9),
     ]
 
 
@@ -89,9 +91,14 @@ def gauss(delta, sigma):
 
 
 class System:
-    """The oracle's view of one workload (mesh, modes, force constants)."""
+    """The oracle's view of one workload (mesh, modes, force constants).
 
-    def __init__(self, cfg, phi3=None, phi4=None):
+    broadening: None for the fixed width of each call, or {"factor": a,
+    "recip": (3, 3) reciprocal vectors as rows} for the per-process width
+    max(a sigma0_p, sigma) from the partners' group velocities cfg["vel"].
+    """
+
+    def __init__(self, cfg, phi3=None, phi4=None, broadening=None):
         self._keep = []
 
         def arr(x, dt):
@@ -117,6 +124,13 @@ class System:
             setattr(s, f"atoms{m}", arr(ifc["atoms"], np.int32))
             setattr(s, f"cells{m}", arr(ifc["cells"], np.int32))
             setattr(s, f"phi{m}", arr(ifc["phi"] if phi is None else phi, np.float64))
+        if broadening is not None:
+            s.adaptive = 1
+            s.factor = float(broadening["factor"])
+            s.vel = arr(cfg["vel"].reshape(-1), np.float64)
+            rc = np.asarray(broadening["recip"], dtype=np.float64).reshape(9)
+            for i in range(9):
+                s.recip[i] = float(rc[i])
         self.s = s
         self.cfg = cfg
         self.nb = int(cfg["nb"])

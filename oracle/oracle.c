@@ -87,6 +87,12 @@ typedef struct {
     const int32_t* atoms4; /* [n4][4] */
     const int32_t* cells4; /* [n4][3][3] */
     const double* phi4;    /* [n4][81] */
+    /* broadening: adaptive = 0 uses the fixed sigma of each call; adaptive = 1
+     * uses sigma_p = max(factor * sigma0_p, sigma), see process_sigma */
+    int32_t adaptive;
+    double factor;
+    const double* vel;     /* [nq*nb][3] group velocities, A/ps */
+    double recip[9];       /* reciprocal vectors b_1..b_3 as rows, rad/A */
 } orc_sys;
 
 typedef struct {
@@ -326,6 +332,41 @@ static void canonical_order(int ptype, int64_t* g, double* w) {
 }
 
 /* energy mismatch evaluated left to right in the given partner order */
+/*
+ * Width of the energy-conservation Gaussian of one process (partners g[1..m-1]).
+ * Fixed: sigma.  Adaptive (the per-process width the paper computes from the
+ * partners' group velocities, Sec. 3 and Alg. 2-3): the Gaussian whose variance
+ * equals that of the mismatch when the free partner wavevectors range uniformly
+ * over one mesh cell.  Closing slot k by momentum, the mismatch moves by
+ * sum_{r != k} s_r (v_r - v_k).dq_r; a uniform dq over the cell
+ * sum_d u_d b_d / N_d (u_d in [-1/2, 1/2]) gives it variance
+ * sum_{r != k} sum_d ((v_r - v_k).b_d / N_d)^2 / 12.  Averaged over the choice of
+ * k, so that the width is symmetric in the partners, and with sigma^2 = 2 var
+ * (the Gaussian exp(-D^2/sigma^2) has variance sigma^2 / 2):
+ *   sigma0^2 = sum_{i<j partners} sum_d ((v_i - v_j).b_d / N_d)^2 / (3 (m - 1)),
+ * i.e. sum_d ((v' - v'').b_d / N_d)^2 / 6 for three phonons.  Then
+ * sigma_p = max(factor * sigma0, sigma).  Pairs (i, j) in ascending slot order,
+ * d = 0, 1, 2, each term as written, left to right.
+ */
+static double process_sigma(const orc_sys* s, int m, const int64_t* g, double sigma) {
+    if (!s->adaptive) return sigma;
+    double s2 = 0.0;
+    for (int i = 1; i < m; ++i)
+        for (int j = i + 1; j < m; ++j) {
+            const double* vi = s->vel + g[i] * 3;
+            const double* vj = s->vel + g[j] * 3;
+            double w0 = vi[0] - vj[0], w1 = vi[1] - vj[1], w2 = vi[2] - vj[2];
+            for (int d = 0; d < 3; ++d) {
+                double p = (w0 * s->recip[d * 3 + 0] + w1 * s->recip[d * 3 + 1] + w2 * s->recip[d * 3 + 2]) /
+                           (double)s->mesh[d];
+                s2 += p * p;
+            }
+        }
+    double sigma0 = sqrt(s2 / (3.0 * (double)(m - 1)));
+    double sp = s->factor * sigma0;
+    return sp > sigma ? sp : sigma;
+}
+
 static double mismatch(int m, const int32_t* sg, const double* w) {
     double d = w[0];
     for (int r = 1; r < m; ++r) d = sg[r] > 0 ? d + w[r] : d - w[r];
@@ -349,7 +390,7 @@ typedef struct {
     const orc_sys* s;
     int ptype, m, n_T;
     const double* T;
-    double sigma, cut;
+    double sigma, nsigma;
     int32_t sg[4];
 } proc_ctx;
 
@@ -370,8 +411,9 @@ static int process(const proc_ctx* pc, int64_t qc[4][3], const int32_t br[4], do
     memcpy(ws, w, sizeof w);
     if (filter) canonical_order(pc->ptype, gs, ws);
     double delta = mismatch(m, pc->sg, ws);
-    if (filter && !(fabs(delta) <= pc->cut)) return 0;
-    double G = orc_gauss(delta, pc->sigma);
+    double sp = process_sigma(s, m, gs, pc->sigma);
+    if (filter && !(fabs(delta) <= pc->nsigma * sp)) return 0;
+    double G = orc_gauss(delta, sp);
     double wprod = 1.0;
     for (int r = 0; r < m; ++r) wprod *= w[r];
     int64_t sq[4][3];
@@ -422,7 +464,7 @@ int orc_rates(const orc_sys* s, int ptype, int mode, int64_t n_rows, const int32
     pc.n_T = n_T;
     pc.T = T;
     pc.sigma = sigma;
-    pc.cut = nsigma * sigma;
+    pc.nsigma = nsigma;
     type_signs(ptype, pc.sg);
     double pre = prefactor(m, N), wpre = wp_prefactor(m, N);
     for (int64_t row = 0; row < n_rows; ++row) {
@@ -599,7 +641,7 @@ int orc_grad(const orc_sys* s, int ptype, int64_t n_rows, const int32_t* row_mod
             for (int k = 1; k < m; ++k) g[k] = q_index(s, qc[k]) * nb + br[k];
             for (int k = 0; k < m; ++k) w[k] = s->omega[g[k]];
             double delta = mismatch(m, sg, w);
-            double G = orc_gauss(delta, sigma);
+            double G = orc_gauss(delta, process_sigma(s, m, g, sigma));
             double wprod = 1.0;
             for (int k = 0; k < m; ++k) wprod *= w[k];
             double base = triangle_weight(ptype, g) * G / wprod;
@@ -659,7 +701,6 @@ int64_t orc_enumerate(const orc_sys* s, int ptype, int32_t row_mode, double sigm
     int64_t N = n_q(s);
     int32_t sg[4];
     type_signs(ptype, sg);
-    double cut = nsigma * sigma;
     int64_t count = 0;
     int64_t qc[4][3];
     int32_t br[4];
@@ -693,7 +734,7 @@ int64_t orc_enumerate(const orc_sys* s, int ptype, int32_t row_mode, double sigm
                 canonical_order(ptype, gs, ws);
                 if (memcmp(gs, g, sizeof(int64_t) * m) != 0) continue; /* not the canonical ordering */
                 double delta = mismatch(m, sg, ws);
-                if (!(fabs(delta) <= cut)) continue;
+                if (!(fabs(delta) <= nsigma * process_sigma(s, m, gs, sigma))) continue;
                 uint64_t r = (uint64_t)g[1];
                 if (m == 3)
                     r |= (uint64_t)br[2] << 24;

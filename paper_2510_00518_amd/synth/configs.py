@@ -62,7 +62,7 @@ def _cell(kind):
 def _harmonic(kind, mesh):
     cell = _cell(kind)
     fc2 = spring_fc2(cell, springs())
-    return phonons(cell, fc2, (mesh, mesh, mesh))
+    return phonons(cell, fc2, (mesh, mesh, mesh) if isinstance(mesh, int) else mesh)
 
 
 @functools.lru_cache(maxsize=None)
@@ -93,7 +93,7 @@ def make_config(name):
     cfg = dict(
         name=name, description=DESCRIPTION[name], mesh=np.array(mesh, dtype=np.int32),
         n_atoms=cell.n_at, nb=cell.nb, lattice=cell.lattice.copy(), masses=cell.masses.copy(),
-        volume=cell.volume, omega=omega, evec=evec, vel=vel, q1=q1, q1_weight=w,
+        volume=cell.volume, recip=cell.recip.copy(), omega=omega, evec=evec, vel=vel, q1=q1, q1_weight=w,
         sigma=SIGMA, nsigma=NSIGMA, omega_floor=OMEGA_FLOOR, T=np.array(s["T"]),
         ifc3=_ifc(s["cell"], 3, s["n3"]), ifc4=_ifc(s["cell"], 4, s["n4"]),
     )
@@ -103,13 +103,16 @@ def make_config(name):
 
 
 def small_config(mesh, n3=32, n4=96, cell="prim", T=(300.0,)):
-    """Same recipe as the named workloads on a small mesh, every q1 with weight 1."""
+    """Same recipe as the named workloads on a small mesh (N or (N0, N1, N2)),
+    every q1 with weight 1."""
     c = _cell(cell)
-    omega, evec, vel = _harmonic(cell, int(mesh))
+    m3 = (int(mesh),) * 3 if np.isscalar(mesh) else tuple(int(x) for x in mesh)
+    omega, evec, vel = _harmonic(cell, m3)
     nq = omega.shape[0]
     return dict(
-        name=f"small{mesh}", description=f"{cell} cell, {mesh}^3 mesh", mesh=np.array((mesh,) * 3, dtype=np.int32),
-        n_atoms=c.n_at, nb=c.nb, lattice=c.lattice.copy(), masses=c.masses.copy(), volume=c.volume,
+        name=f"small{m3[0]}x{m3[1]}x{m3[2]}", description=f"{cell} cell, {m3[0]}x{m3[1]}x{m3[2]} mesh",
+        mesh=np.array(m3, dtype=np.int32),
+        n_atoms=c.n_at, nb=c.nb, lattice=c.lattice.copy(), masses=c.masses.copy(), volume=c.volume, recip=c.recip.copy(),
         omega=omega, evec=evec, vel=vel, q1=np.arange(nq, dtype=np.int32), q1_weight=np.ones(nq),
         sigma=SIGMA, nsigma=NSIGMA, omega_floor=OMEGA_FLOOR, T=np.array(T),
         ifc3=_ifc(cell, 3, n3), ifc4=_ifc(cell, 4, n4),

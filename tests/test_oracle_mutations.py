@@ -38,8 +38,19 @@ MUTATIONS = {
                                        "return 1.0 / exp(c_hbar() * omega / (c_kb() * T));"),
     "momentum closed with wrong sign": ("qc[m - 1][d] = wrap(sg[m - 1] * (-Q), s->mesh[d]);",
                                         "qc[m - 1][d] = wrap(sg[m - 1] * Q, s->mesh[d]);"),
-    "filter with strict bound on wrong side": ("if (filter && !(fabs(delta) <= pc->cut)) return 0;",
-                                               "if (filter && !(fabs(delta) <= 2.0 * pc->cut)) return 0;"),
+    "filter with strict bound on wrong side": ("if (filter && !(fabs(delta) <= pc->nsigma * sp)) return 0;",
+                                               "if (filter && !(fabs(delta) <= 2.0 * pc->nsigma * sp)) return 0;"),
+    "adaptive width with the variance, not 2 var": ("double sigma0 = sqrt(s2 / (3.0 * (double)(m - 1)));",
+                                                    "double sigma0 = sqrt(s2 / (6.0 * (double)(m - 1)));"),
+    "adaptive width with reciprocal vectors transposed": (
+        "double p = (w0 * s->recip[d * 3 + 0] + w1 * s->recip[d * 3 + 1] + w2 * s->recip[d * 3 + 2]) /",
+        "double p = (w0 * s->recip[0 * 3 + d] + w1 * s->recip[1 * 3 + d] + w2 * s->recip[2 * 3 + d]) /"),
+    "adaptive width divided by the wrong mesh axis": ("                           (double)s->mesh[d];",
+                                                      "                           (double)s->mesh[2 - d];"),
+    "adaptive four-phonon width from one partner pair": (
+        "        for (int j = i + 1; j < m; ++j) {\n            const double* vi",
+        "        for (int j = i + 1; j < (i == 1 ? m : 0); ++j) {\n            const double* vi"),
+    "adaptive width taken before the floor": ("    return sp > sigma ? sp : sigma;", "    return sp;"),
 }
 
 

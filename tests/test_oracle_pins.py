@@ -479,3 +479,151 @@ def test_gradient_euler_identity(ptype):
     g, _, _, _ = S.rates(ptype, rows, T, 2.0, row_off=off, rec=rec)
     L = np.sum(dLdG * g)
     assert np.sum(cfg[key]["phi"] * grad) == pytest.approx(2 * L, rel=1e-11)
+
+
+# ------------------------------------------------------ adaptive broadening
+#
+# Reading of the per-process width (Sec. 3, the compute_sigma(v' - v'') step of
+# Alg. 2-3): the Gaussian whose variance equals that of the energy mismatch when
+# the free partner wavevectors range uniformly over one mesh cell, to first order
+# in the displacement, averaged over which partner momentum conservation closes;
+# sigma_p = max(factor * sigma0, sigma).  The pins below take that definition by
+# quadrature, independently of the oracle's closed form.
+
+_ANISO = (2, 3, 4)
+
+
+def _tilted_recip(cfg):
+    """Reciprocal vectors (rows) with no symmetry, so a transposed or permuted use fails."""
+    rng = np.random.default_rng(99)
+    return cfg["recip"] + rng.uniform(-0.3, 0.3, size=(3, 3))
+
+
+def _full_modes(ptype, g0, r, cfg):
+    """All m global modes of record r of row g0, closing the last by momentum here."""
+    nb = cfg["nb"]
+    mesh3 = np.asarray(cfg["mesh"])
+    coords = mesh_coords(mesh3)
+    sg = oracle.SIGNS[ptype]
+    r = int(r)
+    g = [int(g0), r & 0xFFFFFF]
+    if oracle.ORDER[ptype] == 4:
+        g.append((r >> 24) & 0xFFFFFF)
+        jl = (r >> 48) & 0xFF
+    else:
+        jl = (r >> 24) & 0xFF
+    Q = sum(sg[k] * coords[g[k] // nb] for k in range(len(g)))
+    ql = np.mod(sg[-1] * (-Q), mesh3)
+    g.append(int((ql[0] * mesh3[1] + ql[1]) * mesh3[2] + ql[2]) * nb + jl)
+    return g
+
+
+def _width_by_quadrature(ptype, g, cfg, recip, factor):
+    """factor * sqrt(2 var): var of the linearised mismatch under uniform cell
+    displacements of the free partners, by tensor Gauss-Legendre quadrature
+    (exact for this quadratic integrand), averaged over the closing partner."""
+    sg = oracle.SIGNS[ptype]
+    v = cfg["vel"].reshape(-1, 3)
+    mesh3 = np.asarray(cfg["mesh"], dtype=float)
+    x, wx = np.polynomial.legendre.leggauss(2)
+    u1, w1 = x / 2.0, wx / 2.0                      # nodes and weights on [-1/2, 1/2]
+    partners = list(range(1, len(g)))
+    variances = []
+    for k in partners:
+        free = [r for r in partners if r != k]
+        nvar = 3 * len(free)
+        ev = 0.0
+        for idx in itertools.product(range(2), repeat=nvar):
+            wgt = np.prod([w1[i] for i in idx])
+            X = 0.0
+            for a, r in enumerate(free):
+                dq = sum(u1[idx[3 * a + d]] * recip[d] / mesh3[d] for d in range(3))
+                X += sg[r] * np.dot(v[g[r]] - v[g[k]], dq)
+            ev += wgt * X * X
+        variances.append(ev)
+    return factor * np.sqrt(2.0 * np.mean(variances))
+
+
+@pytest.fixture(scope="module")
+def aniso():
+    cfg = small_config(_ANISO)
+    return cfg, _tilted_recip(cfg)
+
+
+def _single_record_rate(S, ptype, g0, r, sigma):
+    g, wp, _, _ = S.rates(ptype, [g0], [300.0], sigma, row_off=np.array([0, 1]), rec=np.array([r], np.uint64))
+    return g[0, 0], wp[0, 0]
+
+
+@pytest.mark.parametrize("ptype", [T3P, T3M, T4PP, T4PM, T4MM])
+def test_adaptive_width_equals_mismatch_spread(ptype, aniso):
+    """Each listed process evaluated with adaptive broadening equals the same
+    process at a fixed width equal to the quadrature value of its spread."""
+    cfg, recip = aniso
+    factor = 0.7
+    floor = 1e-6
+    Sa = oracle.System(cfg, broadening={"factor": factor, "recip": recip})
+    S = oracle.System(cfg)
+    rows = row_modes(cfg)[::5]
+    checked = 0
+    for g0 in rows:
+        recs = S.enumerate_row(ptype, int(g0), 10.0)
+        for r in recs[:: max(1, len(recs) // 4)]:
+            g = _full_modes(ptype, g0, r, cfg)
+            want = max(_width_by_quadrature(ptype, g, cfg, recip, factor), floor)
+            ga, wa = _single_record_rate(Sa, ptype, int(g0), r, floor)
+            gf, wf = _single_record_rate(S, ptype, int(g0), r, want)
+            assert wa == pytest.approx(wf, rel=1e-11, abs=1e-300)
+            assert ga == pytest.approx(gf, rel=1e-11, abs=1e-300)
+            checked += 1
+    assert checked >= 10
+
+
+def test_adaptive_floor_and_velocity_shift(aniso):
+    """A negligible factor leaves the fixed width (the floor) exactly; adding one
+    velocity to every mode changes no width."""
+    cfg, recip = aniso
+    rows = row_modes(cfg)[::3]
+    sig = 0.6283185307179586
+    S = oracle.System(cfg)
+    Sa = oracle.System(cfg, broadening={"factor": 1e-30, "recip": recip})
+    shifted = dict(cfg, vel=cfg["vel"] + np.array([3.25, -1.5, 0.75]))
+    Sb = oracle.System(cfg, broadening={"factor": 0.5, "recip": recip})
+    Ss = oracle.System(shifted, broadening={"factor": 0.5, "recip": recip})
+    for pt in (T3M, T4PM):
+        g0, w0, k0, _ = S.rates(pt, rows, 300.0, sig)
+        ga, wa, ka, _ = Sa.rates(pt, rows, 300.0, sig)
+        np.testing.assert_array_equal(ga, g0)
+        np.testing.assert_array_equal(ka, k0)
+        gb, _, kb, _ = Sb.rates(pt, rows, 300.0, 0.05)
+        gs, _, ks, _ = Ss.rates(pt, rows, 300.0, 0.05)
+        np.testing.assert_array_equal(kb, ks)
+        np.testing.assert_allclose(gs, gb, rtol=1e-9, atol=1e-12 * gb.max())
+        assert kb.sum() != k0.sum()
+
+
+@pytest.mark.parametrize("ptype", [T3P, T3M, T4PP, T4PM, T4MM])
+def test_adaptive_enumeration_and_triangle_sums(ptype, aniso):
+    """Every enumerated record passes |Delta| <= nsigma * sigma_p with sigma_p from
+    quadrature; brute-force ordered sums equal the triangle-reduced list sums."""
+    cfg, recip = aniso
+    factor, floor = 0.5, 0.05
+    Sa = oracle.System(cfg, broadening={"factor": factor, "recip": recip})
+    rows = row_modes(cfg)[::7]
+    om = cfg["omega"].reshape(-1)
+    sg = oracle.SIGNS[ptype]
+    recs = [Sa.enumerate_row(ptype, int(g0), floor) for g0 in rows]
+    for g0, rr in zip(rows, recs):
+        for r in rr[:: max(1, len(rr) // 12)]:
+            g = _full_modes(ptype, g0, r, cfg)
+            sp = max(_width_by_quadrature(ptype, g, cfg, recip, factor), floor)
+            delta = om[g[0]] + sum(sg[k] * om[g[k]] for k in range(1, len(g)))
+            assert abs(delta) <= 3.0 * sp * (1 + 1e-12)
+    off = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
+    assert off[-1] > 0
+    rec = np.concatenate(recs).astype(np.uint64)
+    T = [300.0, 700.0]
+    gb, wb, _, _ = Sa.rates(ptype, rows, T, floor)
+    gl, wl, _, _ = Sa.rates(ptype, rows, T, floor, row_off=off, rec=rec)
+    np.testing.assert_allclose(gl, gb, rtol=1e-12, atol=1e-12 * gb.max())
+    np.testing.assert_allclose(wl, wb, rtol=1e-12, atol=1e-300)
