@@ -15,6 +15,9 @@ on its own stream, with the algorithmic FLOP of the form that ran: (320 n4 + 60)
 per process for the per-process forms; 216 n4 per (lambda, q', q'') tuple on
 FP64 MFMA (and 312 n_groups + 60 per process on the VALU) for the tuple-batched
 form.  backward: kappa_RTA with dkappa/dGamma and the adjoint of both orders.
+adaptive: the same step with the per-process width sigma_p = max(0.1 sigma0_p,
+0.01 THz) from the group velocities (the paper's broadening scale 0.1) on lists
+the host enumerates with that width.
 cpu_baseline: the FP64 oracle (list mode) on a bounded sample of the same lists
 on this host's cores.  --paper-scale adds the 16x16x16 two-atom cell (every row,
 three types, T = 300/600/900 K) through GPU-side enumeration; it holds the GPU
@@ -168,6 +171,7 @@ def main():
                     help="also run a 1 GiB device copy (reference kernel for HBM counter scaling)")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--paper-scale", action="store_true",
                     help="also run the 16^3 two-atom cell through GPU-side enumeration (about a minute)")
     ap.add_argument("--ppl", type=int, default=None)
@@ -183,7 +187,7 @@ def main():
 
     from paper_2510_00518_amd import fp
     from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists
-    from paper_2510_00518_amd.synth import make_config
+    from paper_2510_00518_amd.synth import ADAPTIVE_FACTOR, SIGMA_FLOOR, adaptive_broadening, make_config
 
     if not os.path.exists(fp.LIB_PATH):
         from __graft_entry__ import build
@@ -310,6 +314,32 @@ def main():
                "step": "kappa_RTA with dkappa/dGamma + adjoint of the 3ph and 4ph rates (V recomputed)"}
         log(f"bench: backward {ms_bwd:.3f} ms/step, ratio {ms_bwd / ms_step:.2f}")
 
+    # ---- adaptive broadening: per-process width, lists enumerated with it
+    adaptive = None
+    if not args.no_adaptive:
+        b = adaptive_broadening(cfg)
+        log("bench: enumerating adaptive-width lists on the host")
+        t0 = time.perf_counter()
+        lists_a = host_lists(cfg, TYPES3 + TYPES4, sigma=SIGMA_FLOOR, broadening=b)
+        t_enum_a = time.perf_counter() - t0
+        path_a = RatePath(dict(cfg, sigma=SIGMA_FLOOR), device=0)
+        if args.variant is not None:
+            fp.fp_set_knob(path_a.ctx, "variant", args.variant)
+        path_a.set_broadening(b)
+        path_a.set_lists(lists_a)
+        del lists_a
+        ms_a, kern_a, gam_a, kap_a = run_forward(path_a, T, args.steps, 1, 4, torch, fp)
+        adaptive = {
+            "value": path_a.n_proc4 / (ms_a * 1e-3), "unit": "processes/s", "ms_per_step": ms_a,
+            "processes_4ph": path_a.n_proc4, "processes_3ph": path_a.n_proc3, "kernel_ms": kern_a,
+            "ns_per_process_kernel": kern_a * 1e6 / path_a.n_proc4,
+            "ns_per_process_kernel_fixed_width": kern_ms * 1e6 / n_proc4,
+            "factor": ADAPTIVE_FACTOR, "floor_rad_per_ps": SIGMA_FLOOR, "host_enumeration_s": round(t_enum_a, 2),
+            "kappa_finite": bool(np.all(np.isfinite(kap_a.cpu().numpy()))),
+        }
+        path_a.close()
+        log(f"bench: adaptive {ms_a:.3f} ms/step, {path_a.n_proc4} 4ph processes, kernel {kern_a:.3f} ms")
+
     out = {
         "metric": "4ph processes/sec at 1 GPU, FP64 vs mixed (rel err vs oracle); bwd/fwd time ratio",
         "value": n_proc4 / (ms_step * 1e-3),
@@ -340,6 +370,7 @@ def main():
         "mixed": mixed,
         "bwd_fwd_ratio": None if bwd is None else bwd["bwd_fwd_ratio"],
         "backward": bwd,
+        "adaptive": adaptive,
     }
     if args.paper_scale:
         out["paper_scale"] = paper_scale(torch, fp, RatePath)

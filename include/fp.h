@@ -44,7 +44,8 @@
  * 4ph: pi hbar^2/(8N^2), weights 1/2, 1/2, 1/6; N = N0*N1*N2):
  *   Gamma_lambda = pref sum_records w |V|^2 occ G(Delta) / prod(omega)
  *   WP_lambda    = (1/N or 1/N^2) sum_records w occ G(Delta) / prod(omega)
- *   G(D) = exp(-D^2/sigma^2)/(sigma sqrt(pi))  (Algorithm 1, WP)
+ *   G(D) = exp(-D^2/sigma^2)/(sigma sqrt(pi))  (Algorithm 1, WP); sigma is the
+ *        call's width, or the per-process width of fp_broadening
  *   occ: 3+ n'-n''; 3- 1+n'+n''; ++ n'n''(1+n''')-(1+n')(1+n'')n''';
  *        +- n'(1+n'')(1+n''')-(1+n')n''n'''; -- (1+n')(1+n'')(1+n''')-n'n''n'''
  *   n = 1/expm1(hbar omega / kB T)
@@ -93,6 +94,32 @@ typedef enum { FP_3P = 0, FP_3M = 1, FP_4PP = 2, FP_4PM = 3, FP_4MM = 4 } fp_pty
 #define FP_MAX_T 8
 #define FP_MAX_LISTS 8
 
+/* Width of the Gaussian delta (the broadening step of Algorithms 1-4, whose
+ * formula the paper names but does not print).
+ *   adaptive = 0: every process takes the width `sigma` of the call.
+ *   adaptive = 1: process p takes sigma_p = max(factor * sigma0_p, sigma), with
+ *     sigma0_p^2 = sum over partner pairs i < j of
+ *                  sum_d ((v_i - v_j) . b_d / N_d)^2 / (3 (m - 1))
+ *     over the m - 1 partners of the process (m = 3 or 4), v their group
+ *     velocities (Angstrom/ps) and b_d the reciprocal vectors (rad/Angstrom,
+ *     recip[3d .. 3d+2] = b_d).  For three phonons this is
+ *     sum_d ((v' - v'').b_d/N_d)^2 / 6: the Gaussian whose variance equals that
+ *     of the energy mismatch when the free partner wavevector ranges uniformly
+ *     over one mesh cell; four phonons average that over the choice of the
+ *     momentum-closed partner, so sigma_p is symmetric in the partners and the
+ *     triangle reduction stays exact.  `sigma` of each call is the floor that
+ *     keeps sigma_p > 0 where the partner velocities coincide.
+ * The host enumerator evaluates sigma_p in double precision, pairs in
+ * ascending slot order (record order), d = 0, 1, 2, each projection as
+ * ((v_i - v_j) . b_d) / N_d, left to right without contraction, so its
+ * filter decision is reproducible. */
+typedef struct {
+    int32_t adaptive;
+    int32_t reserved;
+    double factor;   /* > 0 */
+    double recip[9]; /* b_1, b_2, b_3 as rows */
+} fp_broadening;
+
 /* Create a context on HIP device `device`; *out receives it.  Allocates the
  * context's small device buffers.  FP_ERR_ARG if out is NULL, FP_ERR_HIP if the
  * device cannot be used. */
@@ -113,9 +140,10 @@ const char* fp_last_error(const fp_ctx* ctx);
  *   masses       [n_atoms] amu, > 0
  *   omega        [N*nb] rad/ps, finite and >= 0
  *   evec         [N*nb*nb] complex as 2*N*nb*nb doubles
- *   vel          [N*nb*3] group velocities in Angstrom/ps (used only by
- *                fp_kappa_rta; may be NULL)
+ *   vel          [N*nb*3] group velocities in Angstrom/ps (used by
+ *                fp_kappa_rta and adaptive broadening; may be NULL)
  *   omega_floor  modes below it are inactive (rad/ps); lists must not use them
+ * Resets the broadening to the fixed width (fp_set_broadening).
  * FP_ERR_ARG on NULL/invalid values, FP_ERR_UNSUPPORTED beyond the limits. */
 fp_status fp_load_modes(fp_ctx* ctx, const int32_t mesh[3], int32_t n_atoms, const double lattice[9],
                         const double* masses, const double* omega, const double* evec, const double* vel,
@@ -131,6 +159,15 @@ fp_status fp_load_modes(fp_ctx* ctx, const int32_t mesh[3], int32_t n_atoms, con
  * fp_load_modes first (FP_ERR_STATE).  FP_ERR_ARG on atoms/cells out of range. */
 fp_status fp_load_ifc(fp_ctx* ctx, int32_t order, int64_t n_terms, const int32_t* atoms, const int32_t* cells,
                       const double* phi, int32_t phi_on_device, void* hip_stream);
+
+/* Broadening of the rate, adjoint and autotune calls that follow (see
+ * fp_broadening); NULL or adaptive = 0 selects the fixed width of each call.
+ * The context keeps the per-mode projections v . b_d / N_d on the device
+ * (computed here by a kernel, synchronously).  Requires fp_load_modes with
+ * velocities (FP_ERR_STATE).  FP_ERR_ARG for factor <= 0, a non-finite
+ * reciprocal vector or adaptive outside {0, 1}.  fp_rates4_fused supports only
+ * the fixed width (FP_ERR_UNSUPPORTED while adaptive is set). */
+fp_status fp_set_broadening(fp_ctx* ctx, const fp_broadening* broadening);
 
 /* One CSR process list: the rows are modes lambda (the paper's mm loop), the
  * records of row r are rec[row_off[r] .. row_off[r+1]) (N_accum/Ind2/Ind3 of
@@ -187,6 +224,42 @@ fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t
 fp_status fp_rates4_fused(fp_ctx* ctx, int64_t n_rows, const int32_t* row_mode, int32_t type_mask, int32_t n_T,
                           const double* T_K, double sigma, double nsigma, int32_t precision, double* gamma_out,
                           double* wp_out, int64_t* n_kept, void* hip_stream);
+
+/* Figures of one fp_rates_streamed call (host wall-clock milliseconds). */
+typedef struct {
+    int64_t n_records;  /* records evaluated, all selected types */
+    int64_t n_chunks;   /* staged chunks */
+    int64_t max_chunk;  /* records of the largest chunk */
+    double count_ms;    /* host counting pass */
+    double fill_ms;     /* host enumeration into the staging slots, summed */
+    double wait_ms;     /* host time blocked on the GPU (slot reuse, final wait) */
+    double total_ms;    /* the whole call */
+} fp_stream_stats;
+
+/* Rates over lists that never exist whole: the memory-bounded fallback of the
+ * paper's mode-wise variant (Appendix, the mode-wise form of Algorithm 4;
+ * Results, where the all-modes lists outgrow device memory), generalised from
+ * one mode at a time to chunks of records.  The library enumerates, on host
+ * threads and with the rules of fp_enumerate_fill (keep_fraction 1, and the
+ * context's broadening), every (type, row) for the types in type_mask (bit t
+ * selects fp_ptype t, 1..31) and the modes of row_mode (HOST int32 [n_rows],
+ * distinct); it cuts the concatenated record sequence (types ascending, rows in
+ * the given order) into chunks of at most chunk_records and evaluates each with
+ * the fp_rates3/fp_rates4 launches, accumulating into the outputs.  Two pinned
+ * staging slots of chunk_records records (8 bytes each) and their device
+ * copies are owned by the context; the host enumerates one chunk while the GPU
+ * copies and evaluates the previous one.  A row longer than a chunk is split
+ * across chunks.  The result equals fp_rates3 + fp_rates4 over the full lists
+ * up to the grouping of the sums.  Outputs, precision (FP_FP64 or FP_MIXED,
+ * optionally | FP_ACCUMULATE), T and sigma are as in fp_rates4; nsigma as in
+ * fp_enumerate_count; n_threads <= 0 uses every hardware thread.  stats (host,
+ * may be NULL) receives the call's figures.  Requires the force constants of
+ * every selected order.  Synchronous: returns when the GPU work on
+ * `hip_stream` has finished. */
+fp_status fp_rates_streamed(fp_ctx* ctx, int32_t type_mask, int64_t n_rows, const int32_t* row_mode, int32_t n_T,
+                            const double* T_K, double sigma, double nsigma, int32_t precision,
+                            int64_t chunk_records, int32_t n_threads, double* gamma_out, double* wp_out,
+                            fp_stream_stats* stats, void* hip_stream);
 
 /* Adjoint of the rates (vector-Jacobian product): given dL/dGamma, a DEVICE
  * array [n_T][N*nb], write dL/dPhi for the raw force-constant entries,
@@ -281,7 +354,10 @@ fp_status fp_check(fp_ctx* ctx, void* hip_stream);
  * A candidate is kept iff every mode has omega >= omega_floor, its
  * interchangeable partners are in ascending g order (triangle reduction) and
  * |Delta| <= nsigma*sigma, with Delta evaluated in double precision left to
- * right in record order (((w + s'w') + s''w'') + s'''w''').  Within a row the
+ * right in record order (((w + s'w') + s''w'') + s'''w''') and sigma the
+ * call's width, or with broadening->adaptive = 1 the per-process width of
+ * fp_broadening (vel, [N*nb*3] host memory, is then required; both may be
+ * NULL for the fixed width).  Within a row the
  * records are ordered by (q', q'', j', j'', j''') (3ph: q', j', j''), so the
  * records of one (lambda, q', q'') tuple are contiguous.  keep_fraction in
  * (0, 1] keeps a deterministic hash-selected subset of each row's (q', q'')
@@ -292,11 +368,12 @@ fp_status fp_check(fp_ctx* ctx, void* hip_stream);
 fp_status fp_enumerate_count(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
                              double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
                              double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
-                             int64_t* row_off);
+                             const double* vel, const fp_broadening* broadening, int64_t* row_off);
 fp_status fp_enumerate_fill(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
                             double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
                             double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
-                            const int64_t* row_off, uint64_t* rec);
+                            const double* vel, const fp_broadening* broadening, const int64_t* row_off,
+                            uint64_t* rec);
 
 #ifdef __cplusplus
 }

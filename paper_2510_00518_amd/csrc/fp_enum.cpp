@@ -10,15 +10,20 @@
 //
 // The energy mismatch is evaluated in double precision, strictly left to right
 // in record order, and this file is compiled without floating-point
-// contraction, so the filter decision is reproducible bit for bit.
+// contraction, so the filter decision is reproducible bit for bit.  So is the
+// adaptive width: the partner pairs in record order, the three reciprocal
+// directions in order, each projection ((v_i - v_j) . b_d) / N_d as written.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <thread>
 #include <vector>
 
 #include "fp.h"
+#include "fp_enum_impl.h"
 
 #pragma clang fp contract(off)
 
@@ -59,6 +64,37 @@ struct Enum {
     uint64_t keep_threshold;  // keep iff hash < threshold (all when keep_all)
     bool keep_all;
     uint64_t seed;
+    // adaptive broadening: sigma_p = max(factor * sigma0_p, sigma); cut_max bounds
+    // nsigma * sigma_p over every process, so a candidate beyond it is rejected
+    // without evaluating its width
+    bool adaptive;
+    const double* vel;
+    double recip[9], factor, sigma, nsigma, cut_max;
+
+    // squared projections of one partner pair, summed over the three directions
+    // into s2 in order
+    double pair_sq(double s2, int64_t gi, int64_t gj) const {
+        const double* vi = vel + gi * 3;
+        const double* vj = vel + gj * 3;
+        const double w0 = vi[0] - vj[0], w1 = vi[1] - vj[1], w2 = vi[2] - vj[2];
+        for (int d = 0; d < 3; ++d) {
+            const double p = (w0 * recip[d * 3 + 0] + w1 * recip[d * 3 + 1] + w2 * recip[d * 3 + 2]) / (double)N[d];
+            s2 += p * p;
+        }
+        return s2;
+    }
+    // the filter: |delta| <= nsigma * sigma_p; s2 holds the pairs not involving
+    // the last partner (summed first, as their slots come first)
+    bool pass(double delta, double cut_fixed, int m, double s2_head, int64_t gl_prev0, int64_t gl_prev1,
+              int64_t gl) const {
+        const double ad = std::fabs(delta);
+        if (ad <= cut_fixed) return true;   // sigma_p >= sigma
+        if (!adaptive || !(ad <= cut_max)) return false;
+        double s2 = pair_sq(s2_head, gl_prev0, gl);
+        if (m == 4) s2 = pair_sq(s2, gl_prev1, gl);
+        const double sp = factor * std::sqrt(s2 / (3.0 * (double)(m - 1)));
+        return ad <= nsigma * (sp > sigma ? sp : sigma);
+    }
 
     void coords(int64_t iq, int64_t c[3]) const {
         c[2] = iq % N[2];
@@ -102,7 +138,7 @@ struct Enum {
                         const double w2 = omega[g2];
                         if (!(w2 >= floor_)) continue;
                         const double delta = s[2] > 0 ? d1 + w2 : d1 - w2;
-                        if (!(std::fabs(delta) <= cut)) continue;
+                        if (!pass(delta, cut, 3, 0.0, g1, 0, g2)) continue;
                         emit((uint64_t)g1 | ((uint64_t)j2 << 24));
                     }
                 }
@@ -132,13 +168,14 @@ struct Enum {
                         const double w2 = omega[g2];
                         if (!(w2 >= floor_)) continue;
                         const double d2 = s[2] > 0 ? d1 + w2 : d1 - w2;
+                        const double s2_12 = adaptive ? pair_sq(0.0, g1, g2) : 0.0;
                         for (int32_t j3 = 0; j3 < nb; ++j3) {
                             const int64_t g3 = iq3 * nb + j3;
                             if (tri23 && g3 < g2) continue;
                             const double w3 = omega[g3];
                             if (!(w3 >= floor_)) continue;
                             const double delta = s[3] > 0 ? d2 + w3 : d2 - w3;
-                            if (!(std::fabs(delta) <= cut)) continue;
+                            if (!pass(delta, cut, 4, s2_12, g1, g2, g3)) continue;
                             emit((uint64_t)g1 | ((uint64_t)g2 << 24) | ((uint64_t)j3 << 48));
                         }
                     }
@@ -150,7 +187,7 @@ struct Enum {
 
 fp_status setup(Enum* e, int32_t type, const int32_t mesh[3], int32_t nb, const double* omega, double omega_floor,
                 int64_t n_rows, const int32_t* row_mode, double sigma, double nsigma, double keep_fraction,
-                uint64_t seed) {
+                uint64_t seed, const double* vel, const fp_broadening* br) {
     if (!mesh || !omega || (n_rows > 0 && !row_mode) || n_rows < 0) return FP_ERR_ARG;
     if (!type_info(type, &e->ti)) return FP_ERR_ARG;
     if (nb < 1 || nb > 96 || !(sigma > 0.0) || !(nsigma > 0.0) || !(keep_fraction > 0.0 && keep_fraction <= 1.0))
@@ -171,6 +208,41 @@ fp_status setup(Enum* e, int32_t type, const int32_t mesh[3], int32_t nb, const 
     e->keep_all = keep_fraction >= 1.0;
     e->keep_threshold = e->keep_all ? ~0ULL : (uint64_t)std::ldexp(keep_fraction, 64);
     e->seed = seed;
+    e->adaptive = br && br->adaptive;
+    e->sigma = sigma;
+    e->nsigma = nsigma;
+    e->vel = vel;
+    e->factor = 0.0;
+    e->cut_max = e->cut;
+    if (br && br->adaptive != 0 && br->adaptive != 1) return FP_ERR_ARG;
+    if (e->adaptive) {
+        if (!vel || !(br->factor > 0.0) || !std::isfinite(br->factor)) return FP_ERR_ARG;
+        for (int i = 0; i < 9; ++i) {
+            if (!std::isfinite(br->recip[i])) return FP_ERR_ARG;
+            e->recip[i] = br->recip[i];
+        }
+        e->factor = br->factor;
+        // bound: |(v_i - v_j).b_d / N_d| <= 2 max_g |v_g . b_d| / N_d for every pair
+        double pmax[3] = {0.0, 0.0, 0.0};
+        const int64_t nm = e->nq * nb;
+        for (int64_t g = 0; g < nm; ++g) {
+            for (int i = 0; i < 3; ++i)
+                if (!std::isfinite(vel[g * 3 + i])) return FP_ERR_ARG;
+            for (int d = 0; d < 3; ++d) {
+                const double p = std::fabs(vel[g * 3] * e->recip[d * 3] + vel[g * 3 + 1] * e->recip[d * 3 + 1] +
+                                           vel[g * 3 + 2] * e->recip[d * 3 + 2]) /
+                                 (double)e->N[d];
+                if (p > pmax[d]) pmax[d] = p;
+            }
+        }
+        const int m = e->ti.order;
+        const double n_pairs = m == 3 ? 1.0 : 3.0;
+        double b2 = 0.0;
+        for (int d = 0; d < 3; ++d) b2 += 4.0 * pmax[d] * pmax[d];
+        const double smax = std::max(e->factor * std::sqrt(n_pairs * b2 / (3.0 * (double)(m - 1))), sigma);
+        // relative margin far above the rounding of either evaluation
+        e->cut_max = nsigma * smax * (1.0 + 1e-9);
+    }
     return FP_OK;
 }
 
@@ -198,10 +270,10 @@ void parallel_rows(int64_t n_rows, int32_t n_threads, F&& body) {
 extern "C" fp_status fp_enumerate_count(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
                                         double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
                                         double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
-                                        int64_t* row_off) {
+                                        const double* vel, const fp_broadening* broadening, int64_t* row_off) {
     Enum e;
     fp_status st = setup(&e, type, mesh, nb, omega, omega_floor, n_rows, row_mode, sigma, nsigma, keep_fraction,
-                         seed);
+                         seed, vel, broadening);
     if (st != FP_OK) return st;
     if (!row_off) return FP_ERR_ARG;
     std::vector<int64_t> cnt((size_t)n_rows, 0);
@@ -218,10 +290,11 @@ extern "C" fp_status fp_enumerate_count(int32_t type, const int32_t mesh[3], int
 extern "C" fp_status fp_enumerate_fill(int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
                                        double omega_floor, int64_t n_rows, const int32_t* row_mode, double sigma,
                                        double nsigma, double keep_fraction, uint64_t seed, int32_t n_threads,
-                                       const int64_t* row_off, uint64_t* rec) {
+                                       const double* vel, const fp_broadening* broadening, const int64_t* row_off,
+                                       uint64_t* rec) {
     Enum e;
     fp_status st = setup(&e, type, mesh, nb, omega, omega_floor, n_rows, row_mode, sigma, nsigma, keep_fraction,
-                         seed);
+                         seed, vel, broadening);
     if (st != FP_OK) return st;
     if (!row_off || (!rec && row_off[n_rows] > 0)) return FP_ERR_ARG;
     std::atomic<int> bad(0);
@@ -236,3 +309,52 @@ extern "C" fp_status fp_enumerate_fill(int32_t type, const int32_t mesh[3], int3
     });
     return bad.load() ? FP_ERR_ARG : FP_OK;
 }
+
+// ------------------------------------------------ streaming executor interface
+
+namespace fpenum {
+
+struct Handle {
+    Enum e;
+};
+
+fp_status open(Handle** h, int32_t type, const int32_t mesh[3], int32_t nb, const double* omega,
+               double omega_floor, double sigma, double nsigma, const double* vel, const fp_broadening* br) {
+    if (!h) return FP_ERR_ARG;
+    *h = nullptr;
+    Handle* p = new (std::nothrow) Handle;
+    if (!p) return FP_ERR_NOMEM;
+    fp_status st = setup(&p->e, type, mesh, nb, omega, omega_floor, 0, nullptr, sigma, nsigma, 1.0, 0, vel, br);
+    if (st != FP_OK) {
+        delete p;
+        return st;
+    }
+    *h = p;
+    return FP_OK;
+}
+
+void close(Handle* h) { delete h; }
+
+int64_t count_row(const Handle* h, int32_t g0) {
+    int64_t c = 0;
+    h->e.row(g0, [&](uint64_t) { ++c; });
+    return c;
+}
+
+int64_t fill_row(const Handle* h, int32_t g0, int64_t begin, int64_t end, uint64_t* out) {
+    int64_t i = 0, n = 0;
+    h->e.row(g0, [&](uint64_t v) {
+        if (i >= begin && i < end) {
+            out[i - begin] = v;
+            ++n;
+        }
+        ++i;
+    });
+    return n;
+}
+
+void parallel_for(int64_t n, int32_t n_threads, const std::function<void(int64_t)>& body) {
+    parallel_rows(n, n_threads, body);
+}
+
+}  // namespace fpenum

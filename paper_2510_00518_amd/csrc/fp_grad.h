@@ -100,7 +100,8 @@ struct GradArgs {
     int32_t n_terms, n_groups, n_pairs;
     int32_t n_T;
     ModeGeom geo;
-    double inv_sigma2, gnorm, pref;
+    Broad br;
+    double pref;
     Temps dummy;
 };
 
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_grad(FP_GRAD_PARAMS) {
                     const bool have = idx < count;
                     const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
                     const Proc pr = setup_proc<M>(have, rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega,
-                                                  a.n_modes, flag, a.inv_sigma2, a.gnorm);
+                                                  a.n_modes, flag, a.br);
                     const double2 V = vertex_one<M>(pr, c1, c2, c3, nb, evec, phit_row, groups, a.n_groups, tmeta,
                                                     sroots, geo);
                     double cw = 0.0;

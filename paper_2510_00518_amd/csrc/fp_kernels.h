@@ -92,6 +92,27 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
         p[i] = v;
 }
 
+// P[g] = (v_g . b_0 / N_0, v_g . b_1 / N_1, v_g . b_2 / N_2, 0): the projections
+// behind the adaptive width (b = reciprocal vectors as rows)
+struct RecipN {
+    double b[9];
+    double inv_n[3];
+};
+
+__global__ void k_proj(const double* __restrict__ vel, int64_t n_modes, RecipN r, double* __restrict__ proj) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_modes;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const double v0 = vel[g * 3], v1 = vel[g * 3 + 1], v2 = vel[g * 3 + 2];
+        double4 p;
+        p.x = (v0 * r.b[0] + v1 * r.b[1] + v2 * r.b[2]) * r.inv_n[0];
+        p.y = (v0 * r.b[3] + v1 * r.b[4] + v2 * r.b[5]) * r.inv_n[1];
+        p.z = (v0 * r.b[6] + v1 * r.b[7] + v2 * r.b[8]) * r.inv_n[2];
+        p.w = 0.0;
+        reinterpret_cast<double2*>(proj)[g * 2] = make_double2(p.x, p.y);
+        reinterpret_cast<double2*>(proj)[g * 2 + 1] = make_double2(p.z, p.w);
+    }
+}
+
 __global__ void k_zero_int(int* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -261,6 +282,17 @@ __global__ void k_precontract(const RowInfo* __restrict__ rows, int64_t n_rows, 
 
 // --------------------------------------------------------------- the rates
 
+// Width of the Gaussian delta.  proj == nullptr: the fixed width (inv_sigma2 =
+// 1/sigma^2, gnorm = 1/(sigma sqrt(pi))).  Otherwise the per-process width
+// sigma_p = max(factor * sigma0_p, floor_) with sigma0_p^2 the sum over partner
+// pairs of |P_i - P_j|^2 divided by 3 (m - 1), where P_g[d] = v_g . b_d / N_d is
+// the per-mode projection table (4 doubles per mode, the last unused).
+struct Broad {
+    double inv_sigma2, gnorm;
+    const double* proj;
+    double factor, floor_;
+};
+
 struct RatesArgs {
     int64_t n_units;
     int64_t n_modes;
@@ -268,7 +300,7 @@ struct RatesArgs {
     int32_t n_T;
     int32_t ppl;  // records per lane per unit
     ModeGeom geo;
-    double inv_sigma2, gnorm;  // 1/sigma^2, 1/(sigma sqrt(pi))
+    Broad br;
 };
 
 // Pointers travel as separate restrict-qualified arguments so that the compiler
@@ -355,11 +387,20 @@ __device__ inline Proc decode4(bool have, uint64_t rec, int s1, int s2, int s3, 
     return p;
 }
 
+// squared distance of two projection rows (three directions)
+__device__ inline double proj_sq(const double* __restrict__ proj, int32_t gi, int32_t gj) {
+    const double2 a01 = *reinterpret_cast<const double2*>(proj + (size_t)gi * 4);
+    const double2 b01 = *reinterpret_cast<const double2*>(proj + (size_t)gj * 4);
+    const double a2 = proj[(size_t)gi * 4 + 2], b2 = proj[(size_t)gj * 4 + 2];
+    const double d0 = a01.x - b01.x, d1 = a01.y - b01.y, d2 = a2 - b2;
+    return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
 template <int M>
 __device__ inline Proc setup_proc(bool have, uint64_t rec, int type, int s1, int s2, int s3, int32_t g0, int32_t c00,
                                   int32_t c01, int32_t c02, double w0, const ModeGeom& geo,
                                   const double* __restrict__ omega, int64_t n_modes, int* __restrict__ flag,
-                                  double inv_sigma2, double gnorm) {
+                                  const Broad& br) {
     Proc p;
     p.g1 = p.g2 = p.gl = g0;
     p.Q10 = p.Q11 = p.Q12 = p.Q20 = p.Q21 = p.Q22 = 0;
@@ -426,6 +467,15 @@ __device__ inline Proc setup_proc(bool have, uint64_t rec, int type, int s1, int
     p.g1 = g1;
     p.g2 = M == 4 ? g2 : gl;  // order 3: slot 2 is the momentum-fixed partner
     p.gl = gl;
+    double inv_sigma2 = br.inv_sigma2, gnorm = br.gnorm;
+    if (br.proj) {
+        // partners: g1, gl (order 3); g1, g2, gl (order 4)
+        double s2 = proj_sq(br.proj, g1, M == 4 ? g2 : gl);
+        if (M == 4) s2 += proj_sq(br.proj, g1, gl) + proj_sq(br.proj, g2, gl);
+        const double sig = fmax(br.factor * sqrt(s2 * (M == 3 ? (1.0 / 6.0) : (1.0 / 9.0))), br.floor_);
+        inv_sigma2 = 1.0 / (sig * sig);
+        gnorm = 0.56418958354775628695 / sig;  // 1/(sigma sqrt(pi))
+    }
     p.base = wt * exp(-(delta * delta) * inv_sigma2) * gnorm / wprod;
     return p;
 }
@@ -500,7 +550,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
                     const bool have = idx < count && p0 + i < a.ppl;
                     const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
                     pr[i] = setup_proc<M>(have, rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
-                                          flag, a.inv_sigma2, a.gnorm);
+                                          flag, a.br);
                 }
                 double2 V[NP];
 #pragma unroll

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,6 +19,7 @@
 #include "fp_batched.h"
 #include "fp_mixed.h"
 #include "fp_fused.h"
+#include "fp_enum_impl.h"
 
 namespace {
 
@@ -42,7 +44,10 @@ struct DevBuf {
     hipError_t ensure(size_t want) {
         if (want <= n && p) return hipSuccess;
         if (p) {
-            hipError_t e = hipFree(p);
+            // work queued on any stream may still read the old buffer
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return e;
+            e = hipFree(p);
             p = nullptr;
             n = 0;
             if (e != hipSuccess) return e;
@@ -56,6 +61,45 @@ struct DevBuf {
         if (p) (void)hipFree(p);
         p = nullptr;
         n = 0;
+    }
+};
+
+// Grow-only pinned host buffer (staging of streamed lists).
+template <class T>
+struct HostBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t want) {
+        if (want <= n && p) return hipSuccess;
+        release();
+        const size_t m = std::max<size_t>(want, 1);
+        hipError_t e = hipHostMalloc((void**)&p, m * sizeof(T), hipHostMallocDefault);
+        if (e == hipSuccess) n = m;
+        else p = nullptr;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// One staging slot of the streaming executor: host and device copies of a chunk
+// of lists, and the event that marks the end of the GPU work reading it.
+struct StreamSlot {
+    HostBuf<uint64_t> rec;
+    HostBuf<int64_t> off;
+    HostBuf<int32_t> mode;
+    DevBuf<uint64_t> drec;
+    DevBuf<int64_t> doff;
+    DevBuf<int32_t> dmode;
+    hipEvent_t done = nullptr;
+    void release() {
+        rec.release(); off.release(); mode.release();
+        drec.release(); doff.release(); dmode.release();
+        if (done) (void)hipEventDestroy(done);
+        done = nullptr;
     }
 };
 
@@ -91,7 +135,13 @@ struct fp_ctx {
     int32_t L = 1;
     double volume = 0.0, floor_ = 0.0;
     bool have_vel = false;
+    bool adaptive = false;      // per-process broadening (fp_set_broadening)
+    double bfactor = 0.0;
+    fp_broadening bro{};        // the setting behind proj, for the host enumerator
+    DevBuf<double> proj;        // [n_modes][4] projections v . b_d / N_d
     std::vector<double> masses;
+    std::vector<double> h_omega, h_vel;  // host copies for the streaming executor's enumerator
+    StreamSlot slot[2];
     DevBuf<double> omega, vel;
     DevBuf<double2> evec, roots;
     DevBuf<float2> evec32;  // FP32 copy of the eigenvectors for the mixed-precision contraction
@@ -171,6 +221,17 @@ int grid_for(int64_t n, int threads = 256) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
 }
 
+// Gaussian width of a call: `sigma` itself, or the floor of the per-process width
+fpk::Broad make_broad(const fp_ctx* c, double sigma) {
+    fpk::Broad b;
+    b.inv_sigma2 = 1.0 / (sigma * sigma);
+    b.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+    b.proj = c->adaptive ? c->proj.p : nullptr;
+    b.factor = c->bfactor;
+    b.floor_ = sigma;
+    return b;
+}
+
 }  // namespace
 
 extern "C" fp_status fp_create(fp_ctx** out, int32_t device) {
@@ -205,10 +266,13 @@ extern "C" void fp_destroy(fp_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    c->omega.release(); c->vel.release(); c->evec.release(); c->roots.release();
+    c->omega.release(); c->vel.release(); c->evec.release(); c->roots.release(); c->evec32.release();
+    c->proj.release();
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
     c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release();
+    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->unit_kept.release();
+    c->slot[0].release(); c->slot[1].release();
     if (c->flag) (void)hipFree(c->flag);
     for (auto& e : c->ev_used) {
         (void)hipEventDestroy(e.second.first);
@@ -279,6 +343,9 @@ extern "C" fp_status fp_load_modes(fp_ctx* c, const int32_t mesh[3], int32_t n_a
     for (int64_t i = 0; i < 2 * nm * nb; ++i)
         if (!std::isfinite(evec[i])) return fail(c, FP_ERR_ARG, "eigenvectors must be finite");
     if (!(omega_floor >= 0.0)) return fail(c, FP_ERR_ARG, "omega_floor must be >= 0");
+    if (vel)
+        for (int64_t i = 0; i < nm * 3; ++i)
+            if (!std::isfinite(vel[i])) return fail(c, FP_ERR_ARG, "velocities must be finite");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
     HIP_TRY(c, c->omega.ensure(nm));
@@ -295,7 +362,11 @@ extern "C" fp_status fp_load_modes(fp_ctx* c, const int32_t mesh[3], int32_t n_a
     if (vel) {
         HIP_TRY(c, c->vel.ensure(nm * 3));
         HIP_TRY(c, hipMemcpy(c->vel.p, vel, nm * 3 * sizeof(double), hipMemcpyHostToDevice));
+        c->h_vel.assign(vel, vel + nm * 3);
+    } else {
+        c->h_vel.clear();
     }
+    c->h_omega.assign(omega, omega + nm);
     std::vector<double2> roots((size_t)L);
     for (int64_t k = 0; k < L; ++k) {
         const double ang = 2.0 * kPi * (double)k / (double)L;
@@ -316,7 +387,34 @@ extern "C" fp_status fp_load_modes(fp_ctx* c, const int32_t mesh[3], int32_t n_a
                           A[2] * (A[3] * A[7] - A[4] * A[6]));
     c->ifc[0].release();
     c->ifc[1].release();
+    c->adaptive = false;
     c->modes = true;
+    return FP_OK;
+}
+
+extern "C" fp_status fp_set_broadening(fp_ctx* c, const fp_broadening* b) {
+    if (!c) return FP_ERR_ARG;
+    if (!b || b->adaptive == 0) {
+        c->adaptive = false;
+        return FP_OK;
+    }
+    if (b->adaptive != 1) return fail(c, FP_ERR_ARG, "adaptive must be 0 or 1");
+    if (!(b->factor > 0.0) || !std::isfinite(b->factor)) return fail(c, FP_ERR_ARG, "factor must be > 0");
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(b->recip[i])) return fail(c, FP_ERR_ARG, "reciprocal vectors must be finite");
+    if (!c->modes || !c->have_vel) return fail(c, FP_ERR_STATE, "fp_load_modes with velocities must come first");
+    fpk::RecipN r;
+    for (int i = 0; i < 9; ++i) r.b[i] = b->recip[i];
+    for (int d = 0; d < 3; ++d) r.inv_n[d] = 1.0 / (double)c->mesh[d];
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, c->proj.ensure((size_t)c->n_modes * 4));
+    hipLaunchKernelGGL(fpk::k_proj, dim3(grid_for(c->n_modes)), dim3(256), 0, nullptr, c->vel.p, c->n_modes, r,
+                       c->proj.p);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipDeviceSynchronize());
+    c->bfactor = b->factor;
+    c->bro = *b;
+    c->adaptive = true;
     return FP_OK;
 }
 
@@ -709,8 +807,7 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     a.n_T = n_T;
     a.ppl = (int32_t)ppl;
     a.geo = pp.geo;
-    a.inv_sigma2 = 1.0 / (sigma * sigma);
-    a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+    a.br = make_broad(c, sigma);
     const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
     if (mixed) {
         const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
@@ -843,6 +940,7 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     IfcState& S = c->ifc[1];
     if (S.order != 4) return fail(c, FP_ERR_STATE, "force constants of order 4 not loaded");
     if (c->nb != fpk::kFusedNb) return fail(c, FP_ERR_UNSUPPORTED, "the fused path is built for nb = 6 (two atoms)");
+    if (c->adaptive) return fail(c, FP_ERR_UNSUPPORTED, "the fused path takes the fixed width only");
     if (n_rows < 0 || (n_rows > 0 && !row_mode)) return fail(c, FP_ERR_ARG, "bad row list");
     if (type_mask < 1 || type_mask > 7) return fail(c, FP_ERR_ARG, "type_mask must be in [1, 7]");
     if (n_T < 1 || n_T > FP_MAX_T || !T_K) return fail(c, FP_ERR_ARG, "n_T must be in [1, %d]", FP_MAX_T);
@@ -898,8 +996,7 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     a.n_T = n_T;
     a.ppl = fpk::kBR;
     a.geo = geo;
-    a.inv_sigma2 = 1.0 / (sigma * sigma);
-    a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+    a.br = make_broad(c, sigma);
     const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
     hipEvent_t ev0, ev1;
     fp_status ts = timer_start(c, st, &ev0, &ev1);
@@ -1057,8 +1154,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
             ra.n_T = n_T;
             ra.ppl = mixed ? fpk::kBR : 3;
             ra.geo = pp.geo;
-            ra.inv_sigma2 = 1.0 / (sigma * sigma);
-            ra.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+            ra.br = make_broad(c, sigma);
             const double pref4 = rate_prefactor(c, m);
             if (mixed) {
                 const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
@@ -1086,8 +1182,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
         a.n_pairs = S.n_pairs;
         a.n_T = n_T;
         a.geo = pp.geo;
-        a.inv_sigma2 = 1.0 / (sigma * sigma);
-        a.gnorm = 1.0 / (sigma * std::sqrt(kPi));
+        a.br = make_broad(c, sigma);
         a.pref = rate_prefactor(c, m);
         fp_status ls;
         if (m == 3)
@@ -1181,5 +1276,195 @@ extern "C" fp_status fp_kappa_rta(fp_ctx* c, int32_t n_q1, const int32_t* q1, co
     hipLaunchKernelGGL(fpk::k_kappa, dim3(n_T), dim3(fpk::kBlock), 0, st, q1, q1_weight, n_q1, c->nb, c->omega.p,
                        c->vel.p, gamma, c->n_modes, tx, pref, c->floor_, kappa_out, dkappa_dgamma, c->flag);
     HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+// ------------------------------------------------------- streaming executor
+//
+// Mode-wise fallback generalised to chunks (Appendix, the mode-wise variant of
+// Algorithm 4; Results, memory limits of the all-modes strategy): the host
+// enumerator counts every selected (type, row), the concatenated record
+// sequence is cut into chunks of at most chunk_records, and each chunk is
+// enumerated into a pinned staging slot, copied to the device and evaluated by
+// the ordinary rate launches with FP_ACCUMULATE.  Two slots alternate, so the
+// host fills chunk k+1 while the GPU copies and evaluates chunk k.
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+struct EnumSet {
+    fpenum::Handle* h[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    ~EnumSet() {
+        for (auto* p : h) fpenum::close(p);
+    }
+};
+
+}  // namespace
+
+extern "C" fp_status fp_rates_streamed(fp_ctx* c, int32_t type_mask, int64_t n_rows, const int32_t* row_mode,
+                                       int32_t n_T, const double* T_K, double sigma, double nsigma,
+                                       int32_t precision, int64_t chunk_records, int32_t n_threads,
+                                       double* gamma_out, double* wp_out, fp_stream_stats* stats, void* stream) {
+    if (!c) return FP_ERR_ARG;
+    const Clock::time_point t_call = Clock::now();
+    fp_status cs = check_common(c, 0, nullptr, n_T, T_K, sigma);
+    if (cs != FP_OK) return cs;
+    if (type_mask < 1 || type_mask > 31) return fail(c, FP_ERR_ARG, "type_mask must be in [1, 31]");
+    if (!(nsigma > 0.0) || !std::isfinite(nsigma)) return fail(c, FP_ERR_ARG, "nsigma must be > 0");
+    if (chunk_records < 1 || chunk_records > (int64_t(1) << 32))
+        return fail(c, FP_ERR_ARG, "chunk_records must be in [1, 2^32]");
+    const bool accumulate = (precision & FP_ACCUMULATE) != 0;
+    const int32_t prec = precision & ~FP_ACCUMULATE;
+    if (prec != FP_FP64 && prec != FP_MIXED) return fail(c, FP_ERR_ARG, "unknown precision %d", prec);
+    if (n_rows < 0 || (n_rows > 0 && !row_mode)) return fail(c, FP_ERR_ARG, "bad row list");
+    {
+        std::vector<int32_t> sorted(row_mode, row_mode + n_rows);
+        std::sort(sorted.begin(), sorted.end());
+        for (int64_t r = 0; r < n_rows; ++r) {
+            if (sorted[r] < 0 || sorted[r] >= c->n_modes) return fail(c, FP_ERR_ARG, "row mode out of range");
+            if (r > 0 && sorted[r] == sorted[r - 1]) return fail(c, FP_ERR_ARG, "row modes must be distinct");
+        }
+    }
+    std::vector<int32_t> ts;  // selected types, ascending
+    for (int32_t t = FP_3P; t <= FP_4MM; ++t) {
+        if (!(type_mask & (1 << t))) continue;
+        const int m = t <= FP_3M ? 3 : 4;
+        if (c->ifc[m - 3].order != m) return fail(c, FP_ERR_STATE, "force constants of order %d not loaded", m);
+        ts.push_back(t);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t nm = c->n_modes;
+    if (!accumulate) {
+        if (gamma_out)
+            hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, gamma_out, n_T * nm, 0.0);
+        if (wp_out)
+            hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, wp_out, n_T * nm, 0.0);
+        HIP_TRY(c, hipGetLastError());
+    }
+    EnumSet es;
+    for (int32_t t : ts) {
+        fp_status s = fpenum::open(&es.h[t], t, c->mesh, c->nb, c->h_omega.data(), c->floor_, sigma, nsigma,
+                                   c->adaptive ? c->h_vel.data() : nullptr, c->adaptive ? &c->bro : nullptr);
+        if (s != FP_OK) return fail(c, s, "enumerator setup failed for type %d", t);
+    }
+
+    // count pass: records of every (type, row), types major
+    const int64_t n_seq = (int64_t)ts.size() * n_rows;
+    Clock::time_point t0 = Clock::now();
+    std::vector<int64_t> goff((size_t)n_seq + 1, 0);
+    fpenum::parallel_for(n_seq, n_threads, [&](int64_t i) {
+        goff[(size_t)i + 1] = fpenum::count_row(es.h[ts[(size_t)(i / n_rows)]], row_mode[i % n_rows]);
+    });
+    for (int64_t i = 0; i < n_seq; ++i) goff[(size_t)i + 1] += goff[(size_t)i];
+    const double count_ms = ms_since(t0);
+    const int64_t total = goff[(size_t)n_seq];
+    const int64_t cap = std::min(chunk_records, std::max<int64_t>(total, 1));
+    const int64_t n_chunks = (total + cap - 1) / cap;
+    const size_t nt = ts.size();
+
+    double fill_ms = 0.0, wait_ms = 0.0;
+    int64_t max_chunk = 0;
+    struct Seg {
+        int64_t seq;        // (type, row) index in the global sequence
+        int64_t beg, end;   // record window within the row
+        int64_t dst;        // position in the chunk
+    };
+    std::vector<Seg> segs;
+    for (int64_t k = 0; k < n_chunks; ++k) {
+        StreamSlot& sl = c->slot[k & 1];
+        if (!sl.done) HIP_TRY(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+        if (k >= 2) {
+            t0 = Clock::now();
+            HIP_TRY(c, hipEventSynchronize(sl.done));
+            wait_ms += ms_since(t0);
+        }
+        HIP_TRY(c, sl.rec.ensure((size_t)cap));
+        HIP_TRY(c, sl.off.ensure((size_t)(n_seq + nt)));
+        HIP_TRY(c, sl.mode.ensure((size_t)std::max<int64_t>(n_seq, 1)));
+        HIP_TRY(c, sl.drec.ensure((size_t)cap));
+        HIP_TRY(c, sl.doff.ensure((size_t)(n_seq + nt)));
+        HIP_TRY(c, sl.dmode.ensure((size_t)std::max<int64_t>(n_seq, 1)));
+        const int64_t lo = k * cap, hi = std::min(total, lo + cap);
+        max_chunk = std::max(max_chunk, hi - lo);
+        // the (type, row) entries overlapping [lo, hi)
+        segs.clear();
+        int64_t i = std::upper_bound(goff.begin(), goff.end(), lo) - goff.begin() - 1;
+        for (; i < n_seq && goff[(size_t)i] < hi; ++i) {
+            const int64_t b = std::max(goff[(size_t)i], lo), e = std::min(goff[(size_t)i + 1], hi);
+            if (e > b) segs.push_back({i, b - goff[(size_t)i], e - goff[(size_t)i], b - lo});
+        }
+        // per-type row tables of this chunk: modes, then offsets into the chunk's records
+        int n3 = 0, n4 = 0;
+        fp_plist l3[2], l4[3];
+        int64_t mpos = 0, opos = 0;
+        size_t sj = 0;
+        for (size_t ti = 0; ti < nt; ++ti) {
+            fp_plist P;
+            memset(&P, 0, sizeof P);
+            P.type = ts[ti];
+            const int64_t m0 = mpos, o0 = opos;
+            int64_t first = -1, last = 0;
+            for (; sj < segs.size() && segs[sj].seq / n_rows == (int64_t)ti; ++sj) {
+                sl.mode.p[mpos++] = row_mode[segs[sj].seq % n_rows];
+                sl.off.p[opos++] = segs[sj].dst;
+                if (first < 0) first = segs[sj].dst;
+                last = segs[sj].dst + (segs[sj].end - segs[sj].beg);
+            }
+            if (mpos == m0) continue;
+            sl.off.p[opos++] = last;
+            // offsets relative to the list's first record
+            for (int64_t q = o0; q < opos; ++q) sl.off.p[q] -= first;
+            P.n_rows = mpos - m0;
+            P.n_rec = last - first;
+            P.row_mode = sl.dmode.p + m0;
+            P.row_off = sl.doff.p + o0;
+            P.rec = sl.drec.p + first;
+            if (P.type <= FP_3M) l3[n3++] = P;
+            else l4[n4++] = P;
+        }
+        // enumerate the chunk's records on the host threads
+        t0 = Clock::now();
+        std::vector<int64_t> got(segs.size(), 0);
+        fpenum::parallel_for((int64_t)segs.size(), n_threads, [&](int64_t j) {
+            const Seg& g = segs[(size_t)j];
+            got[(size_t)j] = fpenum::fill_row(es.h[ts[(size_t)(g.seq / n_rows)]], row_mode[g.seq % n_rows], g.beg,
+                                              g.end, sl.rec.p + g.dst);
+        });
+        fill_ms += ms_since(t0);
+        for (size_t j = 0; j < segs.size(); ++j)
+            if (got[j] != segs[j].end - segs[j].beg)
+                return fail(c, FP_ERR_STATE, "enumeration changed between the count and fill passes");
+        HIP_TRY(c, hipMemcpyAsync(sl.drec.p, sl.rec.p, (size_t)(hi - lo) * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                  st));
+        HIP_TRY(c, hipMemcpyAsync(sl.doff.p, sl.off.p, (size_t)opos * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(sl.dmode.p, sl.mode.p, (size_t)mpos * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        if (n3 > 0) {
+            fp_status s = run_rates(c, 3, l3, n3, n_T, T_K, sigma, prec | FP_ACCUMULATE, gamma_out, wp_out, stream);
+            if (s != FP_OK) return s;
+        }
+        if (n4 > 0) {
+            fp_status s = run_rates(c, 4, l4, n4, n_T, T_K, sigma, prec | FP_ACCUMULATE, gamma_out, wp_out, stream);
+            if (s != FP_OK) return s;
+        }
+        HIP_TRY(c, hipEventRecord(sl.done, st));
+    }
+    t0 = Clock::now();
+    HIP_TRY(c, hipStreamSynchronize(st));
+    wait_ms += ms_since(t0);
+    if (stats) {
+        stats->n_records = total;
+        stats->n_chunks = n_chunks;
+        stats->max_chunk = max_chunk;
+        stats->count_ms = count_ms;
+        stats->fill_ms = fill_ms;
+        stats->wait_ms = wait_ms;
+        stats->total_ms = ms_since(t_call);
+    }
     return FP_OK;
 }

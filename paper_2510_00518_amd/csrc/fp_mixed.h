@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4m(FP_RATES_MIXED_PARAMS, co
                 have[k] = idx < count;
                 const uint64_t rec = have[k] ? ri.rec[ud.start + idx] : 0;
                 pr[k] = setup_proc<4>(have[k], rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
-                                      flag, a.inv_sigma2, a.gnorm);
+                                      flag, a.br);
                 const uint64_t key = have[k] ? (((uint64_t)(pr[k].g1 / nb) << 32) | (uint64_t)(pr[k].g2 / nb))
                                              : ~0ull;
                 uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);

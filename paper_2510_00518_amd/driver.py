@@ -17,12 +17,14 @@ TYPES3 = (fp.FP_3P, fp.FP_3M)
 TYPES4 = (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM)
 
 
-def host_lists(cfg, types, rows=None, sigma=None, nsigma=None, keep_fraction=1.0, seed=0, n_threads=0):
-    """{type: (row_mode, row_off, rec)} from the library's host enumerator."""
+def host_lists(cfg, types, rows=None, sigma=None, nsigma=None, keep_fraction=1.0, seed=0, n_threads=0,
+               broadening=None):
+    """{type: (row_mode, row_off, rec)} from the library's host enumerator
+    (broadening: None or {"factor": a, "recip": (3, 3)} for the adaptive width)."""
     out = {}
     for t in types:
         out[t] = fp.enumerate_list(t, cfg, row_mode=rows, sigma=sigma, nsigma=nsigma, keep_fraction=keep_fraction,
-                                   seed=seed, n_threads=n_threads)
+                                   seed=seed, n_threads=n_threads, broadening=broadening)
     return out
 
 
@@ -80,8 +82,16 @@ class RatePath:
             self.phi4 = torch.as_tensor(cfg["ifc4"]["phi"]).to(self.device)
         self.fused_rows = None
         self.fused_mask = 0
+        self.stream_rows = None
+        self.broadening = None
         self.q1 = torch.as_tensor(np.ascontiguousarray(cfg["q1"], dtype=np.int32)).to(self.device)
         self.q1w = torch.as_tensor(np.ascontiguousarray(cfg["q1_weight"], dtype=np.float64)).to(self.device)
+
+    def set_broadening(self, broadening):
+        """None: the fixed width; {"factor": a, "recip": (3, 3)}: the adaptive
+        width, with the sigma of each call as its floor."""
+        fp.fp_set_broadening(self.ctx, broadening)
+        self.broadening = broadening
 
     def close(self):
         if self.own_ctx and self.ctx is not None:
@@ -105,6 +115,18 @@ class RatePath:
         self.lists4 = []
         self.kept = torch.zeros(1, dtype=torch.int64, device=self.device)
 
+    def set_streamed(self, type_mask=31, rows=None, chunk_records=1 << 26, n_threads=0):
+        """Evaluate through fp_rates_streamed: the library enumerates the lists of
+        `rows` (default: every active mode of the q1 set) chunk by chunk on the
+        host, so no whole list is ever held."""
+        self.stream_rows = np.ascontiguousarray(row_modes(self.cfg) if rows is None else rows, dtype=np.int32)
+        self.stream_mask = int(type_mask)
+        self.stream_chunk = int(chunk_records)
+        self.stream_threads = int(n_threads)
+        self.lists3, self.lists4 = [], []
+        self.fused_rows = None
+        self.stream_stats = None
+
     @property
     def n_proc4(self):
         return sum(pl.n_rec for pl in self.lists4)
@@ -117,7 +139,7 @@ class RatePath:
         """Key of the autotuner cache: what the best launch depends on."""
         lists = self.lists3 if order == 3 else self.lists4
         return "|".join(str(x) for x in (order, self.precision if order == 4 else fp.FP_FP64, n_T,
-                                          self.cfg["nb"], self.n_modes, len(lists),
+                                          int(self.broadening is not None), self.cfg["nb"], self.n_modes, len(lists),
                                           sum(pl.n_rows for pl in lists), sum(pl.n_rec for pl in lists)))
 
     def autotune(self, T, order=4, cache=None, reps=2):
@@ -156,6 +178,11 @@ class RatePath:
         cfg = self.cfg
         if self.fused_rows is not None and phi4 is None:
             phi4 = self.phi4
+        if self.stream_rows is not None:
+            if phi3 is None and self.stream_mask & 3 and self.phi3 is not None:
+                phi3 = self.phi3
+            if phi4 is None and self.stream_mask & 28 and self.phi4 is not None:
+                phi4 = self.phi4
         if self.lists3 or phi3 is not None:
             p = self.phi3 if phi3 is None else phi3
             fp.fp_load_ifc(self.ctx, 3, cfg["ifc3"]["atoms"], cfg["ifc3"]["cells"], p)
@@ -179,6 +206,14 @@ class RatePath:
             fp.fp_rates4_fused(self.ctx, self.fused_rows, self.fused_mask, T, sigma, self.cfg["nsigma"], prec, gamma, wp,
                                n_kept=self.kept)
             first = False
+        if self.stream_rows is not None:
+            mask = self.stream_mask & {None: 31, 3: 3, 4: 28}[order]
+            if mask:
+                prec = self.precision if first else self.precision | fp.FP_ACCUMULATE
+                self.stream_stats = fp.fp_rates_streamed(self.ctx, mask, self.stream_rows, T, sigma, self.cfg["nsigma"],
+                                                         prec, self.stream_chunk, gamma, wp,
+                                                         n_threads=self.stream_threads)
+                first = False
         if first:
             gamma.zero_()
             if wp is not None:

@@ -24,7 +24,7 @@ FP_MAX_LISTS = 8
 
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
            "fp_rates4_fused", "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
-           "fp_enumerate_count", "fp_enumerate_fill"]
+           "fp_enumerate_count", "fp_enumerate_fill", "fp_set_broadening", "fp_rates_streamed"]
 
 
 class FpError(RuntimeError):
@@ -42,6 +42,30 @@ class fp_plist(ctypes.Structure):
 class fp_tune_entry(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("ppl", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class fp_stream_stats(ctypes.Structure):
+    _fields_ = [("n_records", ctypes.c_int64), ("n_chunks", ctypes.c_int64), ("max_chunk", ctypes.c_int64),
+                ("count_ms", ctypes.c_double), ("fill_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class fp_broadening(ctypes.Structure):
+    _fields_ = [("adaptive", ctypes.c_int32), ("reserved", ctypes.c_int32), ("factor", ctypes.c_double),
+                ("recip", ctypes.c_double * 9)]
+
+
+def _broadening(b):
+    """None (fixed width) or {"factor": a, "recip": (3, 3) rows b_d} -> fp_broadening pointer or None."""
+    if b is None:
+        return None
+    out = fp_broadening()
+    out.adaptive = 1
+    out.factor = float(b["factor"])
+    rc = np.asarray(b["recip"], dtype=np.float64).reshape(9)
+    for i in range(9):
+        out.recip[i] = float(rc[i])
+    return ctypes.pointer(out)
 
 
 _lib = None
@@ -74,8 +98,12 @@ def lib():
                                   ctypes.POINTER(fp_tune_entry), i32, vp, vp]
         L.fp_profile.argtypes = [vp, i32]
         L.fp_profile_read.argtypes = [vp, i32, vp, vp]
-        L.fp_enumerate_count.argtypes = [i32, vp, i32, vp, dbl, i64, vp, dbl, dbl, dbl, u64, i32, vp]
-        L.fp_enumerate_fill.argtypes = [i32, vp, i32, vp, dbl, i64, vp, dbl, dbl, dbl, u64, i32, vp, vp]
+        bp = ctypes.POINTER(fp_broadening)
+        L.fp_enumerate_count.argtypes = [i32, vp, i32, vp, dbl, i64, vp, dbl, dbl, dbl, u64, i32, vp, bp, vp]
+        L.fp_enumerate_fill.argtypes = [i32, vp, i32, vp, dbl, i64, vp, dbl, dbl, dbl, u64, i32, vp, bp, vp, vp]
+        L.fp_set_broadening.argtypes = [vp, bp]
+        L.fp_rates_streamed.argtypes = [vp, i32, i64, vp, i32, vp, dbl, dbl, i32, i64, i32, vp, vp,
+                                        ctypes.POINTER(fp_stream_stats), vp]
         for name in EXPORTS:
             if name not in ("fp_destroy", "fp_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -252,45 +280,77 @@ def fp_profile_read(ctx, order):
     return ms.value, n.value
 
 
+def fp_set_broadening(ctx, broadening):
+    """broadening: None (the fixed width of each call) or {"factor": a, "recip": (3, 3)}."""
+    _check(ctx, lib().fp_set_broadening(ctx, _broadening(broadening)))
+
+
+def fp_rates_streamed(ctx, type_mask, row_mode, T, sigma, nsigma, precision, chunk_records, gamma_out, wp_out=None,
+                      n_threads=0, stream=None):
+    """Rates over host-enumerated lists streamed through bounded staging slots
+    (row_mode: host array).  Synchronous; returns the call's figures as a dict."""
+    rm = _host(row_mode, np.int32)
+    T = _host(np.atleast_1d(T), np.float64)
+    st = fp_stream_stats()
+    _check(ctx, lib().fp_rates_streamed(ctx, int(type_mask), len(rm), _hp(rm), len(T), _hp(T), float(sigma),
+                                        float(nsigma), int(precision), int(chunk_records), int(n_threads),
+                                        _dp(gamma_out), _dp(wp_out), ctypes.byref(st), _stream(stream)))
+    return {k: getattr(st, k) for k, _ in fp_stream_stats._fields_}
+
+
 def fp_check(ctx, stream=None):
     _check(ctx, lib().fp_check(ctx, _stream(stream)))
 
 
+def _vel(vel, broadening):
+    if broadening is None:
+        return None, None
+    if vel is None:
+        raise ValueError("adaptive broadening needs the group velocities")
+    v = _host(vel, np.float64).reshape(-1)
+    return v, _hp(v)
+
+
 def fp_enumerate_count(ptype, mesh, nb, omega, omega_floor, row_mode, sigma, nsigma, keep_fraction=1.0, seed=0,
-                       n_threads=0):
+                       n_threads=0, vel=None, broadening=None):
     mesh = _host(mesh, np.int32)
     omega = _host(omega, np.float64).reshape(-1)
     row_mode = _host(row_mode, np.int32)
     row_off = np.zeros(len(row_mode) + 1, dtype=np.int64)
+    v, vp = _vel(vel, broadening)
     st = lib().fp_enumerate_count(int(ptype), _hp(mesh), int(nb), _hp(omega), float(omega_floor), len(row_mode),
                                   _hp(row_mode), float(sigma), float(nsigma), float(keep_fraction), int(seed),
-                                  int(n_threads), _hp(row_off))
+                                  int(n_threads), vp, _broadening(broadening), _hp(row_off))
     _check(None, st)
     return row_off
 
 
 def fp_enumerate_fill(ptype, mesh, nb, omega, omega_floor, row_mode, sigma, nsigma, row_off, keep_fraction=1.0,
-                      seed=0, n_threads=0):
+                      seed=0, n_threads=0, vel=None, broadening=None):
     mesh = _host(mesh, np.int32)
     omega = _host(omega, np.float64).reshape(-1)
     row_mode = _host(row_mode, np.int32)
     row_off = _host(row_off, np.int64)
     rec = np.zeros(max(1, int(row_off[-1])), dtype=np.uint64)
+    v, vp = _vel(vel, broadening)
     st = lib().fp_enumerate_fill(int(ptype), _hp(mesh), int(nb), _hp(omega), float(omega_floor), len(row_mode),
                                  _hp(row_mode), float(sigma), float(nsigma), float(keep_fraction), int(seed),
-                                 int(n_threads), _hp(row_off), _hp(rec))
+                                 int(n_threads), vp, _broadening(broadening), _hp(row_off), _hp(rec))
     _check(None, st)
     return rec[: int(row_off[-1])]
 
 
-def enumerate_list(ptype, cfg, row_mode=None, nsigma=None, sigma=None, keep_fraction=1.0, seed=0, n_threads=0):
-    """Both enumeration passes for one list of a synthetic workload (host arrays)."""
+def enumerate_list(ptype, cfg, row_mode=None, nsigma=None, sigma=None, keep_fraction=1.0, seed=0, n_threads=0,
+                   broadening=None):
+    """Both enumeration passes for one list of a synthetic workload (host arrays).
+    broadening: None or {"factor": a, "recip": (3, 3)} (adaptive width, floor sigma)."""
     from .synth import row_modes
     rm = row_modes(cfg) if row_mode is None else np.asarray(row_mode, dtype=np.int32)
     sig = cfg["sigma"] if sigma is None else sigma
     ns = cfg["nsigma"] if nsigma is None else nsigma
+    vel = cfg["vel"] if broadening is not None else None
     off = fp_enumerate_count(ptype, cfg["mesh"], cfg["nb"], cfg["omega"], cfg["omega_floor"], rm, sig, ns,
-                             keep_fraction, seed, n_threads)
+                             keep_fraction, seed, n_threads, vel, broadening)
     rec = fp_enumerate_fill(ptype, cfg["mesh"], cfg["nb"], cfg["omega"], cfg["omega_floor"], rm, sig, ns, off,
-                            keep_fraction, seed, n_threads)
+                            keep_fraction, seed, n_threads, vel, broadening)
     return rm, off, rec

@@ -14,7 +14,8 @@
 Common recipe: a = 5.431 A, masses 28 amu, per-shell spring constants
 k1, k2 ~ U[5, 15] eV/A^2, cubic coefficients scaled to RMS 1 eV/A^3, quartic to
 RMS 0.3 eV/A^4, Gaussian width sigma = 0.1 THz = 2 pi * 0.1 rad/ps, filter
-|Delta| <= 3 sigma, omega floor 1e-3 rad/ps.  Seeds: default_rng(251000518 + k)
+|Delta| <= 3 sigma, omega floor 1e-3 rad/ps.  Adaptive-width variant of a
+workload: sigma_p = max(0.1 sigma0_p, 0.01 THz) from the group velocities.  Seeds: default_rng(251000518 + k)
 with k = 0 springs, 1 cubic, 2 quartic, 3 gradient-component pick, 4 uneven list lengths.
 """
 import functools
@@ -30,6 +31,10 @@ SEED = 251000518
 SIGMA = 2.0 * np.pi * 0.1   # rad/ps
 NSIGMA = 3.0
 OMEGA_FLOOR = 1e-3          # rad/ps
+# adaptive broadening: scale 0.1 (the paper's setting for three- plus
+# four-phonon runs) and a floor of 0.01 THz where the partner velocities coincide
+ADAPTIVE_FACTOR = 0.1
+SIGMA_FLOOR = 2.0 * np.pi * 0.01   # rad/ps
 
 _SPEC = {
     "fcc4_3ph": dict(cell="prim", mesh=4, q1="all", n3=32, n4=0, T=[300.0]),
@@ -117,6 +122,11 @@ def small_config(mesh, n3=32, n4=96, cell="prim", T=(300.0,)):
         sigma=SIGMA, nsigma=NSIGMA, omega_floor=OMEGA_FLOOR, T=np.array(T),
         ifc3=_ifc(cell, 3, n3), ifc4=_ifc(cell, 4, n4),
     )
+
+
+def adaptive_broadening(cfg, factor=ADAPTIVE_FACTOR):
+    """The adaptive-width setting of a workload: {"factor", "recip"} (its floor is SIGMA_FLOOR)."""
+    return {"factor": float(factor), "recip": np.asarray(cfg["recip"], dtype=np.float64)}
 
 
 def row_modes(cfg):

@@ -85,6 +85,48 @@ def test_enumerator_matches_oracle_brute_force(ptype, mesh, sigma, nsigma):
     assert off[-1] > 0
 
 
+def _tilted(cfg):
+    # reciprocal vectors with no symmetry, so a transposed or permuted use shows
+    rng = np.random.default_rng(99)
+    return cfg["recip"] + rng.uniform(-0.3, 0.3, size=(3, 3))
+
+
+ADAPTIVE_CASES = [(fp.FP_3P, (2, 3, 4), 0.5, 0.05), (fp.FP_3M, (2, 3, 4), 0.5, 0.05),
+                  (fp.FP_4PP, (2, 3, 4), 0.5, 0.05), (fp.FP_4PM, (2, 3, 4), 0.5, 0.05),
+                  (fp.FP_4MM, (2, 3, 4), 0.5, 0.05), (fp.FP_3M, 4, 0.1, 0.02), (fp.FP_4PM, 3, 0.1, 0.02),
+                  (fp.FP_4PM, 3, 2.0, 0.3)]
+
+
+@pytest.mark.parametrize("ptype,mesh,factor,floor", ADAPTIVE_CASES)
+def test_enumerator_adaptive_matches_oracle_brute_force(ptype, mesh, factor, floor):
+    """With the per-process width, the enumerator keeps exactly the oracle's set."""
+    cfg = small_config(mesh)
+    b = {"factor": factor, "recip": _tilted(cfg)}
+    rows = row_modes(cfg)
+    if fp.ORDER[ptype] == 4 and np.prod(cfg["mesh"]) > 8:
+        rows = rows[::5]
+    rm, off, rec = fp.enumerate_list(ptype, cfg, row_mode=rows, sigma=floor, broadening=b)
+    S = oracle.System(cfg, broadening=b)
+    want = [S.enumerate_row(ptype, int(g), floor) for g in rows]
+    fixed = fp.enumerate_list(ptype, cfg, row_mode=rows, sigma=floor)[1][-1]
+    assert off[-1] == sum(len(w) for w in want)
+    assert off[-1] > fixed   # the width is the floor's only where velocities coincide
+    for r, w in enumerate(want):
+        np.testing.assert_array_equal(np.sort(rec[off[r]:off[r + 1]]), w)
+
+
+def test_enumerator_adaptive_argument_errors():
+    cfg = small_config(2)
+    ok = {"factor": 0.1, "recip": cfg["recip"]}
+    with pytest.raises(ValueError):
+        fp.fp_enumerate_count(fp.FP_3P, cfg["mesh"], cfg["nb"], cfg["omega"], 1e-3, [5], 1.0, 3.0, broadening=ok)
+    for bad in ({"factor": 0.0, "recip": cfg["recip"]}, {"factor": 0.1, "recip": np.full((3, 3), np.nan)}):
+        with pytest.raises(fp.FpError) as e:
+            fp.fp_enumerate_count(fp.FP_3P, cfg["mesh"], cfg["nb"], cfg["omega"], 1e-3, [5], 1.0, 3.0,
+                                  vel=cfg["vel"], broadening=bad)
+        assert e.value.status == fp.FP_ERR_ARG
+
+
 def test_enumerator_thread_count_invariant_and_momentum():
     cfg = small_config(4)
     rows = row_modes(cfg)[::7]
