@@ -35,11 +35,24 @@
  * Records are one uint64 each (0-based forms of the paper's Ind2/Ind3):
  *   3ph: bits 0-23 g', bits 24-31 j''            (q'' from momentum)
  *   4ph: bits 0-23 g', bits 24-47 g'', bits 48-55 j'''  (q''' from momentum)
+ *   FP_3E   three-phonon events lambda + lambda' -> lambda'' with g' >= g,
+ *           each evaluated once for all three of its modes (see below)
  * Lists are triangle-reduced over interchangeable partners (the paper's
  * triangular iteration domain, Methodology section): FP_3M and FP_4PP keep
  * g' <= g'', FP_4PM keeps g'' <= g''', FP_4MM keeps g' <= g'' <= g'''; the
  * weight of a record (1, 1/2 or 1/6) follows from equality of those indices.
  *
+ * Event lists (FP_3E; the event-symmetric form of the all-modes strategy,
+ * Results): a record has the FP_3P layout plus two flags, bit 32 = the 3+
+ * processes of g and g' pass the filter (mismatch ((w + w') - w'')), bit 33 =
+ * the 3- process of g'' with partners g <= g' passes it ((w'' - w) - w').  Its
+ * one matrix element adds the 3+ rate of g, the 3+ rate of g' (if g' != g) and
+ * the 3- rate of g'' (weight 1/2 if g' == g), each with its own occupations
+ * and Gaussian.  With every active mode of the mesh as a row, FP_3E lists give
+ * the Gamma and WP of FP_3P + FP_3M lists over all modes from a third of the
+ * matrix elements.  The contributions to g' and g'' are added with device
+ * atomics (their rounding depends on timing).  Fixed width only (not with an
+ * adaptive fp_broadening); not accepted by fp_rates_backward.
  * Rates (FP_3P/FP_3M: prefactor pi hbar/(4N), ordered-sum weights 1, 1/2;
  * 4ph: pi hbar^2/(8N^2), weights 1/2, 1/2, 1/6; N = N0*N1*N2):
  *   Gamma_lambda = pref sum_records w |V|^2 occ G(Delta) / prod(omega)
@@ -87,7 +100,7 @@ typedef enum { FP_FP64 = 0, FP_MIXED = 1 } fp_precision;
  * outputs instead of overwriting them (Gamma = Gamma3 + Gamma4 in one pass). */
 #define FP_ACCUMULATE 0x100
 
-typedef enum { FP_3P = 0, FP_3M = 1, FP_4PP = 2, FP_4PM = 3, FP_4MM = 4 } fp_ptype;
+typedef enum { FP_3P = 0, FP_3M = 1, FP_4PP = 2, FP_4PM = 3, FP_4MM = 4, FP_3E = 5 } fp_ptype;
 
 /* Limits: n_modes < 2^24, nb <= 96 (32 atoms), n_T <= 8, lists per call <= 8,
  * lcm(N0, N1, N2) <= 1024, force-constant terms per order <= 4096. */
@@ -184,7 +197,7 @@ typedef struct {
     const uint64_t* rec;      /* [n_rec] packed records */
 } fp_plist;
 
-/* Three-phonon rates over 3ph lists (types FP_3P/FP_3M).  Enqueued on
+/* Three-phonon rates over 3ph lists (types FP_3P/FP_3M/FP_3E).  Enqueued on
  * `hip_stream` (hipStream_t, NULL = default stream); returns after argument
  * checks without waiting for the GPU.  Outputs are DEVICE arrays
  * [n_T][N*nb] in g order, OVERWRITTEN (modes in no row get 0); either may be

@@ -41,6 +41,7 @@ bool type_info(int32_t type, TypeInfo* ti) {
         case FP_4PP: *ti = {4, {1, 1, 1, -1}}; return true;
         case FP_4PM: *ti = {4, {1, 1, -1, -1}}; return true;
         case FP_4MM: *ti = {4, {1, -1, -1, -1}}; return true;
+        case FP_3E: *ti = {3, {1, 1, -1, 0}}; return true;  // events lambda + lambda' -> lambda''
         default: return false;
     }
 }
@@ -57,6 +58,7 @@ inline uint64_t mix64(uint64_t z) {
 
 struct Enum {
     TypeInfo ti;
+    bool events;  // FP_3E
     int64_t N[3], nq;
     int32_t nb;
     const double* omega;
@@ -129,6 +131,7 @@ struct Enum {
                 const int64_t iq2 = index(q2);
                 for (int32_t j1 = 0; j1 < nb; ++j1) {
                     const int64_t g1 = iq1 * nb + j1;
+                    if (events && g1 < g0) continue;  // FP_3E: g' >= g, one record per event
                     const double w1 = omega[g1];
                     if (!(w1 >= floor_)) continue;
                     const double d1 = s[1] > 0 ? w0 + w1 : w0 - w1;
@@ -138,6 +141,17 @@ struct Enum {
                         const double w2 = omega[g2];
                         if (!(w2 >= floor_)) continue;
                         const double delta = s[2] > 0 ? d1 + w2 : d1 - w2;
+                        if (events) {
+                            // the 3+ processes of g and g' (mismatch as in their FP_3P
+                            // lists) and the 3- process of g'' (as in its FP_3M list,
+                            // partners g <= g')
+                            const bool plus = std::fabs(delta) <= cut;
+                            const bool minus = std::fabs((w2 - w0) - w1) <= cut;
+                            if (!plus && !minus) continue;
+                            emit((uint64_t)g1 | ((uint64_t)j2 << 24) | ((uint64_t)plus << 32) |
+                                 ((uint64_t)minus << 33));
+                            continue;
+                        }
                         if (!pass(delta, cut, 3, 0.0, g1, 0, g2)) continue;
                         emit((uint64_t)g1 | ((uint64_t)j2 << 24));
                     }
@@ -208,7 +222,9 @@ fp_status setup(Enum* e, int32_t type, const int32_t mesh[3], int32_t nb, const 
     e->keep_all = keep_fraction >= 1.0;
     e->keep_threshold = e->keep_all ? ~0ULL : (uint64_t)std::ldexp(keep_fraction, 64);
     e->seed = seed;
+    e->events = type == FP_3E;
     e->adaptive = br && br->adaptive;
+    if (e->events && e->adaptive) return FP_ERR_UNSUPPORTED;
     e->sigma = sigma;
     e->nsigma = nsigma;
     e->vel = vel;

@@ -301,6 +301,11 @@ struct RatesArgs {
     int32_t ppl;  // records per lane per unit
     ModeGeom geo;
     Broad br;
+    // three-phonon event lists: the contributions to the partner modes are added
+    // straight into the outputs, scaled by the final prefactors
+    double pref, wpref;
+    double* gamma_out;
+    double* wp_out;
 };
 
 // Pointers travel as separate restrict-qualified arguments so that the compiler
@@ -323,6 +328,7 @@ __device__ inline void type_signs(int type, int& s1, int& s2, int& s3) {
     switch (type) {
         case 0: s1 = 1; s2 = -1; s3 = 0; break;    // 3+
         case 1: s1 = -1; s2 = -1; s3 = 0; break;   // 3-
+        case 5: s1 = 1; s2 = -1; s3 = 0; break;    // 3ph event, as 3+
         case 2: s1 = 1; s2 = 1; s3 = -1; break;    // ++
         case 3: s1 = 1; s2 = -1; s3 = -1; break;   // +-
         default: s1 = -1; s2 = -1; s3 = -1; break; // --
@@ -544,6 +550,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
             const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * NC;
             for (int p0 = 0; p0 * kWave < count; p0 += NP) {
                 Proc pr[NP];
+                uint32_t evf[NP];  // event flags (FP_3E records): bit 0 the 3+ processes, bit 1 the 3- one
 #pragma unroll
                 for (int i = 0; i < NP; ++i) {
                     const int idx = (p0 + i) * kWave + lane;
@@ -551,6 +558,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
                     const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
                     pr[i] = setup_proc<M>(have, rec, type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
                                           flag, a.br);
+                    const bool valid = (int64_t)(rec & 0xFFFFFFu) < a.n_modes && (int32_t)((rec >> 24) & 0xFFu) < nb;
+                    evf[i] = (M == 3 && type == 5 && have && valid) ? (uint32_t)(rec >> 32) & 3u : 0u;
                 }
                 double2 V[NP];
 #pragma unroll
@@ -688,6 +697,43 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
                     }
                 }
 
+                // ---- three-phonon events: one matrix element for all three modes
+                if (M == 3 && type == 5) {
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) {
+                        const double V2 = V[i].x * V[i].x + V[i].y * V[i].y;
+                        const int32_t gb = pr[i].g1, gc = pr[i].gl;
+                        const double wb = omega[gb], wc = omega[gc];
+                        // the 3- process of g'': mismatch (w'' - w) - w', weight 1/2 if g' == g
+                        const double dm = (wc - w0) - wb;
+                        const double bm = (gb == g0 ? 0.5 : 1.0) * exp(-(dm * dm) * a.br.inv_sigma2) * a.br.gnorm /
+                                          (w0 * wb * wc);
+#pragma unroll
+                        for (int it = 0; it < MAXT; ++it) {
+                            if (it < a.n_T && evf[i] != 0u) {
+                                const double* n = occ + (int64_t)it * a.n_modes;
+                                const double na = n[g0], nb_ = n[gb], nc = n[gc];
+                                const int64_t o = (int64_t)it * a.n_modes;
+                                if (evf[i] & 1u) {
+                                    const double xa = pr[i].base * (nb_ - nc);
+                                    accw[it] += xa;
+                                    accg[it] += xa * V2;
+                                    if (gb != g0) {
+                                        const double xb = pr[i].base * (na - nc);
+                                        if (a.gamma_out) atomicAdd(a.gamma_out + o + gb, a.pref * xb * V2);
+                                        if (a.wp_out) atomicAdd(a.wp_out + o + gb, a.wpref * xb);
+                                    }
+                                }
+                                if (evf[i] & 2u) {
+                                    const double xc = bm * (1.0 + na + nb_);
+                                    if (a.gamma_out) atomicAdd(a.gamma_out + o + gc, a.pref * xc * V2);
+                                    if (a.wp_out) atomicAdd(a.wp_out + o + gc, a.wpref * xc);
+                                }
+                            }
+                        }
+                    }
+                    continue;
+                }
                 // ---- occupation per temperature
 #pragma unroll
                 for (int i = 0; i < NP; ++i) {

@@ -200,7 +200,7 @@ int64_t gcd64(int64_t a, int64_t b) {
 
 int64_t wrapi(int64_t x, int64_t n) { return ((x % n) + n) % n; }
 
-int ORDER_OF(int32_t type) { return type == FP_3P || type == FP_3M ? 3 : 4; }
+int ORDER_OF(int32_t type) { return type == FP_3P || type == FP_3M || type == FP_3E ? 3 : 4; }
 
 fpk::ModeGeom geometry(const fp_ctx* c) {
     fpk::ModeGeom g;
@@ -666,7 +666,7 @@ fp_status check_common(fp_ctx* c, int n_lists, const fp_plist* lists, int32_t n_
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(c, FP_ERR_ARG, "sigma must be > 0");
     for (int l = 0; l < n_lists; ++l) {
         const fp_plist& P = lists[l];
-        if (P.type < FP_3P || P.type > FP_4MM) return fail(c, FP_ERR_ARG, "list %d has unknown type %d", l, P.type);
+        if (P.type < FP_3P || P.type > FP_3E) return fail(c, FP_ERR_ARG, "list %d has unknown type %d", l, P.type);
         if (P.n_rows < 0 || P.n_rec < 0) return fail(c, FP_ERR_ARG, "list %d: negative size", l);
         if (P.n_rows > 0 && (!P.row_mode || !P.row_off)) return fail(c, FP_ERR_ARG, "list %d: null row arrays", l);
         if (P.n_rec > 0 && !P.rec) return fail(c, FP_ERR_ARG, "list %d: null records", l);
@@ -776,6 +776,8 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     for (int l = 0; l < n_lists; ++l) {
         if (ORDER_OF(lists[l].type) != m)
             return fail(c, FP_ERR_ARG, "list %d has type %d, not of order %d", l, lists[l].type, m);
+        if (lists[l].type == FP_3E && c->adaptive)
+            return fail(c, FP_ERR_UNSUPPORTED, "event lists take the fixed width only");
         sel.push_back(l);
     }
     const int np = m == 3 ? 1 : kVariants[c->variant].np;
@@ -808,6 +810,10 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     a.ppl = (int32_t)ppl;
     a.geo = pp.geo;
     a.br = make_broad(c, sigma);
+    a.pref = rate_prefactor(c, m);
+    a.wpref = m == 3 ? 1.0 / (double)c->nq : 1.0 / ((double)c->nq * (double)c->nq);
+    a.gamma_out = gamma_out;
+    a.wp_out = wp_out;
     const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
     if (mixed) {
         const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
@@ -1105,6 +1111,8 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
     if (!c) return FP_ERR_ARG;
     fp_status cs = check_common(c, n_lists, lists, n_T, T_K, sigma);
     if (cs != FP_OK) return cs;
+    for (int l = 0; l < n_lists; ++l)
+        if (lists[l].type == FP_3E) return fail(c, FP_ERR_UNSUPPORTED, "the adjoint takes per-mode lists, not events");
     const bool accumulate = (precision & FP_ACCUMULATE) != 0;
     precision &= ~FP_ACCUMULATE;
     if (precision != FP_FP64 && precision != FP_MIXED) return fail(c, FP_ERR_ARG, "unknown precision %d", precision);

@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libfp.so")
 FP_OK, FP_ERR_ARG, FP_ERR_STATE, FP_ERR_RANGE, FP_ERR_NOMEM, FP_ERR_HIP, FP_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FP_FP64, FP_MIXED = 0, 1
 FP_ACCUMULATE = 0x100
-FP_3P, FP_3M, FP_4PP, FP_4PM, FP_4MM = 0, 1, 2, 3, 4
-ORDER = {FP_3P: 3, FP_3M: 3, FP_4PP: 4, FP_4PM: 4, FP_4MM: 4}
+FP_3P, FP_3M, FP_4PP, FP_4PM, FP_4MM, FP_3E = 0, 1, 2, 3, 4, 5
+ORDER = {FP_3P: 3, FP_3M: 3, FP_4PP: 4, FP_4PM: 4, FP_4MM: 4, FP_3E: 3}
 FP_MAX_T = 8
 FP_MAX_LISTS = 8
 

@@ -127,6 +127,46 @@ def test_enumerator_adaptive_argument_errors():
         assert e.value.status == fp.FP_ERR_ARG
 
 
+@pytest.mark.parametrize("mesh,sigma", [(3, 2.0), (4, 0.6283185307179586), ((2, 3, 4), 1.5)])
+def test_event_lists_are_the_union_of_the_oracle_per_mode_lists(mesh, sigma):
+    """FP_3E: one record per event a + b -> c (g_b >= g_a) for every event whose
+    3+ processes (of a and b) or 3- process (of c) the oracle's brute-force
+    enumeration keeps, flagged by which."""
+    cfg = small_config(mesh)
+    rows = row_modes(cfg)
+    rm, off, rec = fp.enumerate_list(fp.FP_3E, cfg, row_mode=rows, sigma=sigma)
+    S = oracle.System(cfg)
+    nb = cfg["nb"]
+    m3 = np.asarray(cfg["mesh"])
+    coords = mesh_coords(m3)
+    want = {}
+    for a in rows:
+        for r in S.enumerate_row(fp.FP_3P, int(a), sigma):
+            if (int(r) & 0xFFFFFF) >= a:
+                want.setdefault((int(a), int(r)), [0, 0])[0] = 1
+    for c in rows:
+        for r in S.enumerate_row(fp.FP_3M, int(c), sigma):
+            a, jb = int(r) & 0xFFFFFF, (int(r) >> 24) & 0xFF
+            qb = np.mod(coords[int(c) // nb] - coords[a // nb], m3)   # q_c = q_a + q_b
+            b = int((qb[0] * m3[1] + qb[1]) * m3[2] + qb[2]) * nb + jb
+            assert b >= a
+            want.setdefault((a, b | ((int(c) % nb) << 24)), [0, 0])[1] = 1
+    got = {}
+    for r in range(len(rm)):
+        for x in rec[off[r]:off[r + 1]]:
+            x = int(x)
+            got[(int(rm[r]), x & 0xFFFFFFFF)] = [(x >> 32) & 1, (x >> 33) & 1]
+    assert len(got) == int(off[-1]) > 0
+    assert got == want
+
+
+def test_event_lists_reject_adaptive_width():
+    cfg = small_config(2)
+    with pytest.raises(fp.FpError) as e:
+        fp.enumerate_list(fp.FP_3E, cfg, row_mode=[5], broadening={"factor": 0.1, "recip": cfg["recip"]})
+    assert e.value.status == fp.FP_ERR_UNSUPPORTED
+
+
 def test_enumerator_thread_count_invariant_and_momentum():
     cfg = small_config(4)
     rows = row_modes(cfg)[::7]
