@@ -312,8 +312,8 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *                    (lambda, q', q'') tuple on FP64 MFMA, then per-process
  *                    contraction) with two records per lane (4),
  *                    one (5), or two with 24-tuple batches and three resident
- *                    blocks per CU (6), or three records per lane (7, the
- *                    default)
+ *                    blocks per CU (6, the default), or three records per
+ *                    lane (7)
  *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);

@@ -25,6 +25,24 @@ constexpr int kBU = 128;            // records per unit
 constexpr int kBR = kBU / kWave;    // records per lane
 constexpr int kTB = 32;             // tuples staged per batch
 constexpr int kMaxKs = 4;           // K-steps of four terms per partner group (groups hold <= 16 terms)
+constexpr int kStageTerms = 512;    // term tables up to this size are staged in LDS
+
+// Dynamic LDS of the tuple-batched kernels: the root table (L entries), then the
+// term table (8 int32 per term) when it has at most kStageTerms terms.
+inline size_t tb_dyn_lds(int32_t L, int64_t n_terms) {
+    return (size_t)L * sizeof(double2) + (n_terms <= kStageTerms ? (size_t)n_terms * 8 * sizeof(int32_t) : 0);
+}
+
+// Copy the root table (and the term table when it fits) into the block's
+// dynamic LDS; returns the term table to read, staged or global.
+__device__ inline const int32_t* tb_stage(double2* sroots, const double2* __restrict__ roots, int32_t L,
+                                          const int32_t* __restrict__ tmeta, int32_t n_terms) {
+    for (int i = threadIdx.x; i < L; i += kBlock) sroots[i] = roots[i];
+    if (n_terms > kStageTerms) return tmeta;
+    int32_t* stm = reinterpret_cast<int32_t*>(sroots + L);
+    for (int i = threadIdx.x; i < n_terms * 8; i += kBlock) stm[i] = tmeta[i];
+    return stm;
+}
 
 
 // One batch of up to 128 consecutive records of one row (two per lane, record
@@ -89,7 +107,6 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
         const int n_ks = (t1 - t0 + 3) >> 2;  // <= kMaxKs: groups hold at most 16 terms
         // this group's force constants and phase vectors for every K-step, one load
         double2 Fk[kMaxKs][2];
-        int32_t tmk[kMaxKs][6];
         bool kv[kMaxKs];
 #pragma unroll
         for (int ks = 0; ks < kMaxKs; ++ks) {
@@ -100,9 +117,6 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
                 const int comp = mt * 16 + li;
                 Fk[ks][mt] = (kv[ks] && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
             }
-            const int32_t* tmp = tmeta + (kv[ks] ? term : t0) * 8;
-#pragma unroll
-            for (int d = 0; d < 6; ++d) tmk[ks][d] = tmp[1 + d];
         }
         // with one record per lane, this group's partner eigenvector components are
         // loaded here, together with the force constants, so that one memory
@@ -141,6 +155,10 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
             // MFMAs (Karatsuba):
             //   k1 = (Fr + Fi) pr,  k2 = Fr (pi - pr),  k3 = Fi (pr + pi),
             //   Re = k1 - k3,  Im = k1 + k2.
+            // the contraction below waits on gathers and LDS reads; it takes issue
+            // priority over this MFMA phase, which another wave of the SIMD can
+            // then fill
+            __builtin_amdgcn_s_setprio(0);
             const int n_nt = (nbt + 15) >> 4;  // <= TB / 16
             for (int nt = 0; nt < n_nt; ++nt) {
                 const int tj = nt * 16 + li;
@@ -164,8 +182,9 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
                     double2 ph = make_double2(0.0, 0.0);
                     if (kv[ks] && tval) {
                         uint32_t kk = 0;
+                        const int32_t* tmp = tmeta + (t0 + 4 * ks + lk) * 8;
 #pragma unroll
-                        for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[d] * tmk[ks][d]);
+                        for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[d] * tmp[1 + d]);
                         ph = sroots[mod_l(kk, geo.L, geo.magic)];
                     }
                     const double pd = ph.y - ph.x, ps = ph.x + ph.y;
@@ -189,7 +208,9 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
                 }
             }
             lds_fence();
-            // per-process contraction with this group's partner eigenvectors
+            __builtin_amdgcn_s_setprio(3);
+            // per-process contraction with this group's partner eigenvectors, one
+            // record at a time (no hoisting of later records' gathers)
 #pragma unroll
             for (int k = 0; k < BR; ++k) {
                 const int s = slot[k] - tb;
@@ -229,6 +250,7 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
                     V[k].x += acc.x;
                     V[k].y += acc.y;
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
             lds_fence();
         }
@@ -275,7 +297,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_rates4b(FP_RATES_PARAMS, const 
     extern __shared__ double2 sroots[];
     __shared__ double2 sA[kWavesPerBlock][TB][27];
     __shared__ int32_t sQ[kWavesPerBlock][TB][2];
-    for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
+    const int32_t* tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_terms);
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -306,7 +328,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_rates4b(FP_RATES_PARAMS, const 
             double dl[MAXT];
 #pragma unroll
             for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
-            tb_batch<MAXT, GRAD, BR, TB>(rec, count, g0, type, phit + (int64_t)row * a.n_terms * 27, omega, evec, occ, tmeta,
+            tb_batch<MAXT, GRAD, BR, TB>(rec, count, g0, type, phit + (int64_t)row * a.n_terms * 27, omega, evec, occ, tm,
                                  groups, flag, a, sroots, sA[wave], sQ[wave], accg, accw, dl, pref,
                                  GRAD ? hbuf + ri.hbase + ud.start : nullptr);
         }

@@ -83,10 +83,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                                                      int64_t* __restrict__ unit_kept, int* __restrict__ flag,
                                                      RatesArgs a, FusedArgs f) {
     constexpr int NB = kFusedNb;
-    __shared__ double2 sroots[kMaxRoots];
+    extern __shared__ double2 sroots[];
     __shared__ double2 sA[kWavesPerBlock][kTB][27];
     __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
-    for (int i = threadIdx.x; i < a.geo.L; i += kBlock) sroots[i] = roots[i];
+    const int32_t* tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_terms);
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                         const uint64_t g2 = (uint64_t)((start + lo) * NB + j2);
                         rec[k] = p < total ? (g1 | (g2 << 24) | ((uint64_t)j3 << 48)) : 0;
                     }
-                    tb_batch<MAXT, false>(rec, count, g0, type, phit_row, omega, evec, occ, tmeta, groups, flag, a,
+                    tb_batch<MAXT, false>(rec, count, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
                                           sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
                 }
             }

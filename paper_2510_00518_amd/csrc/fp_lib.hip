@@ -161,7 +161,7 @@ struct fp_ctx {
     // tuning knobs
     int32_t ppl = 2;
     int32_t blocks_per_cu = 0;  // 0: as many resident blocks as the kernel's occupancy allows
-    int32_t variant = 7;        // order-4 contraction form: 0-3 per-process (k_rates), 4-7 tuple-batched
+    int32_t variant = 6;        // order-4 contraction form: 0-3 per-process (k_rates), 4-7 tuple-batched
     int32_t grad_chunk = 8192;  // records per adjoint chunk (a multiple of 256)
     // kernel timing
     bool profile = false;
@@ -600,7 +600,7 @@ fp_status launch_mixed_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::
 template <int T, int BR, int TB, int OCC>
 fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
     auto kern = fpk::k_rates4b<T, false, BR, TB, OCC>;
-    const size_t shm = (size_t)c->L * sizeof(double2);
+    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
@@ -616,12 +616,13 @@ fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::
 }
 
 // First half of the order-4 adjoint: h_p = c_p conj(V_p) per record, by the
-// tuple-batched kernel over units of 128 records.
+// tuple-batched kernel over units of 128 records (24-tuple batches, three
+// resident blocks per CU).
 template <int T>
 fp_status launch_batched_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S,
                            const double* dldg, double pref) {
-    auto kern = fpk::k_rates4b<T, true, 3, 32, 2>;
-    const size_t shm = (size_t)c->L * sizeof(double2);
+    auto kern = fpk::k_rates4b<T, true, 2, 24, 3>;
+    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
@@ -922,14 +923,15 @@ template <int T>
 fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const fpk::FusedArgs& f,
                        const IfcState& S) {
     auto kern = fpk::k_fused4<T>;
+    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
     int occ = 0;
-    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, 0));
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
     const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
     const int64_t want = (f.n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->partial.p, c->unit_kept.p, c->flag,
                        a, f);
     HIP_TRY(c, hipGetLastError());
@@ -1149,8 +1151,8 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
         fp_status ps;
         if (m == 4 && n_rec > 0) {
             // first half: h_p = c_p conj(V_p) for every record (tuple-batched, units of
-            // 192 records; mixed precision: units of 128)
-            ps = prepare(c, m, lists, sel, n_T, T_K, (mixed ? fpk::kBR : 3) * fpk::kWave, st, &pp);
+            // 128 records, FP64 or mixed precision)
+            ps = prepare(c, m, lists, sel, n_T, T_K, fpk::kBR * fpk::kWave, st, &pp);
             if (ps != FP_OK) return ps;
             HIP_TRY(c, c->hbuf.ensure((size_t)n_rec));
             fpk::RatesArgs ra;
@@ -1160,7 +1162,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
             ra.n_terms = (int32_t)S.n_terms;
             ra.n_groups = S.n_groups;
             ra.n_T = n_T;
-            ra.ppl = mixed ? fpk::kBR : 3;
+            ra.ppl = fpk::kBR;
             ra.geo = pp.geo;
             ra.br = make_broad(c, sigma);
             const double pref4 = rate_prefactor(c, m);
