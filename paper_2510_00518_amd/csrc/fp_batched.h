@@ -244,6 +244,8 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
 #pragma unroll
                             for (int d = 0; d < 3; ++d) vc = cfma(vc, A[s][(b * 3 + c) * 3 + d], z[d]);
                             ub = cfma(ub, vc, y[c]);
+                            // three LDS reads per step: hoisting all 27 would spill
+                            __builtin_amdgcn_sched_barrier(0);
                         }
                         acc = cfma(acc, ub, x[b]);
                     }
