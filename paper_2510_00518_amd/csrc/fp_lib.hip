@@ -1349,6 +1349,10 @@ extern "C" fp_status fp_rates_streamed(fp_ctx* c, int32_t type_mask, int64_t n_r
     }
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
+    // a previous call that stopped on an error may have left copies from the
+    // staging slots in flight
+    for (StreamSlot& sl : c->slot)
+        if (sl.done) HIP_TRY(c, hipEventSynchronize(sl.done));
     const int64_t nm = c->n_modes;
     if (!accumulate) {
         if (gamma_out)
@@ -1454,15 +1458,15 @@ extern "C" fp_status fp_rates_streamed(fp_ctx* c, int32_t type_mask, int64_t n_r
                                   st));
         HIP_TRY(c, hipMemcpyAsync(sl.doff.p, sl.off.p, (size_t)opos * sizeof(int64_t), hipMemcpyHostToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(sl.dmode.p, sl.mode.p, (size_t)mpos * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        if (n3 > 0) {
-            fp_status s = run_rates(c, 3, l3, n3, n_T, T_K, sigma, prec | FP_ACCUMULATE, gamma_out, wp_out, stream);
-            if (s != FP_OK) return s;
-        }
-        if (n4 > 0) {
-            fp_status s = run_rates(c, 4, l4, n4, n_T, T_K, sigma, prec | FP_ACCUMULATE, gamma_out, wp_out, stream);
-            if (s != FP_OK) return s;
-        }
+        fp_status rs = FP_OK;
+        if (n3 > 0) rs = run_rates(c, 3, l3, n3, n_T, T_K, sigma, prec | FP_ACCUMULATE, gamma_out, wp_out, stream);
+        if (rs == FP_OK && n4 > 0)
+            rs = run_rates(c, 4, l4, n4, n_T, T_K, sigma, prec | FP_ACCUMULATE, gamma_out, wp_out, stream);
         HIP_TRY(c, hipEventRecord(sl.done, st));
+        if (rs != FP_OK) {
+            (void)hipStreamSynchronize(st);
+            return rs;
+        }
     }
     t0 = Clock::now();
     HIP_TRY(c, hipStreamSynchronize(st));
