@@ -107,13 +107,18 @@ def partner_groups(ifc):
     return len({tuple(a[1:]) for a in np.asarray(ifc["atoms"]).tolist()})
 
 
-def paper_scale(torch, fp, RatePath):
+def paper_scale(torch, fp, RatePath, adaptive=False):
     """The 16^3 two-atom cell: every active row and the three four-phonon types
-    in one fp_rates4_fused call (lists generated on the GPU), T = 300/600/900 K."""
-    from paper_2510_00518_amd.synth import make_config, row_modes
+    in one fp_rates4_fused call (lists generated on the GPU), T = 300/600/900 K;
+    with adaptive, the per-process width max(0.1 sigma0_p, 0.01 THz)."""
+    from paper_2510_00518_amd.synth import SIGMA_FLOOR, adaptive_broadening, make_config, row_modes
     cfg = make_config("fcc16_34ph")
+    if adaptive:
+        cfg = dict(cfg, sigma=SIGMA_FLOOR)
     T = [float(x) for x in cfg["T"]]
     p = RatePath(cfg, device=0)
+    if adaptive:
+        p.set_broadening(adaptive_broadening(cfg))
     p.set_fused(row_modes(cfg), 7)
     gam, wp = p.outputs(len(T))
     p.load_ifc()
@@ -128,9 +133,11 @@ def paper_scale(torch, fp, RatePath):
     fp.fp_check(p.ctx)
     kept = int(p.kept.cpu()[0])
     p.close()
-    log(f"bench: 16^3 fused: {kept} processes in {dt:.2f} s")
+    log(f"bench: 16^3 fused{' adaptive' if adaptive else ''}: {kept} processes in {dt:.2f} s")
+    width = "adaptive width max(0.1 sigma0, 0.01 THz)" if adaptive else "sigma 0.1 THz"
     return {"workload": "4ph FP64, 2-atom diamond cell, 16x16x16 mesh, Oh-irreducible q1 (145), 62 cubic + "
-                        f"{int(cfg['ifc4']['n_terms'])} quartic terms, T = 300/600/900 K, lists generated on the GPU",
+                        f"{int(cfg['ifc4']['n_terms'])} quartic terms, T = 300/600/900 K, {width}, "
+                        "lists generated on the GPU",
             "processes_4ph": kept, "seconds": dt, "value": kept / dt, "unit": "processes/s",
             "kernel_ms": k_ms / max(1, n), "rows": int(len(row_modes(cfg)))}
 
@@ -172,6 +179,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--paper-scale-adaptive", action="store_true",
+                    help="also run the 16^3 cell with the adaptive width (about a minute)")
     ap.add_argument("--paper-scale", action="store_true",
                     help="also run the 16^3 two-atom cell through GPU-side enumeration (about a minute)")
     ap.add_argument("--ppl", type=int, default=None)
@@ -374,6 +383,8 @@ def main():
     }
     if args.paper_scale:
         out["paper_scale"] = paper_scale(torch, fp, RatePath)
+    if args.paper_scale_adaptive:
+        out["paper_scale_adaptive"] = paper_scale(torch, fp, RatePath, adaptive=True)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cfg, lists, args.cpu_seconds)

@@ -178,8 +178,9 @@ fp_status fp_load_ifc(fp_ctx* ctx, int32_t order, int64_t n_terms, const int32_t
  * The context keeps the per-mode projections v . b_d / N_d on the device
  * (computed here by a kernel, synchronously).  Requires fp_load_modes with
  * velocities (FP_ERR_STATE).  FP_ERR_ARG for factor <= 0, a non-finite
- * reciprocal vector or adaptive outside {0, 1}.  fp_rates4_fused supports only
- * the fixed width (FP_ERR_UNSUPPORTED while adaptive is set). */
+ * reciprocal vector or adaptive outside {0, 1}.  fp_rates4_fused applies the
+ * same rule in its on-GPU filter (the same operations in the same order,
+ * correctly rounded), so its kept set equals the host enumerator's. */
 fp_status fp_set_broadening(fp_ctx* ctx, const fp_broadening* broadening);
 
 /* One CSR process list: the rows are modes lambda (the paper's mm loop), the

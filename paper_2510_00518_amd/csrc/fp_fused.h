@@ -32,7 +32,74 @@ struct FusedArgs {
     int32_t n_types;
     int32_t types[3];
     double floor_, cut;
+    // adaptive width (the ADAPT instantiation): sigma_p = max(factor sigma0_p,
+    // sigma); a candidate with cut < |Delta| <= cut_max has its width evaluated
+    // exactly as the host enumerator does
+    const double* vel;
+    double recip[9];
+    double factor, sigma, nsigma, cut_max;
 };
+
+// |Delta| <= nsigma * sigma_p for partners g1, g2, g3 of a four-phonon process,
+// evaluated as the host enumerator evaluates it: pairs (1,2), (1,3), (2,3),
+// each projection ((v_i - v_j) . b_d) / N_d, d = 0, 1, 2, summed left to right
+// in double precision without contraction; correctly rounded square root and
+// division.
+__device__ inline double fused_pair_sq(double s2, const double* __restrict__ vel, int32_t gi, int32_t gj,
+                                       const FusedArgs& f, const ModeGeom& geo) {
+#pragma clang fp contract(off)
+    const double w0 = vel[gi * 3] - vel[gj * 3];
+    const double w1 = vel[gi * 3 + 1] - vel[gj * 3 + 1];
+    const double w2 = vel[gi * 3 + 2] - vel[gj * 3 + 2];
+    const double n[3] = {(double)geo.N0, (double)geo.N1, (double)geo.N2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double p = (w0 * f.recip[d * 3] + w1 * f.recip[d * 3 + 1] + w2 * f.recip[d * 3 + 2]) / n[d];
+        s2 = s2 + p * p;
+    }
+    return s2;
+}
+
+// max over the branches of one q-point of |v . b_d| / N_d, d = 0, 1, 2: bounds
+// the pair projections of the adaptive width from above
+__device__ inline void fused_proj_max(const double* __restrict__ vel, int32_t iq, const FusedArgs& f,
+                                      const ModeGeom& geo, double (&pm)[3]) {
+    const double n[3] = {(double)geo.N0, (double)geo.N1, (double)geo.N2};
+    pm[0] = pm[1] = pm[2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < kFusedNb; ++j) {
+        const double* v = vel + ((int64_t)iq * kFusedNb + j) * 3;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            pm[d] = fmax(pm[d], fabs(v[0] * f.recip[d * 3] + v[1] * f.recip[d * 3 + 1] + v[2] * f.recip[d * 3 + 2]) / n[d]);
+    }
+}
+
+// Largest nsigma * sigma_p any branch triple of the q-points with projection
+// bounds p1, p2, p3 can reach (with a margin far above rounding).
+__device__ inline double fused_cut_bound(const double (&p1)[3], const double (&p2)[3], const double (&p3)[3],
+                                         const FusedArgs& f) {
+    double b2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double a = p1[d] + p2[d], b = p1[d] + p3[d], c = p2[d] + p3[d];
+        b2 += a * a + b * b + c * c;
+    }
+    const double sp = fmax(f.factor * sqrt(b2 / 9.0), f.sigma);
+    return fmin(f.nsigma * sp * (1.0 + 1e-9), f.cut_max);
+}
+
+// not inlined: the filter loop is unrolled over the 216 branch triples, and the
+// exact width is needed only for the few candidates between the two cuts
+__device__ __noinline__ bool fused_adaptive_pass(double ad, int32_t g1, int32_t g2, int32_t g3, const FusedArgs& f,
+                                           const ModeGeom& geo) {
+#pragma clang fp contract(off)
+    double s2 = fused_pair_sq(0.0, f.vel, g1, g2, f, geo);
+    s2 = fused_pair_sq(s2, f.vel, g1, g3, f, geo);
+    s2 = fused_pair_sq(s2, f.vel, g2, g3, f, geo);
+    const double sp = f.factor * __builtin_sqrt(s2 / 9.0);
+    return ad <= f.nsigma * (sp > f.sigma ? sp : f.sigma);
+}
 
 // Row and unit tables of a fused call: fused row fr = ti * n_rows + r.
 __global__ void k_fused_rows(const int32_t* __restrict__ row_mode, FusedArgs f, int64_t nq, int64_t n_modes,
@@ -73,7 +140,7 @@ __device__ inline int select_bit(uint64_t w, int n) {
     return pos;
 }
 
-template <int MAXT>
+template <int MAXT, bool ADAPT>
 __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
                                                      const double* __restrict__ occ, const double2* __restrict__ roots,
                                                      const double2* __restrict__ phit,
@@ -125,6 +192,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
             double w1[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) w1[j] = omega[iq1 * NB + j];
+            double pm1[3] = {0.0, 0.0, 0.0};
+            if (ADAPT) fused_proj_max(f.vel, iq1, f, geo, pm1);
 
             for (int32_t start = tri12 ? iq1 : 0; start < nq; start += kWave) {
                 // ---- candidate masks: lane = q''
@@ -143,6 +212,15 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                         w2[j] = omega[iq2 * NB + j];
                         w3[j] = omega[iq3 * NB + j];
                     }
+                    // adaptive width: a bound for this triple of q-points, so the
+                    // exact width is evaluated only where it can matter
+                    double cut_q = f.cut;
+                    if (ADAPT) {
+                        double pm2[3], pm3[3];
+                        fused_proj_max(f.vel, iq2, f, geo, pm2);
+                        fused_proj_max(f.vel, iq3, f, geo, pm3);
+                        cut_q = fused_cut_bound(pm1, pm2, pm3, f);
+                    }
 #pragma unroll
                     for (int j1 = 0; j1 < NB; ++j1) {
                         const int32_t g1 = iq1 * NB + j1;
@@ -157,8 +235,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                             for (int j3 = 0; j3 < NB; ++j3) {
                                 const int32_t g3 = iq3 * NB + j3;
                                 const double delta = s3 > 0 ? d2 + w3[j3] : d2 - w3[j3];
-                                const bool keep = ok2 && !(tri23 && g3 < g2) && w3[j3] >= f.floor_ &&
-                                                  fabs(delta) <= f.cut;
+                                bool keep = ok2 && !(tri23 && g3 < g2) && w3[j3] >= f.floor_;
+                                if (keep) {
+                                    const double ad = fabs(delta);
+                                    // sigma_p >= sigma, so the fixed cut keeps without the width
+                                    keep = ad <= f.cut;
+                                    if (ADAPT && !keep && ad <= cut_q)
+                                        keep = fused_adaptive_pass(ad, g1, g2, g3, f, geo);
+                                }
                                 const int c = (j1 * NB + j2) * NB + j3;
                                 if (keep) m[c >> 6] |= 1ull << (c & 63);
                             }

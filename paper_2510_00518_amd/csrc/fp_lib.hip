@@ -922,7 +922,7 @@ namespace {
 template <int T>
 fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const fpk::FusedArgs& f,
                        const IfcState& S) {
-    auto kern = fpk::k_fused4<T>;
+    auto kern = f.vel ? fpk::k_fused4<T, true> : fpk::k_fused4<T, false>;
     const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
@@ -948,7 +948,6 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     IfcState& S = c->ifc[1];
     if (S.order != 4) return fail(c, FP_ERR_STATE, "force constants of order 4 not loaded");
     if (c->nb != fpk::kFusedNb) return fail(c, FP_ERR_UNSUPPORTED, "the fused path is built for nb = 6 (two atoms)");
-    if (c->adaptive) return fail(c, FP_ERR_UNSUPPORTED, "the fused path takes the fixed width only");
     if (n_rows < 0 || (n_rows > 0 && !row_mode)) return fail(c, FP_ERR_ARG, "bad row list");
     if (type_mask < 1 || type_mask > 7) return fail(c, FP_ERR_ARG, "type_mask must be in [1, 7]");
     if (n_T < 1 || n_T > FP_MAX_T || !T_K) return fail(c, FP_ERR_ARG, "n_T must be in [1, %d]", FP_MAX_T);
@@ -978,6 +977,26 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     f.n_units = (int64_t)f.n_types * n_rows * c->nq;
     f.floor_ = c->floor_;
     f.cut = nsigma * sigma;
+    if (c->adaptive) {
+        // the enumerator's rule; cut_max bounds nsigma * sigma_p over every process
+        f.vel = c->vel.p;
+        for (int i = 0; i < 9; ++i) f.recip[i] = c->bro.recip[i];
+        f.factor = c->bro.factor;
+        f.sigma = sigma;
+        f.nsigma = nsigma;
+        double pmax[3] = {0.0, 0.0, 0.0};
+        for (int64_t g = 0; g < nm; ++g)
+            for (int d = 0; d < 3; ++d) {
+                const double* v = c->h_vel.data() + g * 3;
+                const double p = std::fabs(v[0] * f.recip[d * 3] + v[1] * f.recip[d * 3 + 1] + v[2] * f.recip[d * 3 + 2]) /
+                                 (double)c->mesh[d];
+                pmax[d] = std::max(pmax[d], p);
+            }
+        double b2 = 0.0;
+        for (int d = 0; d < 3; ++d) b2 += 4.0 * pmax[d] * pmax[d];
+        const double smax = std::max(f.factor * std::sqrt(3.0 * b2 / 9.0), sigma);
+        f.cut_max = nsigma * smax * (1.0 + 1e-9);
+    }
     const int64_t n_frows = (int64_t)f.n_types * n_rows;
     HIP_TRY(c, c->occ.ensure((size_t)n_T * nm));
     HIP_TRY(c, c->rows.ensure((size_t)n_frows));

@@ -187,21 +187,17 @@ def test_adaptive_errors_and_reset(ctx):
         with pytest.raises(fp.FpError) as e:
             p.set_broadening(bad)
         assert e.value.status == fp.FP_ERR_ARG
-    # the fused enumeration takes the fixed width only
     p.set_broadening(tilted(cfg))
     p.load_ifc(phi4=p.phi4)
     rows = torch.as_tensor(np.asarray(row_modes(cfg)[:2], np.int32)).cuda()
     gam = torch.zeros((1, p.n_modes), dtype=torch.float64, device="cuda")
-    with pytest.raises(fp.FpError) as e:
-        fp.fp_rates4_fused(ctx, rows, 7, [300.0], cfg["sigma"], 3.0, fp.FP_FP64, gam)
-    assert e.value.status == fp.FP_ERR_UNSUPPORTED
     # without velocities there is nothing to take the width from
     fp.fp_load_modes(ctx, cfg["mesh"], cfg["n_atoms"], cfg["lattice"], cfg["masses"], cfg["omega"], cfg["evec"],
                      None, cfg["omega_floor"])
     with pytest.raises(fp.FpError) as e:
         fp.fp_set_broadening(ctx, tilted(cfg))
     assert e.value.status == fp.FP_ERR_STATE
-    # a new load of the modes returns to the fixed width: the fused path runs again
+    # a new load of the modes returns to the fixed width
     p = RatePath(cfg, ctx=ctx)
     p.load_ifc(phi4=p.phi4)
     fp.fp_rates4_fused(ctx, rows, 7, [300.0], cfg["sigma"], 3.0, fp.FP_FP64, gam)

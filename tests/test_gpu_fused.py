@@ -97,6 +97,80 @@ def test_fused_matches_oracle_brute_force(ctx, mesh, sigma, stride):
     assert_modes(w, wo, "WP4")
 
 
+@pytest.mark.parametrize("mesh,factor,floor,stride", [(4, 0.5, 0.3, 13), ((2, 3, 4), 0.7, 0.2, 5), (3, 2.0, 0.5, 4)])
+def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride):
+    """Adaptive width in the on-GPU filter: the kept count equals the oracle's
+    adaptive enumeration exactly, and the rates its list-mode sums."""
+    import torch
+    from paper_2510_00518_amd.driver import RatePath
+    cfg = small_config(mesh)
+    rng = np.random.default_rng(99)
+    b = {"factor": factor, "recip": cfg["recip"] + rng.uniform(-0.3, 0.3, size=(3, 3))}
+    rows = np.asarray(row_modes(cfg)[::stride], np.int32)
+    T = [300.0, 900.0]
+    p = RatePath(dict(cfg, sigma=floor), ctx=ctx)
+    p.set_broadening(b)
+    p.set_fused(rows, 7)
+    gam, wp = p.outputs(len(T))
+    p.load_ifc()
+    p.rates(T, gam, wp, order=4)
+    fp.fp_check(ctx)
+    torch.cuda.synchronize()
+    kept = int(p.kept.cpu()[0])
+    S = oracle.System(cfg, broadening=b)
+    n = cfg["omega"].size
+    go, wo = np.zeros((len(T), n)), np.zeros((len(T), n))
+    ko = 0
+    for t in TYPES4:
+        recs = [S.enumerate_row(t, int(g), floor, cfg["nsigma"]) for g in rows]
+        off = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
+        ko += int(off[-1])
+        if off[-1]:
+            g, w, _, _ = S.rates(t, rows, T, floor, cfg["nsigma"], row_off=off, rec=np.concatenate(recs).astype(np.uint64))
+            go[:, rows] += g.T
+            wo[:, rows] += w.T
+    say(f"fused adaptive {mesh}: {kept} processes (oracle {ko})")
+    assert kept == ko
+    assert_modes(gam.cpu().numpy(), go, "Gamma4 adaptive")
+    assert_modes(wp.cpu().numpy(), wo, "WP4 adaptive")
+
+
+@pytest.mark.slow
+def test_fused_adaptive_fcc8_against_lists(ctx):
+    """8^3 workload with a = 0.1 and a 0.01 THz floor: the fused launch against
+    the list-driven path on the host enumerator's adaptive lists."""
+    import torch
+    from paper_2510_00518_amd.driver import RatePath, host_lists
+    from paper_2510_00518_amd.synth import SIGMA_FLOOR, adaptive_broadening
+    cfg = make_config("fcc8_4ph")
+    b = adaptive_broadening(cfg)
+    lists = host_lists(cfg, TYPES4, sigma=SIGMA_FLOOR, broadening=b)
+    n_rec = sum(int(v[1][-1]) for v in lists.values())
+    p = RatePath(dict(cfg, sigma=SIGMA_FLOOR), ctx=ctx)
+    p.set_broadening(b)
+    p.set_lists(lists)
+    gam, _ = p.outputs(1)
+    p.load_ifc()
+    p.rates([300.0], gam, order=4)
+    torch.cuda.synchronize()
+    g_list = gam.cpu().numpy()
+    del lists
+    q = RatePath(dict(cfg, sigma=SIGMA_FLOOR), ctx=ctx)
+    q.set_broadening(b)
+    q.set_fused(row_modes(cfg), 7)
+    gam2, _ = q.outputs(1)
+    q.load_ifc()
+    t0 = time.perf_counter()
+    q.rates([300.0], gam2, order=4)
+    fp.fp_check(ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kept = int(q.kept.cpu()[0])
+    say(f"fcc8_4ph fused adaptive: {kept} processes in {dt:.3f} s, lists {n_rec}")
+    assert kept == n_rec
+    assert_modes(gam2.cpu().numpy(), g_list, "fused adaptive vs lists", rtol=1e-12)
+
+
 def test_fused_type_mask(ctx):
     cfg = small_config(4)
     rows = np.asarray(row_modes(cfg)[::7], np.int32)
