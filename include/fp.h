@@ -228,7 +228,8 @@ fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t
  * and every type selected by type_mask (bit 0 FP_4PP, bit 1 FP_4PM, bit 2
  * FP_4MM), each (q', q'') pair and branch triple is tested on the GPU with the
  * host enumerator's rules (frequency floor, triangle order, |Delta| <=
- * nsigma*sigma in FP64 left to right) and the kept processes are evaluated in
+ * nsigma*sigma in FP64 left to right, or nsigma*sigma_p under an adaptive
+ * fp_broadening) and the kept processes are evaluated in
  * the FP64 tuple-batched form.  The result equals fp_rates4 over the lists that
  * fp_enumerate_fill gives for these rows (keep_fraction 1), up to the grouping
  * of the sums.  n_kept (DEVICE int64 [1], may be NULL) receives the number of
