@@ -418,14 +418,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
                     // B-operand: B_tuple[c] for component c = 16 mt + li
                     const int c = mt * 16 + li;
                     double2 B = make_double2(0.0, 0.0);
+                    // the tuple sums wait on LDS; they take issue priority over
+                    // another wave's MFMAs
+                    __builtin_amdgcn_s_setprio(3);
                     if (c < 27) {
                         const int b = c / 9, gd = c % 9;
                         for (int r = r0; r < r1; ++r) B = cfma(B, U[r][b], W[r][gd]);
                     }
+                    __builtin_amdgcn_s_setprio(0);
                     // G += ph B (Karatsuba: k1 = (Ar + Ai) Br, k2 = Ar (Bi - Br), k3 = Ai (Br + Bi))
                     k1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(pd_s, B.x, k1[mt], 0, 0, 0);
                     k2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.x, B.y - B.x, k2[mt], 0, 0, 0);
                     k3[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.y, B.x + B.y, k3[mt], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             lds_fence();
