@@ -107,7 +107,7 @@ def partner_groups(ifc):
     return len({tuple(a[1:]) for a in np.asarray(ifc["atoms"]).tolist()})
 
 
-def paper_scale(torch, fp, RatePath, adaptive=False):
+def paper_scale(torch, fp, RatePath, adaptive=False, precision=None):
     """The 16^3 two-atom cell: every active row and the three four-phonon types
     in one fp_rates4_fused call (lists generated on the GPU), T = 300/600/900 K;
     with adaptive, the per-process width max(0.1 sigma0_p, 0.01 THz)."""
@@ -116,7 +116,7 @@ def paper_scale(torch, fp, RatePath, adaptive=False):
     if adaptive:
         cfg = dict(cfg, sigma=SIGMA_FLOOR)
     T = [float(x) for x in cfg["T"]]
-    p = RatePath(cfg, device=0)
+    p = RatePath(cfg, device=0, precision=fp.FP_FP64 if precision is None else precision)
     if adaptive:
         p.set_broadening(adaptive_broadening(cfg))
     p.set_fused(row_modes(cfg), 7)
@@ -133,9 +133,11 @@ def paper_scale(torch, fp, RatePath, adaptive=False):
     fp.fp_check(p.ctx)
     kept = int(p.kept.cpu()[0])
     p.close()
-    log(f"bench: 16^3 fused{' adaptive' if adaptive else ''}: {kept} processes in {dt:.2f} s")
+    mixed = precision == fp.FP_MIXED
+    log(f"bench: 16^3 fused{' adaptive' if adaptive else ''}{' mixed' if mixed else ''}: {kept} processes in {dt:.2f} s")
     width = "adaptive width max(0.1 sigma0, 0.01 THz)" if adaptive else "sigma 0.1 THz"
-    return {"workload": "4ph FP64, 2-atom diamond cell, 16x16x16 mesh, Oh-irreducible q1 (145), 62 cubic + "
+    return {"workload": f"4ph {'mixed' if mixed else 'FP64'}, 2-atom diamond cell, 16x16x16 mesh, "
+                        "Oh-irreducible q1 (145), 62 cubic + "
                         f"{int(cfg['ifc4']['n_terms'])} quartic terms, T = 300/600/900 K, {width}, "
                         "lists generated on the GPU",
             "processes_4ph": kept, "seconds": dt, "value": kept / dt, "unit": "processes/s",
@@ -383,6 +385,7 @@ def main():
     }
     if args.paper_scale:
         out["paper_scale"] = paper_scale(torch, fp, RatePath)
+        out["paper_scale_mixed"] = paper_scale(torch, fp, RatePath, precision=fp.FP_MIXED)
     if args.paper_scale_adaptive:
         out["paper_scale_adaptive"] = paper_scale(torch, fp, RatePath, adaptive=True)
     if not args.no_cpu_baseline:

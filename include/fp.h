@@ -229,13 +229,14 @@ fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t
  * FP_4MM), each (q', q'') pair and branch triple is tested on the GPU with the
  * host enumerator's rules (frequency floor, triangle order, |Delta| <=
  * nsigma*sigma in FP64 left to right, or nsigma*sigma_p under an adaptive
- * fp_broadening) and the kept processes are evaluated in
- * the FP64 tuple-batched form.  The result equals fp_rates4 over the lists that
- * fp_enumerate_fill gives for these rows (keep_fraction 1), up to the grouping
- * of the sums.  n_kept (DEVICE int64 [1], may be NULL) receives the number of
- * processes evaluated.  Other arguments as fp_rates4; precision must be
- * FP_FP64 (optionally | FP_ACCUMULATE).  Requires nb = 6 (two-atom cells):
- * FP_ERR_UNSUPPORTED otherwise.  Asynchronous on hip_stream. */
+ * fp_broadening) and the kept processes are evaluated in the tuple-batched
+ * form, FP64 or FP_MIXED as in fp_rates4.  The result equals fp_rates4 with the
+ * same precision over the lists that fp_enumerate_fill gives for these rows
+ * (keep_fraction 1), up to the grouping of the sums.  n_kept (DEVICE int64 [1],
+ * may be NULL) receives the number of processes evaluated.  Other arguments as
+ * fp_rates4 (precision FP_FP64 or FP_MIXED, optionally | FP_ACCUMULATE).
+ * Requires nb = 6 (two-atom cells): FP_ERR_UNSUPPORTED otherwise.  Asynchronous
+ * on hip_stream. */
 fp_status fp_rates4_fused(fp_ctx* ctx, int64_t n_rows, const int32_t* row_mode, int32_t type_mask, int32_t n_T,
                           const double* T_K, double sigma, double nsigma, int32_t precision, double* gamma_out,
                           double* wp_out, int64_t* n_kept, void* hip_stream);

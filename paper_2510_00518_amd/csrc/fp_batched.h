@@ -35,13 +35,17 @@ inline size_t tb_dyn_lds(int32_t L, int64_t n_terms) {
 
 // Copy the root table (and the term table when it fits) into the block's
 // dynamic LDS; returns the term table to read, staged or global.
+__device__ inline const int32_t* tb_stage_terms(void* at, const int32_t* __restrict__ tmeta, int32_t n_terms) {
+    if (n_terms > kStageTerms) return tmeta;
+    int32_t* stm = reinterpret_cast<int32_t*>(at);
+    for (int i = threadIdx.x; i < n_terms * 8; i += kBlock) stm[i] = tmeta[i];
+    return stm;
+}
+
 __device__ inline const int32_t* tb_stage(double2* sroots, const double2* __restrict__ roots, int32_t L,
                                           const int32_t* __restrict__ tmeta, int32_t n_terms) {
     for (int i = threadIdx.x; i < L; i += kBlock) sroots[i] = roots[i];
-    if (n_terms > kStageTerms) return tmeta;
-    int32_t* stm = reinterpret_cast<int32_t*>(sroots + L);
-    for (int i = threadIdx.x; i < n_terms * 8; i += kBlock) stm[i] = tmeta[i];
-    return stm;
+    return tb_stage_terms(sroots + L, tmeta, n_terms);
 }
 
 

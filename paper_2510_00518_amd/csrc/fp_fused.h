@@ -140,7 +140,9 @@ __device__ inline int select_bit(uint64_t w, int n) {
     return pos;
 }
 
-template <int MAXT, bool ADAPT>
+// MIXED: the kept records are evaluated by the mixed-precision batch (split
+// bf16 MFMA build, FP32 contraction, FP64 weights) instead of the FP64 one.
+template <int MAXT, bool ADAPT, bool MIXED>
 __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
                                                      const double* __restrict__ occ, const double2* __restrict__ roots,
                                                      const double2* __restrict__ phit,
@@ -148,12 +150,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                                                      const int32_t* __restrict__ groups,
                                                      const RowInfo* __restrict__ rows, double* __restrict__ partial,
                                                      int64_t* __restrict__ unit_kept, int* __restrict__ flag,
-                                                     RatesArgs a, FusedArgs f) {
+                                                     RatesArgs a, FusedArgs f, const float2* __restrict__ evec32,
+                                                     const uint4* __restrict__ fsp, int32_t n_kblk) {
     constexpr int NB = kFusedNb;
+    // dynamic LDS: the root table (FP64, or its bf16 splits: 16 bytes an entry
+    // either way), then the term table
     extern __shared__ double2 sroots[];
-    __shared__ double2 sA[kWavesPerBlock][kTB][27];
+    __shared__ std::conditional_t<MIXED, float2, double2> sA[kWavesPerBlock][kTB][27];
     __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
-    const int32_t* tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_terms);
+    const int32_t* tm;
+    if constexpr (MIXED) {
+        tbm_roots(reinterpret_cast<uint4*>(sroots), roots, a.geo.L);
+        tm = tb_stage_terms(sroots + a.geo.L, tmeta, a.n_terms);
+    } else {
+        tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_terms);
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -300,8 +311,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                         const uint64_t g2 = (uint64_t)((start + lo) * NB + j2);
                         rec[k] = p < total ? (g1 | (g2 << 24) | ((uint64_t)j3 << 48)) : 0;
                     }
-                    tb_batch<MAXT, false>(rec, count, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
-                                          sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
+                    if constexpr (MIXED)
+                        tbm_batch<MAXT, false>(rec, count, g0, type, fsp + fr * n_kblk * 4 * kWave * 3, omega, evec32,
+                                               occ, tm, groups, flag, a, reinterpret_cast<const uint4*>(sroots),
+                                               sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
+                    else
+                        tb_batch<MAXT, false>(rec, count, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
+                                              sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
                 }
             }
         }

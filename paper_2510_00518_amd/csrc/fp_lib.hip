@@ -11,6 +11,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fp.h"
@@ -921,8 +922,9 @@ namespace {
 
 template <int T>
 fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const fpk::FusedArgs& f,
-                       const IfcState& S) {
-    auto kern = f.vel ? fpk::k_fused4<T, true> : fpk::k_fused4<T, false>;
+                       const IfcState& S, bool mixed) {
+    auto kern = mixed ? (f.vel ? fpk::k_fused4<T, true, true> : fpk::k_fused4<T, false, true>)
+                      : (f.vel ? fpk::k_fused4<T, true, false> : fpk::k_fused4<T, false, false>);
     const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
@@ -933,7 +935,7 @@ fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->partial.p, c->unit_kept.p, c->flag,
-                       a, f);
+                       a, f, c->evec32.p, c->fsp.p, S.n_kblk);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -955,7 +957,9 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
         if (!(T_K[i] > 0.0)) return fail(c, FP_ERR_ARG, "temperatures must be positive");
     if (!(sigma > 0.0) || !(nsigma > 0.0)) return fail(c, FP_ERR_ARG, "sigma and nsigma must be positive");
     const bool accumulate = (precision & FP_ACCUMULATE) != 0;
-    if ((precision & ~FP_ACCUMULATE) != FP_FP64) return fail(c, FP_ERR_UNSUPPORTED, "the fused path is FP_FP64 only");
+    const int32_t prec = precision & ~FP_ACCUMULATE;
+    if (prec != FP_FP64 && prec != FP_MIXED) return fail(c, FP_ERR_ARG, "unknown precision %d", prec);
+    const bool mixed = prec == FP_MIXED;
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
     const int64_t nm = c->n_modes;
@@ -1013,6 +1017,12 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     const fpk::ModeGeom geo = geometry(c);
     hipLaunchKernelGGL(fpk::k_precontract<4>, dim3(grid_for(n_frows * S.n_terms * 27)), dim3(256), 0, st, c->rows.p,
                        n_frows, c->evec.p, c->roots.p, geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+    if (mixed) {
+        const int64_t nf = n_frows * S.n_kblk * 4 * fpk::kWave;
+        HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
+        hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, n_frows, c->phit.p, S.groups.p,
+                           S.kblk.p, S.n_kblk, (int32_t)S.n_terms, c->fsp.p);
+    }
     HIP_TRY(c, hipGetLastError());
     fpk::RatesArgs a;
     memset(&a, 0, sizeof a);
@@ -1028,8 +1038,8 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     hipEvent_t ev0, ev1;
     fp_status ts = timer_start(c, st, &ev0, &ev1);
     if (ts != FP_OK) return ts;
-    fp_status ls = tsel == 1 ? launch_fused<1>(c, st, a, f, S)
-                             : (tsel == 4 ? launch_fused<4>(c, st, a, f, S) : launch_fused<8>(c, st, a, f, S));
+    fp_status ls = tsel == 1 ? launch_fused<1>(c, st, a, f, S, mixed)
+                             : (tsel == 4 ? launch_fused<4>(c, st, a, f, S, mixed) : launch_fused<8>(c, st, a, f, S, mixed));
     if (ls != FP_OK) return ls;
     ts = timer_stop(c, st, 34, ev0, ev1);
     if (ts != FP_OK) return ts;

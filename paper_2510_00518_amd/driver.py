@@ -202,7 +202,7 @@ class RatePath:
             fp.fp_rates4(self.ctx, self.lists4, T, sigma, prec, gamma, wp)
             first = False
         if self.fused_rows is not None and order in (None, 4):
-            prec = fp.FP_FP64 if first else fp.FP_FP64 | fp.FP_ACCUMULATE
+            prec = self.precision if first else self.precision | fp.FP_ACCUMULATE
             fp.fp_rates4_fused(self.ctx, self.fused_rows, self.fused_mask, T, sigma, self.cfg["nsigma"], prec, gamma, wp,
                                n_kept=self.kept)
             first = False

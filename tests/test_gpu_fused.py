@@ -37,13 +37,13 @@ def ctx():
     fp.fp_destroy(h)
 
 
-def fused_rates(ctx, cfg, rows, T, mask=7, sigma=None):
+def fused_rates(ctx, cfg, rows, T, mask=7, sigma=None, precision=fp.FP_FP64):
     import torch
     from paper_2510_00518_amd.driver import RatePath
     cfg = dict(cfg)
     if sigma is not None:
         cfg["sigma"] = sigma
-    p = RatePath(cfg, ctx=ctx)
+    p = RatePath(cfg, ctx=ctx, precision=precision)
     p.set_fused(rows, mask)
     gam, wp = p.outputs(len(T))
     p.load_ifc()
@@ -171,6 +171,50 @@ def test_fused_adaptive_fcc8_against_lists(ctx):
     assert_modes(gam2.cpu().numpy(), g_list, "fused adaptive vs lists", rtol=1e-12)
 
 
+@pytest.mark.parametrize("mesh,sigma,stride", [(4, None, 5), (3, 4.0, 2)])
+def test_fused_mixed_precision_matches_oracle(ctx, mesh, sigma, stride):
+    """FP_MIXED in the fused launch: the same kept set, rates within the mixed
+    bar (2e-5 per mode relative; modes below 1e-6 of the largest within that
+    absolute floor) of the oracle's FP64 sums."""
+    cfg = small_config(mesh)
+    sig = cfg["sigma"] if sigma is None else sigma
+    rows = np.asarray(row_modes(cfg)[::stride], np.int32)
+    T = [300.0, 1200.0]
+    g, w, kept = fused_rates(ctx, cfg, rows, T, sigma=sig, precision=fp.FP_MIXED)
+    go, wo, ko = oracle_rows(cfg, TYPES4, rows, T, sig)
+    assert kept == ko
+    scale = np.abs(go).max()
+    big = np.abs(go) > 1e-6 * scale
+    rel = np.abs(g[big] - go[big]) / np.abs(go[big])
+    say(f"fused mixed {mesh}^3: {kept} processes, Gamma rel err max {rel.max():.2e} median {np.median(rel):.1e}")
+    assert rel.max() <= 2e-5
+    assert np.abs(g[~big] - go[~big]).max() <= 1e-6 * scale
+    assert_modes(w, wo, "WP4 (FP64 in both)", rtol=1e-10)
+
+
+@pytest.mark.slow
+def test_fused_mixed_fcc8_against_mixed_lists(ctx):
+    """8^3 workload: the fused mixed launch against the list-driven mixed path
+    (the same per-process arithmetic, sums grouped differently)."""
+    import torch
+    from paper_2510_00518_amd.driver import RatePath, host_lists
+    cfg = make_config("fcc8_4ph")
+    lists = host_lists(cfg, TYPES4)
+    p = RatePath(cfg, ctx=ctx, precision=fp.FP_MIXED)
+    p.set_lists(lists)
+    gam, _ = p.outputs(1)
+    p.load_ifc()
+    p.rates([300.0], gam, order=4)
+    torch.cuda.synchronize()
+    g_list = gam.cpu().numpy()
+    del lists
+    g, _, kept = fused_rates(ctx, cfg, row_modes(cfg), [300.0], precision=fp.FP_MIXED)
+    scale = np.abs(g_list).max()
+    err = np.abs(g - g_list) / np.maximum(np.abs(g_list), 1e-6 * scale)
+    say(f"fcc8 fused mixed vs mixed lists: max rel err {err.max():.2e} (modes below 1e-6 of the largest: absolute)")
+    assert err.max() <= 1e-12
+
+
 def test_fused_type_mask(ctx):
     cfg = small_config(4)
     rows = np.asarray(row_modes(cfg)[::7], np.int32)
@@ -197,7 +241,7 @@ def test_fused_argument_errors(ctx):
     p.load_ifc(phi4=p.phi4)
     rows = torch.as_tensor(np.asarray(row_modes(cfg)[:2], np.int32)).cuda()
     gam = torch.zeros((1, p.n_modes), dtype=torch.float64, device="cuda")
-    for mask, prec in ((0, fp.FP_FP64), (8, fp.FP_FP64), (7, fp.FP_MIXED)):
+    for mask, prec in ((0, fp.FP_FP64), (8, fp.FP_FP64), (7, 5)):
         with pytest.raises(fp.FpError):
             fp.fp_rates4_fused(ctx, rows, mask, [300.0], cfg["sigma"], 3.0, prec, gam)
 
@@ -269,3 +313,30 @@ def test_fused_paper_scale_fcc16(ctx):
     err = np.abs(g[:, gm] - want) / np.abs(want)
     say(f"row g={gm}: {n_rec} processes, fused {g[:, gm]} oracle {want} rel {err}")
     assert err.max() <= 1e-10
+    # the mixed-precision launch on the same cell: kappa_RTA within 1e-5 of FP64
+    pm = RatePath(cfg, ctx=ctx, precision=fp.FP_MIXED)
+    pm.set_fused(rows, 7)
+    gm_, _ = pm.outputs(len(T))
+    pm.load_ifc()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm.rates(T, gm_, order=4)
+    fp.fp_check(ctx)
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    kap = {}
+    for name, gg in (("fp64", gam), ("mixed", gm_)):
+        k = torch.zeros((len(T), 9), dtype=torch.float64, device="cuda")
+        p.kappa(T, gg, k)
+        torch.cuda.synchronize()
+        k = k.cpu().numpy()
+        kap[name] = (k[:, 0] + k[:, 4] + k[:, 8]) / 3
+    kerr = np.abs(kap["mixed"] - kap["fp64"]) / np.abs(kap["fp64"])
+    gmx = gm_.cpu().numpy()
+    big = np.abs(g) > 1e-6 * np.abs(g).max()
+    rel = np.abs(gmx[big] - g[big]) / np.abs(g[big])
+    say(f"fcc16_34ph fused mixed: {int(pm.kept.cpu()[0])} processes in {dtm:.2f} s ({kept / dtm:.3e} processes/s); "
+        f"kappa rel err {kerr}, Gamma rel err max {rel.max():.2e}")
+    assert int(pm.kept.cpu()[0]) == kept
+    assert kerr.max() <= 1e-5
+    assert rel.max() <= 2e-5
