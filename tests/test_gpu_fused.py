@@ -270,10 +270,11 @@ def test_fused_matches_lists_fcc8(ctx):
     assert_modes(g, g_list, "fused vs lists", rtol=1e-12)
 
 
-@pytest.mark.slow
-def test_fused_paper_scale_fcc16(ctx):
+@pytest.fixture(scope="module")
+def fcc16_fp64(ctx):
     """The 16^3 two-atom cell (145 irreducible q1, 62 + 164 terms, T = 300, 600,
-    900 K): every row in one fused launch; one sampled row against the oracle."""
+    900 K): every row in one FP64 fused launch, shared by the parity and the
+    mixed-precision tests below."""
     import torch
     from paper_2510_00518_amd.driver import RatePath
     cfg = make_config("fcc16_34ph")
@@ -290,8 +291,15 @@ def test_fused_paper_scale_fcc16(ctx):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kept = int(p.kept.cpu()[0])
-    g = gam.cpu().numpy()
     say(f"fcc16_34ph fused: {len(rows)} rows, {kept} processes in {dt:.2f} s ({kept / dt:.3e} processes/s)")
+    return cfg, T, rows, p, gam, kept
+
+
+@pytest.mark.slow
+def test_fused_paper_scale_fcc16(fcc16_fp64):
+    """All rows finite and non-negative; one sampled row against the oracle."""
+    cfg, T, rows, p, gam, kept = fcc16_fp64
+    g = gam.cpu().numpy()
     assert np.all(np.isfinite(g)) and np.all(g[:, rows] >= 0)
     # the sampled row: the one with the fewest processes among six seeded candidates
     rng = np.random.default_rng(251000518 + 7)
@@ -313,7 +321,16 @@ def test_fused_paper_scale_fcc16(ctx):
     err = np.abs(g[:, gm] - want) / np.abs(want)
     say(f"row g={gm}: {n_rec} processes, fused {g[:, gm]} oracle {want} rel {err}")
     assert err.max() <= 1e-10
-    # the mixed-precision launch on the same cell: kappa_RTA within 1e-5 of FP64
+
+
+@pytest.mark.slow
+def test_fused_paper_scale_fcc16_mixed(ctx, fcc16_fp64):
+    """The mixed-precision launch on the same cell: the same processes, every
+    non-negligible rate within 2e-5 and kappa_RTA within 1e-5 of FP64."""
+    import torch
+    from paper_2510_00518_amd.driver import RatePath
+    cfg, T, rows, p, gam, kept = fcc16_fp64
+    g = gam.cpu().numpy()
     pm = RatePath(cfg, ctx=ctx, precision=fp.FP_MIXED)
     pm.set_fused(rows, 7)
     gm_, _ = pm.outputs(len(T))
