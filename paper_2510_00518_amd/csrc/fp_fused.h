@@ -170,20 +170,29 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int xcd = blockIdx.x % kXcd;
-    const int64_t per_xcd = (f.n_units + kXcd - 1) / kXcd;
-    const int64_t u_beg = xcd * per_xcd;
-    const int64_t u_end = u_beg + per_xcd < f.n_units ? u_beg + per_xcd : f.n_units;
     const int64_t wstride = (int64_t)(gridDim.x / kXcd) * kWavesPerBlock;
     const ModeGeom geo = a.geo;
     const int32_t N0 = geo.N0, N1 = geo.N1, N2 = geo.N2;
     const int32_t nq = N0 * N1 * N2;
+    // Each XCD takes one slice of the q' range of every fused row.  The kept
+    // processes per unit differ by orders of magnitude between the types (and
+    // between rows), so a contiguous range of units per XCD would leave most
+    // XCDs idle while the few holding the +- rows finish; slices of q' spread
+    // every row evenly, and consecutive units of an XCD still share a row's
+    // force-constant table in its L2.  Unit u = fr * nq + q' keeps its slot in
+    // the partials, so the per-row sums keep their order.
+    const int32_t q_sl = (nq + kXcd - 1) / kXcd;
+    const int32_t q_beg = xcd * q_sl < nq ? xcd * q_sl : nq;
+    const int32_t q_cnt = (q_beg + q_sl < nq ? q_beg + q_sl : nq) - q_beg;
+    const int64_t w_end = (f.n_units / nq) * q_cnt;
     double dl[MAXT];
 #pragma unroll
     for (int it = 0; it < MAXT; ++it) dl[it] = 0.0;
 
-    for (int64_t u = u_beg + (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave; u < u_end; u += wstride) {
-        const int32_t iq1 = (int32_t)(u % nq);
-        const int64_t fr = u / nq;
+    for (int64_t w = (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave; w < w_end; w += wstride) {
+        const int64_t fr = w / q_cnt;
+        const int32_t iq1 = q_beg + (int32_t)(w % q_cnt);
+        const int64_t u = fr * nq + iq1;
         const RowInfo ri = rows[fr];
         const int32_t g0 = __builtin_amdgcn_readfirstlane(ri.mode);
         const int type = __builtin_amdgcn_readfirstlane(ri.type);
@@ -206,7 +215,15 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
             double pm1[3] = {0.0, 0.0, 0.0};
             if (ADAPT) fused_proj_max(f.vel, iq1, f, geo, pm1);
 
-            for (int32_t start = tri12 ? iq1 : 0; start < nq; start += kWave) {
+            // kept records wait in buf (position k * 64 + lane in buf[k], pend of
+            // them) until 128 have gathered, across chunks of q''; one pass past
+            // the last chunk (no candidates) evaluates the remainder
+            uint64_t buf[kBR];
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) buf[k] = 0;
+            int pend = 0;
+            for (int32_t start = tri12 ? iq1 : 0;; start += kWave) {
+                const bool last = start >= nq;
                 // ---- candidate masks: lane = q''
                 const int32_t iq2 = start + lane;
                 const bool qv = iq2 < nq;
@@ -272,53 +289,63 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                 const int excl = incl - cnt;
                 kept += total;
                 // ---- batches of 128 kept records, in (q'', j', j'', j''') order
-                for (int b0 = 0; b0 < total; b0 += kBU) {
-                    const int count = total - b0 < kBU ? total - b0 : kBU;
-                    uint64_t rec[kBR];
+                int used = 0;
+                do {
+                    const int take = kBU - pend < total - used ? kBU - pend : total - used;
+                    if (take > 0) {
 #pragma unroll
-                    for (int k = 0; k < kBR; ++k) {
-                        // every lane decodes (clamped), so the shuffles see the whole wave
-                        const int p = b0 + k * kWave + lane;
-                        const int pc = p < total ? p : total - 1;
-                        int lo = 0, hi = kWave - 1;  // largest lane s with excl[s] <= pc
+                        for (int k = 0; k < kBR; ++k) {
+                            // every lane decodes (clamped), so the shuffles see the whole wave
+                            const int pos = k * kWave + lane;
+                            const int p = used + pos - pend;
+                            const int pc = p < 0 ? 0 : (p < total ? p : total - 1);
+                            int lo = 0, hi = kWave - 1;  // largest lane s with excl[s] <= pc
 #pragma unroll
-                        for (int it = 0; it < 6; ++it) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (__shfl(excl, mid, kWave) <= pc)
-                                lo = mid;
-                            else
-                                hi = mid - 1;
-                        }
-                        int n = pc - __shfl(excl, lo, kWave);
-                        uint64_t w[4];
-#pragma unroll
-                        for (int x = 0; x < 4; ++x) w[x] = __shfl(m[x], lo, kWave);
-                        // word holding the n-th set bit, then the bit within it
-                        uint64_t ww = w[0];
-                        int word = 0;
-#pragma unroll
-                        for (int x = 0; x < 3; ++x) {
-                            const int c = __popcll(ww);
-                            if (word == x && n >= c) {
-                                n -= c;
-                                word = x + 1;
-                                ww = w[x + 1];
+                            for (int it = 0; it < 6; ++it) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (__shfl(excl, mid, kWave) <= pc)
+                                    lo = mid;
+                                else
+                                    hi = mid - 1;
                             }
+                            int n = pc - __shfl(excl, lo, kWave);
+                            uint64_t w[4];
+#pragma unroll
+                            for (int x = 0; x < 4; ++x) w[x] = __shfl(m[x], lo, kWave);
+                            // word holding the n-th set bit, then the bit within it
+                            uint64_t ww = w[0];
+                            int word = 0;
+#pragma unroll
+                            for (int x = 0; x < 3; ++x) {
+                                const int c = __popcll(ww);
+                                if (word == x && n >= c) {
+                                    n -= c;
+                                    word = x + 1;
+                                    ww = w[x + 1];
+                                }
+                            }
+                            const int c = word * 64 + select_bit(ww, n);
+                            const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
+                            const uint64_t g1 = (uint64_t)(iq1 * NB + j1);
+                            const uint64_t g2 = (uint64_t)((start + lo) * NB + j2);
+                            if (pos >= pend && pos < pend + take) buf[k] = g1 | (g2 << 24) | ((uint64_t)j3 << 48);
                         }
-                        const int c = word * 64 + select_bit(ww, n);
-                        const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
-                        const uint64_t g1 = (uint64_t)(iq1 * NB + j1);
-                        const uint64_t g2 = (uint64_t)((start + lo) * NB + j2);
-                        rec[k] = p < total ? (g1 | (g2 << 24) | ((uint64_t)j3 << 48)) : 0;
                     }
-                    if constexpr (MIXED)
-                        tbm_batch<MAXT, false>(rec, count, g0, type, fsp + fr * n_kblk * 4 * kWave * 3, omega, evec32,
-                                               occ, tm, groups, flag, a, reinterpret_cast<const uint4*>(sroots),
-                                               sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
-                    else
-                        tb_batch<MAXT, false>(rec, count, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
-                                              sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
-                }
+                    pend += take;
+                    used += take;
+                    if (pend == kBU || (last && pend > 0)) {
+                        if constexpr (MIXED)
+                            tbm_batch<MAXT, false>(buf, pend, g0, type, fsp + fr * n_kblk * 4 * kWave * 3, omega,
+                                                   evec32, occ, tm, groups, flag, a,
+                                                   reinterpret_cast<const uint4*>(sroots), sA[wave], sQ[wave], accg,
+                                                   accw, dl, 0.0, nullptr);
+                        else
+                            tb_batch<MAXT, false>(buf, pend, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
+                                                  sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
+                        pend = 0;
+                    }
+                } while (used < total);
+                if (last) break;
             }
         }
         double* out = partial + u * (2 * a.n_T);
