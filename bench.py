@@ -20,8 +20,10 @@ adaptive: the same step with the per-process width sigma_p = max(0.1 sigma0_p,
 the host enumerates with that width.
 cpu_baseline: the FP64 oracle (list mode) on a bounded sample of the same lists
 on this host's cores.  --paper-scale adds the 16x16x16 two-atom cell (every row,
-three types, T = 300/600/900 K) through GPU-side enumeration; it holds the GPU
-for about a minute, so it is not part of the default run.
+three types, T = 300/600/900 K) through GPU-side enumeration, FP64 and mixed,
+each with a roofline from the library's tuple count; with --paper-scale-adaptive
+the adaptive width too.  They hold the GPU for about a minute, so they are not
+part of the default run.
 """
 import argparse
 import hashlib
@@ -132,16 +134,38 @@ def paper_scale(torch, fp, RatePath, adaptive=False, precision=None):
     fp.fp_profile(p.ctx, False)
     fp.fp_check(p.ctx)
     kept = int(p.kept.cpu()[0])
+    n_proc, n_tup = fp.fp_fused_counts(p.ctx)
+    n4 = int(cfg["ifc4"]["n_terms"])
+    n_groups = partner_groups(cfg["ifc4"])
     p.close()
     mixed = precision == fp.FP_MIXED
+    # the fused kernel's algorithmic work in the tuple form that ran: 216 n4 FLOP per
+    # (lambda, q', q'') tuple on matrix cores, (312 n_groups + 60) per process on the VALU
+    sec = k_ms / max(1, n) * 1e-3
+    f_build = 216 * n4 * n_tup
+    f_contract = (312 * n_groups + 60) * n_proc
+    if mixed:
+        roof = {"bound": "mfma", "achieved": 6 * f_build / sec / 1e12, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "kernel": "k_fused4 mixed (bf16 split MFMA + FP32 VALU)",
+                "work": f"6 bf16 products per FP32-accurate product, 216*n4 FLOP per tuple, n4 = {n4}, {n_tup} tuples",
+                "fp32_equivalent_tflops": f_build / sec / 1e12}
+    else:
+        roof = {"bound": "mfma", "achieved": f_build / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "kernel": "k_fused4 (GPU enumeration + tuple-batched FP64 MFMA + FP64 VALU)",
+                "work": f"216*n4 FLOP per (lambda, q', q'') tuple on FP64 MFMA, n4 = {n4}, {n_tup} tuples"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["valu_achieved"] = f_contract / sec / 1e12
+    roof["per_process_form_equivalent_tflops"] = (320 * n4 + 60) * n_proc / sec / 1e12
+    roof["kernel_ms"] = k_ms / max(1, n)
+    roof["traffic"] = None
     log(f"bench: 16^3 fused{' adaptive' if adaptive else ''}{' mixed' if mixed else ''}: {kept} processes in {dt:.2f} s")
     width = "adaptive width max(0.1 sigma0, 0.01 THz)" if adaptive else "sigma 0.1 THz"
     return {"workload": f"4ph {'mixed' if mixed else 'FP64'}, 2-atom diamond cell, 16x16x16 mesh, "
                         "Oh-irreducible q1 (145), 62 cubic + "
                         f"{int(cfg['ifc4']['n_terms'])} quartic terms, T = 300/600/900 K, {width}, "
                         "lists generated on the GPU",
-            "processes_4ph": kept, "seconds": dt, "value": kept / dt, "unit": "processes/s",
-            "kernel_ms": k_ms / max(1, n), "rows": int(len(row_modes(cfg)))}
+            "processes_4ph": kept, "tuples_4ph": n_tup, "seconds": dt, "value": kept / dt, "unit": "processes/s",
+            "kernel_ms": k_ms / max(1, n), "rows": int(len(row_modes(cfg))), "roofline": roof}
 
 
 def run_forward(path, T, steps, warmup, tag, torch, fp):

@@ -241,6 +241,19 @@ fp_status fp_rates4_fused(fp_ctx* ctx, int64_t n_rows, const int32_t* row_mode, 
                           const double* T_K, double sigma, double nsigma, int32_t precision, double* gamma_out,
                           double* wp_out, int64_t* n_kept, void* hip_stream);
 
+/* Work counts of the last fp_rates4_fused call on this context, for throughput
+ * and roofline accounting of the tuple-batched form (Appendix, Algorithms 3
+ * and 4, evaluated per (lambda, q', q'') tuple):
+ *   out[0]  processes evaluated (the n_kept of that call)
+ *   out[1]  (lambda, q', q'') tuples, over every row and type of the call, with
+ *           at least one kept process: the phase-weighted force-constant builds
+ *           the form needs at least (a tuple split between two 128-record
+ *           batches is built once in each)
+ * out is a HOST array of 2; the copy is enqueued on hip_stream, which must be
+ * (or follow) the stream of that call, and the function waits for it.
+ * FP_ERR_ARG for NULL out, FP_ERR_STATE before any fp_rates4_fused call. */
+fp_status fp_fused_counts(fp_ctx* ctx, int64_t out[2], void* hip_stream);
+
 /* Figures of one fp_rates_streamed call (host wall-clock milliseconds). */
 typedef struct {
     int64_t n_records;  /* records evaluated, all selected types */

@@ -149,8 +149,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                                                      const int32_t* __restrict__ tmeta,
                                                      const int32_t* __restrict__ groups,
                                                      const RowInfo* __restrict__ rows, double* __restrict__ partial,
-                                                     int64_t* __restrict__ unit_kept, int* __restrict__ flag,
-                                                     RatesArgs a, FusedArgs f, const float2* __restrict__ evec32,
+                                                     int64_t* __restrict__ unit_kept, int64_t* __restrict__ unit_tup,
+                                                     int* __restrict__ flag, RatesArgs a, FusedArgs f, const float2* __restrict__ evec32,
                                                      const uint4* __restrict__ fsp, int32_t n_kblk) {
     constexpr int NB = kFusedNb;
     // dynamic LDS: the root table (FP64, or its bf16 splits: 16 bytes an entry
@@ -200,6 +200,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
 #pragma unroll
         for (int it = 0; it < MAXT; ++it) accg[it] = accw[it] = 0.0;
         int64_t kept = 0;
+        int64_t ntup = 0;  // (lambda, q', q'') tuples with a kept record
         const double w0 = g0 >= 0 ? omega[g0] : 0.0;
         if (g0 >= 0 && w0 >= f.floor_) {
             int s1, s2, s3;
@@ -288,6 +289,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                 const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
                 const int excl = incl - cnt;
                 kept += total;
+                ntup += __popcll(__ballot(cnt > 0));
                 // ---- batches of 128 kept records, in (q'', j', j'', j''') order
                 int used = 0;
                 do {
@@ -360,7 +362,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                 }
             }
         }
-        if (lane == 0) unit_kept[u] = kept;
+        if (lane == 0) {
+            unit_kept[u] = kept;
+            unit_tup[u] = ntup;
+        }
     }
 }
 

@@ -158,6 +158,9 @@ struct fp_ctx {
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
     DevBuf<int64_t> unit_kept;  // fused enumeration: kept records per unit
+    DevBuf<int64_t> unit_tup;   // fused enumeration: tuples with a kept record per unit
+    DevBuf<int64_t> fused_cnt;  // last fused call: processes, tuples
+    bool fused_done = false;
     int* flag = nullptr;
     // tuning knobs
     int32_t ppl = 2;
@@ -273,6 +276,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
     c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release();
     c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->unit_kept.release();
+    c->unit_tup.release(); c->fused_cnt.release();
     c->slot[0].release(); c->slot[1].release();
     if (c->flag) (void)hipFree(c->flag);
     for (auto& e : c->ev_used) {
@@ -934,8 +938,8 @@ fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
-                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->partial.p, c->unit_kept.p, c->flag,
-                       a, f, c->evec32.p, c->fsp.p, S.n_kblk);
+                       c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->partial.p, c->unit_kept.p,
+                       c->unit_tup.p, c->flag, a, f, c->evec32.p, c->fsp.p, S.n_kblk);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -967,10 +971,15 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
         hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, gamma_out, n_T * nm, 0.0);
     if (wp_out && !accumulate)
         hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_T * nm)), dim3(256), 0, st, wp_out, n_T * nm, 0.0);
+    HIP_TRY(c, c->fused_cnt.ensure(2));
     if (n_rows == 0) {
         if (n_kept) hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, (const int64_t*)nullptr,
                                        (int64_t)0, n_kept);
+        for (int i = 0; i < 2; ++i)
+            hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, (const int64_t*)nullptr,
+                               (int64_t)0, c->fused_cnt.p + i);
         HIP_TRY(c, hipGetLastError());
+        c->fused_done = true;
         return FP_OK;
     }
     fpk::FusedArgs f;
@@ -1008,6 +1017,7 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     HIP_TRY(c, c->phit.ensure((size_t)n_frows * S.n_terms * 27));
     HIP_TRY(c, c->partial.ensure((size_t)f.n_units * 2 * n_T));
     HIP_TRY(c, c->unit_kept.ensure((size_t)f.n_units));
+    HIP_TRY(c, c->unit_tup.ensure((size_t)f.n_units));
     fpk::Temps tx;
     for (int i = 0; i < 8; ++i) tx.x[i] = i < n_T ? kHbar / (kBoltz * T_K[i]) : 0.0;
     hipLaunchKernelGGL(fpk::k_occ, dim3(grid_for(n_T * nm)), dim3(256), 0, st, c->omega.p, nm, n_T, tx, c->floor_,
@@ -1047,12 +1057,27 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     const double wpref = 1.0 / ((double)c->nq * (double)c->nq);
     if (n_kept)
         hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->unit_kept.p, f.n_units, n_kept);
+    hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->unit_kept.p, f.n_units, c->fused_cnt.p);
+    hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->unit_tup.p, f.n_units,
+                       c->fused_cnt.p + 1);
+    c->fused_done = true;
     // one finalize launch per type: rows of one mode in different types add into the same outputs
     for (int ti = 0; ti < f.n_types; ++ti)
         hipLaunchKernelGGL(fpk::k_finalize, dim3((unsigned)n_rows), dim3(fpk::kBlock), 0, st, c->partial.p,
                            c->unit_off.p, c->rows.p, (int64_t)ti * n_rows, n_T, pref, wpref, gamma_out, wp_out, nm);
     HIP_TRY(c, hipGetLastError());
     if (c->validate) return fp_check(c, stream);
+    return FP_OK;
+}
+
+extern "C" fp_status fp_fused_counts(fp_ctx* c, int64_t out[2], void* stream) {
+    if (!c) return FP_ERR_ARG;
+    if (!out) return fail(c, FP_ERR_ARG, "out is NULL");
+    if (!c->fused_done) return fail(c, FP_ERR_STATE, "no fp_rates4_fused call on this context");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipMemcpyAsync(out, c->fused_cnt.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
     return FP_OK;
 }
 

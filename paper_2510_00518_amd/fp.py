@@ -24,7 +24,7 @@ FP_MAX_LISTS = 8
 
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
            "fp_rates4_fused", "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
-           "fp_enumerate_count", "fp_enumerate_fill", "fp_set_broadening", "fp_rates_streamed"]
+           "fp_enumerate_count", "fp_enumerate_fill", "fp_set_broadening", "fp_rates_streamed", "fp_fused_counts"]
 
 
 class FpError(RuntimeError):
@@ -89,6 +89,7 @@ def lib():
         for f in (L.fp_rates3, L.fp_rates4):
             f.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp]
         L.fp_rates4_fused.argtypes = [vp, i64, vp, i32, i32, vp, dbl, dbl, i32, vp, vp, vp, vp]
+        L.fp_fused_counts.argtypes = [vp, vp, vp]
         L.fp_rates_backward.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp, vp]
         L.fp_kappa_rta.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
         L.fp_check.argtypes = [vp, vp]
@@ -241,6 +242,13 @@ def fp_rates4_fused(ctx, row_mode, type_mask, T, sigma, nsigma, precision=FP_FP6
                                       float(sigma), float(nsigma), int(precision), _dp(gamma_out), _dp(wp_out),
                                       _dp(n_kept), _stream(stream)))
 
+
+
+def fp_fused_counts(ctx, stream=None):
+    """(processes, tuples) of the last fp_rates4_fused call; waits on `stream`."""
+    out = np.zeros(2, np.int64)
+    _check(ctx, lib().fp_fused_counts(ctx, _hp(out), _stream(stream)))
+    return int(out[0]), int(out[1])
 
 def fp_autotune(ctx, order, lists, T, sigma, precision=FP_FP64, reps=2, stream=None):
     """Run the library's autotuner; returns the measured candidates as dicts

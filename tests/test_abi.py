@@ -45,6 +45,7 @@ def test_null_context_arguments():
     assert L.fp_load_modes(None, None, 2, None, None, None, None, None, 0.0) == fp.FP_ERR_ARG
     assert L.fp_rates4(None, None, 0, 1, None, 1.0, 0, None, None, None) == fp.FP_ERR_ARG
     assert L.fp_check(None, None) == fp.FP_ERR_ARG
+    assert L.fp_fused_counts(None, None, None) == fp.FP_ERR_ARG
     assert L.fp_last_error(None) == b"null context"
     L.fp_destroy(None)
 

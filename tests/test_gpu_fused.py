@@ -53,26 +53,37 @@ def fused_rates(ctx, cfg, rows, T, mask=7, sigma=None, precision=fp.FP_FP64):
     return gam.cpu().numpy(), wp.cpu().numpy(), int(p.kept.cpu()[0])
 
 
+def record_tuples(recs, nb):
+    """Distinct (q', q'') pairs among the records of one row."""
+    r = np.asarray(recs, np.uint64)
+    q1 = (r & np.uint64(0xFFFFFF)).astype(np.int64) // nb
+    q2 = ((r >> np.uint64(24)) & np.uint64(0xFFFFFF)).astype(np.int64) // nb
+    return len(np.unique(q1 * (1 << 24) + q2))
+
+
 def oracle_rows(cfg, types, rows, T, sigma):
     """The oracle's canonical (triangle-reduced) enumeration of each row, its
-    list-mode rates, and the number of listed processes."""
+    list-mode rates, the number of listed processes and of their distinct
+    (lambda, q', q'') tuples."""
     S = oracle.System(cfg)
     n = cfg["omega"].size
     gam = np.zeros((len(T), n))
     wp = np.zeros((len(T), n))
     kept = 0
+    tuples = 0
     rows = np.asarray(rows, np.int32)
     for t in types:
         recs = [S.enumerate_row(t, int(g), sigma, cfg["nsigma"]) for g in rows]
         off = np.concatenate([[0], np.cumsum([len(r) for r in recs])]).astype(np.int64)
         kept += int(off[-1])
+        tuples += sum(record_tuples(r, cfg["nb"]) for r in recs if len(r))
         if off[-1] == 0:
             continue
         rec = np.concatenate(recs).astype(np.uint64)
         g, w, _, _ = S.rates(t, rows, T, sigma, cfg["nsigma"], row_off=off, rec=rec)
         gam[:, rows] += g.T
         wp[:, rows] += w.T
-    return gam, wp, kept
+    return gam, wp, kept, tuples
 
 
 def assert_modes(g, go, what, rtol=1e-10):
@@ -90,9 +101,11 @@ def test_fused_matches_oracle_brute_force(ctx, mesh, sigma, stride):
     rows = np.asarray(row_modes(cfg)[::stride], np.int32)
     T = [300.0, 1200.0]
     g, w, kept = fused_rates(ctx, cfg, rows, T, sigma=sig)
-    go, wo, ko = oracle_rows(cfg, TYPES4, rows, T, sig)
-    say(f"fused {mesh}^3 sigma={sig}: {kept} processes (oracle {ko})")
-    assert kept == ko
+    n_proc, n_tup = fp.fp_fused_counts(ctx)
+    go, wo, ko, to = oracle_rows(cfg, TYPES4, rows, T, sig)
+    say(f"fused {mesh}^3 sigma={sig}: {kept} processes in {n_tup} tuples (oracle {ko} in {to})")
+    assert kept == ko and n_proc == ko
+    assert n_tup == to
     assert_modes(g, go, "Gamma4")
     assert_modes(w, wo, "WP4")
 
@@ -181,8 +194,9 @@ def test_fused_mixed_precision_matches_oracle(ctx, mesh, sigma, stride):
     rows = np.asarray(row_modes(cfg)[::stride], np.int32)
     T = [300.0, 1200.0]
     g, w, kept = fused_rates(ctx, cfg, rows, T, sigma=sig, precision=fp.FP_MIXED)
-    go, wo, ko = oracle_rows(cfg, TYPES4, rows, T, sig)
+    go, wo, ko, to = oracle_rows(cfg, TYPES4, rows, T, sig)
     assert kept == ko
+    assert fp.fp_fused_counts(ctx) == (ko, to)
     scale = np.abs(go).max()
     big = np.abs(go) > 1e-6 * scale
     rel = np.abs(g[big] - go[big]) / np.abs(go[big])
@@ -220,8 +234,9 @@ def test_fused_type_mask(ctx):
     rows = np.asarray(row_modes(cfg)[::7], np.int32)
     T = [300.0]
     g, _, kept = fused_rates(ctx, cfg, rows, T, mask=2, sigma=6.0)
-    go, _, ko = oracle_rows(cfg, (fp.FP_4PM,), rows, T, 6.0)
+    go, _, ko, to = oracle_rows(cfg, (fp.FP_4PM,), rows, T, 6.0)
     assert kept == ko
+    assert fp.fp_fused_counts(ctx) == (ko, to)
     assert_modes(g, go, "Gamma4 (+- only)")
 
 
@@ -244,6 +259,15 @@ def test_fused_argument_errors(ctx):
     for mask, prec in ((0, fp.FP_FP64), (8, fp.FP_FP64), (7, 5)):
         with pytest.raises(fp.FpError):
             fp.fp_rates4_fused(ctx, rows, mask, [300.0], cfg["sigma"], 3.0, prec, gam)
+    # work counts: none before a fused call on a context, NULL output rejected
+    h = fp.fp_create(0)
+    try:
+        with pytest.raises(fp.FpError) as e:
+            fp.fp_fused_counts(h)
+        assert e.value.status == fp.FP_ERR_STATE
+    finally:
+        fp.fp_destroy(h)
+    assert fp.lib().fp_fused_counts(ctx, None, None) == fp.FP_ERR_ARG
 
 
 @pytest.mark.slow
@@ -264,9 +288,13 @@ def test_fused_matches_lists_fcc8(ctx):
     g_list = gam.cpu().numpy()
     fp.fp_set_knob(ctx, "variant", 1)
     g, _, kept = fused_rates(ctx, cfg, row_modes(cfg), [300.0])
+    n_proc, n_tup = fp.fp_fused_counts(ctx)
     n_rec = sum(int(v[1][-1]) for v in lists.values())
-    say(f"fcc8_4ph fused: {kept} processes, lists {n_rec}")
-    assert kept == n_rec
+    n_tup_lists = sum(record_tuples(rec[off[r]:off[r + 1]], cfg["nb"])
+                      for rm, off, rec in lists.values() for r in range(len(rm)) if off[r + 1] > off[r])
+    say(f"fcc8_4ph fused: {kept} processes in {n_tup} tuples, lists {n_rec} in {n_tup_lists}")
+    assert kept == n_rec and n_proc == n_rec
+    assert n_tup == n_tup_lists
     assert_modes(g, g_list, "fused vs lists", rtol=1e-12)
 
 
@@ -291,7 +319,10 @@ def fcc16_fp64(ctx):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kept = int(p.kept.cpu()[0])
-    say(f"fcc16_34ph fused: {len(rows)} rows, {kept} processes in {dt:.2f} s ({kept / dt:.3e} processes/s)")
+    n_proc, n_tup = fp.fp_fused_counts(ctx)
+    assert n_proc == kept and 0 < n_tup <= kept
+    say(f"fcc16_34ph fused: {len(rows)} rows, {kept} processes in {n_tup} tuples, {dt:.2f} s "
+        f"({kept / dt:.3e} processes/s)")
     return cfg, T, rows, p, gam, kept
 
 
