@@ -89,8 +89,8 @@ __device__ inline double fused_cut_bound(const double (&p1)[3], const double (&p
     return fmin(f.nsigma * sp * (1.0 + 1e-9), f.cut_max);
 }
 
-// not inlined: the filter loop is unrolled over the 216 branch triples, and the
-// exact width is needed only for the few candidates between the two cuts
+// not inlined: the exact width is needed only for the few candidates between
+// the two cuts, which each lane walks after its unrolled filter loop
 __device__ __noinline__ bool fused_adaptive_pass(double ad, int32_t g1, int32_t g2, int32_t g3, const FusedArgs& f,
                                            const ModeGeom& geo) {
 #pragma clang fp contract(off)
@@ -244,6 +244,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                     // adaptive width: a bound for this triple of q-points, so the
                     // exact width is evaluated only where it can matter
                     double cut_q = f.cut;
+                    uint64_t xm[4] = {0, 0, 0, 0};  // candidates that need the exact width
                     if (ADAPT) {
                         double pm2[3], pm3[3];
                         fused_proj_max(f.vel, iq2, f, geo, pm2);
@@ -265,15 +266,40 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                                 const int32_t g3 = iq3 * NB + j3;
                                 const double delta = s3 > 0 ? d2 + w3[j3] : d2 - w3[j3];
                                 bool keep = ok2 && !(tri23 && g3 < g2) && w3[j3] >= f.floor_;
+                                bool exact = false;
                                 if (keep) {
                                     const double ad = fabs(delta);
                                     // sigma_p >= sigma, so the fixed cut keeps without the width
                                     keep = ad <= f.cut;
-                                    if (ADAPT && !keep && ad <= cut_q)
-                                        keep = fused_adaptive_pass(ad, g1, g2, g3, f, geo);
+                                    if (ADAPT) exact = !keep && ad <= cut_q;
                                 }
                                 const int c = (j1 * NB + j2) * NB + j3;
                                 if (keep) m[c >> 6] |= 1ull << (c & 63);
+                                if (ADAPT && exact) xm[c >> 6] |= 1ull << (c & 63);
+                            }
+                        }
+                    }
+                    // the candidates between the two cuts: each lane walks its own
+                    // set bits, so the wave runs as many exact widths as its busiest
+                    // lane needs, not one per candidate position any lane needs.
+                    // The mismatch is formed again with the same operations in the
+                    // same order, so the decision is the one the host makes.
+                    if (ADAPT) {
+#pragma unroll
+                        for (int wd = 0; wd < 4; ++wd) {
+                            uint64_t xb = xm[wd];
+                            while (xb) {
+                                const int bit = __builtin_ctzll(xb);
+                                xb &= xb - 1;
+                                const int c = wd * 64 + bit;
+                                const int32_t g1 = iq1 * NB + c / (NB * NB);
+                                const int32_t g2 = iq2 * NB + (c / NB) % NB;
+                                const int32_t g3 = iq3 * NB + c % NB;
+                                const double o1 = omega[g1], o2 = omega[g2], o3 = omega[g3];
+                                const double d1 = s1 > 0 ? w0 + o1 : w0 - o1;
+                                const double d2 = s2 > 0 ? d1 + o2 : d1 - o2;
+                                const double delta = s3 > 0 ? d2 + o3 : d2 - o3;
+                                if (fused_adaptive_pass(fabs(delta), g1, g2, g3, f, geo)) m[wd] |= 1ull << bit;
                             }
                         }
                     }
