@@ -38,6 +38,10 @@ struct FusedArgs {
     const double* vel;
     double recip[9];
     double factor, sigma, nsigma, cut_max;
+    // bound on |norm of the nine pair projections from the per-mode table P
+    // minus the same norm in the enumerator's arithmetic| (3e-12 max_g,d
+    // sum_k |v_gk b_dk| / N_d: several hundred times the rounding of either)
+    double perr;
 };
 
 // |Delta| <= nsigma * sigma_p for partners g1, g2, g3 of a four-phonon process,
@@ -299,7 +303,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                                 const double d1 = s1 > 0 ? w0 + o1 : w0 - o1;
                                 const double d2 = s2 > 0 ? d1 + o2 : d1 - o2;
                                 const double delta = s3 > 0 ? d2 + o3 : d2 - o3;
-                                if (fused_adaptive_pass(fabs(delta), g1, g2, g3, f, geo)) m[wd] |= 1ull << bit;
+                                const double ad = fabs(delta);
+                                // the width from the per-mode projection table brackets the
+                                // enumerator's; only a candidate inside the bracket needs the
+                                // enumerator's own arithmetic
+                                const double nrm = __builtin_sqrt(proj_sq(a.br.proj, g1, g2) +
+                                                                  proj_sq(a.br.proj, g1, g3) +
+                                                                  proj_sq(a.br.proj, g2, g3));
+                                constexpr double rel = 1e-13;
+                                const double sp_lo = f.factor / 3.0 * (nrm * (1.0 - rel) - f.perr) * (1.0 - rel);
+                                const double sp_hi = f.factor / 3.0 * (nrm * (1.0 + rel) + f.perr) * (1.0 + rel);
+                                const double thr_lo = f.nsigma * fmax(sp_lo, f.sigma) * (1.0 - rel);
+                                const double thr_hi = f.nsigma * fmax(sp_hi, f.sigma) * (1.0 + rel);
+                                const bool keep = ad <= thr_lo ||
+                                                  (ad <= thr_hi && fused_adaptive_pass(ad, g1, g2, g3, f, geo));
+                                if (keep) m[wd] |= 1ull << bit;
                             }
                         }
                     }

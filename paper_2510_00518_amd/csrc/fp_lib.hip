@@ -1005,6 +1005,15 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
                                  (double)c->mesh[d];
                 pmax[d] = std::max(pmax[d], p);
             }
+        double babs = 0.0;  // max over modes and directions of sum_k |v_k b_dk| / N_d
+        for (int64_t g = 0; g < nm; ++g)
+            for (int d = 0; d < 3; ++d) {
+                const double* v = c->h_vel.data() + g * 3;
+                const double p = (std::fabs(v[0] * f.recip[d * 3]) + std::fabs(v[1] * f.recip[d * 3 + 1]) +
+                                  std::fabs(v[2] * f.recip[d * 3 + 2])) / (double)c->mesh[d];
+                babs = std::max(babs, p);
+            }
+        f.perr = 3e-12 * babs;
         double b2 = 0.0;
         for (int d = 0; d < 3; ++d) b2 += 4.0 * pmax[d] * pmax[d];
         const double smax = std::max(f.factor * std::sqrt(3.0 * b2 / 9.0), sigma);
