@@ -284,40 +284,65 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                         }
                     }
                     // the candidates between the two cuts: each lane walks its own
-                    // set bits, so the wave runs as many exact widths as its busiest
-                    // lane needs, not one per candidate position any lane needs.
-                    // The mismatch is formed again with the same operations in the
-                    // same order, so the decision is the one the host makes.
+                    // set bits, two at a time so that the table reads of both are in
+                    // flight together (the walk waits on memory, not arithmetic), and
+                    // the wave runs as many steps as its busiest lane needs rather than
+                    // one per candidate position any lane needs.  The mismatch is
+                    // formed again with the same operations in the same order, so the
+                    // decision is the one the host makes.
                     if (ADAPT) {
 #pragma unroll
                         for (int wd = 0; wd < 4; ++wd) {
                             uint64_t xb = xm[wd];
+                            const int bit0 = xb ? __builtin_ctzll(xb) : 0;  // a real candidate, for idle slots
                             while (xb) {
-                                const int bit = __builtin_ctzll(xb);
-                                xb &= xb - 1;
-                                const int c = wd * 64 + bit;
-                                const int32_t g1 = iq1 * NB + c / (NB * NB);
-                                const int32_t g2 = iq2 * NB + (c / NB) % NB;
-                                const int32_t g3 = iq3 * NB + c % NB;
-                                const double o1 = omega[g1], o2 = omega[g2], o3 = omega[g3];
-                                const double d1 = s1 > 0 ? w0 + o1 : w0 - o1;
-                                const double d2 = s2 > 0 ? d1 + o2 : d1 - o2;
-                                const double delta = s3 > 0 ? d2 + o3 : d2 - o3;
-                                const double ad = fabs(delta);
-                                // the width from the per-mode projection table brackets the
-                                // enumerator's; only a candidate inside the bracket needs the
-                                // enumerator's own arithmetic
-                                const double nrm = __builtin_sqrt(proj_sq(a.br.proj, g1, g2) +
-                                                                  proj_sq(a.br.proj, g1, g3) +
-                                                                  proj_sq(a.br.proj, g2, g3));
-                                constexpr double rel = 1e-13;
-                                const double sp_lo = f.factor / 3.0 * (nrm * (1.0 - rel) - f.perr) * (1.0 - rel);
-                                const double sp_hi = f.factor / 3.0 * (nrm * (1.0 + rel) + f.perr) * (1.0 + rel);
-                                const double thr_lo = f.nsigma * fmax(sp_lo, f.sigma) * (1.0 - rel);
-                                const double thr_hi = f.nsigma * fmax(sp_hi, f.sigma) * (1.0 + rel);
-                                const bool keep = ad <= thr_lo ||
-                                                  (ad <= thr_hi && fused_adaptive_pass(ad, g1, g2, g3, f, geo));
-                                if (keep) m[wd] |= 1ull << bit;
+                                int bit[2];
+                                bool cv[2];
+#pragma unroll
+                                for (int k = 0; k < 2; ++k) {
+                                    cv[k] = xb != 0;
+                                    bit[k] = cv[k] ? __builtin_ctzll(xb) : bit0;
+                                    xb &= xb - 1;
+                                }
+                                double ad[2], nrm[2];
+                                int32_t ga[2], gb[2], gc[2];
+#pragma unroll
+                                for (int k = 0; k < 2; ++k) {
+                                    const int c = wd * 64 + bit[k];
+                                    const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
+                                    ga[k] = iq1 * NB + j1;
+                                    gb[k] = iq2 * NB + j2;
+                                    gc[k] = iq3 * NB + j3;
+                                    double o1 = w1[0], o2 = w2[0], o3 = w3[0];
+#pragma unroll
+                                    for (int j = 1; j < NB; ++j) {
+                                        o1 = j1 == j ? w1[j] : o1;
+                                        o2 = j2 == j ? w2[j] : o2;
+                                        o3 = j3 == j ? w3[j] : o3;
+                                    }
+                                    const double d1 = s1 > 0 ? w0 + o1 : w0 - o1;
+                                    const double d2 = s2 > 0 ? d1 + o2 : d1 - o2;
+                                    const double delta = s3 > 0 ? d2 + o3 : d2 - o3;
+                                    ad[k] = fabs(delta);
+                                    nrm[k] = __builtin_sqrt(proj_sq(a.br.proj, ga[k], gb[k]) +
+                                                            proj_sq(a.br.proj, ga[k], gc[k]) +
+                                                            proj_sq(a.br.proj, gb[k], gc[k]));
+                                }
+#pragma unroll
+                                for (int k = 0; k < 2; ++k) {
+                                    // the width from the per-mode projection table brackets the
+                                    // enumerator's; only a candidate inside the bracket needs
+                                    // the enumerator's own arithmetic
+                                    constexpr double rel = 1e-13;
+                                    const double sp_lo = f.factor / 3.0 * (nrm[k] * (1.0 - rel) - f.perr) * (1.0 - rel);
+                                    const double sp_hi = f.factor / 3.0 * (nrm[k] * (1.0 + rel) + f.perr) * (1.0 + rel);
+                                    const double thr_lo = f.nsigma * fmax(sp_lo, f.sigma) * (1.0 - rel);
+                                    const double thr_hi = f.nsigma * fmax(sp_hi, f.sigma) * (1.0 + rel);
+                                    bool keep = ad[k] <= thr_lo;
+                                    if (cv[k] && !keep && ad[k] <= thr_hi)
+                                        keep = fused_adaptive_pass(ad[k], ga[k], gb[k], gc[k], f, geo);
+                                    if (cv[k] && keep) m[wd] |= 1ull << bit[k];
+                                }
                             }
                         }
                     }
