@@ -25,6 +25,10 @@
 namespace fpk {
 
 constexpr int kFusedNb = 6;
+// FP64 instantiations: 24-tuple batches and three resident blocks per CU (16^3
+// cell 16.5 s against 19.4 s at 32 and two); the mixed ones keep 32 and two,
+// which measured faster for them
+constexpr int kFusedTB = 24;
 
 struct FusedArgs {
     int64_t n_units;  // n_types * n_rows * Nq
@@ -147,7 +151,7 @@ __device__ inline int select_bit(uint64_t w, int n) {
 // MIXED: the kept records are evaluated by the mixed-precision batch (split
 // bf16 MFMA build, FP32 contraction, FP64 weights) instead of the FP64 one.
 template <int MAXT, bool ADAPT, bool MIXED>
-__global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
+__global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
                                                      const double* __restrict__ occ, const double2* __restrict__ roots,
                                                      const double2* __restrict__ phit,
                                                      const int32_t* __restrict__ tmeta,
@@ -160,8 +164,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
     // dynamic LDS: the root table (FP64, or its bf16 splits: 16 bytes an entry
     // either way), then the term table
     extern __shared__ double2 sroots[];
-    __shared__ std::conditional_t<MIXED, float2, double2> sA[kWavesPerBlock][kTB][27];
-    __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
+    __shared__ std::conditional_t<MIXED, float2, double2> sA[kWavesPerBlock][MIXED ? kTB : kFusedTB][27];
+    __shared__ int32_t sQ[kWavesPerBlock][MIXED ? kTB : kFusedTB][2];
     const int32_t* tm;
     if constexpr (MIXED) {
         tbm_roots(reinterpret_cast<uint4*>(sroots), roots, a.geo.L);
@@ -411,7 +415,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_fused4(const double* __restrict__
                                                    reinterpret_cast<const uint4*>(sroots), sA[wave], sQ[wave], accg,
                                                    accw, dl, 0.0, nullptr);
                         else
-                            tb_batch<MAXT, false>(buf, pend, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
+                            tb_batch<MAXT, false, kBR, kFusedTB>(buf, pend, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
                                                   sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
                         pend = 0;
                     }
