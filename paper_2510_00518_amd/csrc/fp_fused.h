@@ -11,13 +11,16 @@
 //     (FP64 mismatch left to right, no contraction, "<=", frequency floor,
 //     triangle order on the global mode index) into a bit mask;
 //   - a wave-wide prefix sum of the mask popcounts orders the kept records by
-//     (q'', j', j'', j''') -- the enumerator's order -- and each batch of 128
-//     records is decoded from the masks (binary search over the prefix, select
-//     the n-th set bit; masks and prefixes are read across lanes by shuffles,
-//     so the kernel needs no more LDS than the list-driven one) and evaluated
-//     by tb_batch;
+//     (q'', j', j'', j''') -- the enumerator's order -- and the records are
+//     decoded from the masks (binary search over the prefix, select the n-th
+//     set bit; masks and prefixes are read across lanes by shuffles, so the
+//     kernel needs no more LDS than the list-driven one) into a 128-record
+//     buffer that fills across chunks of q'' and is evaluated by tb_batch (or
+//     tbm_batch) when full and at the end of the unit;
+//   - each XCD takes one slice of the q' range of every row;
 //   - the rates of a unit go to one partial per unit, summed per row by
-//     k_finalize in unit order.
+//     k_finalize in unit order; the unit's kept processes and tuples go to
+//     per-unit counters.
 // Compiled for nb = 6 (two-atom cells): the 216 candidate bits of a lane are
 // then compile-time positions in four 64-bit registers.
 #pragma once
