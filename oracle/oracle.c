@@ -41,9 +41,15 @@
  * weights follow from index equality (1, 1/2, 1/6).  Per-mode sums are
  * Neumaier-compensated.
  *
- * Parity unpinned: the absolute prefactors (pi hbar/4, pi hbar^2/8 and the
- * 1/2, 1/6 weights) are not printed by the paper; only relations between results
- * are pinned by the tests.
+ * The paper prints none of the absolute prefactors (pi hbar/4, pi hbar^2/8 and
+ * the 1/2, 1/6 weights).  They are pinned by a second derivation: the
+ * golden-rule transition rates of the supercell Hamiltonian (1/m!) sum Phi u..u,
+ * linearised in the row mode's occupation, equal this file's per-record rate for
+ * every process type (distinct partners); the 1/2, 1/6 weights of repeated
+ * partners are the ordered-sum convention, pinned by brute ordered sums equal to
+ * triangle-list sums.  The adaptive width (process_sigma) is this build's reading
+ * of a formula the paper names but does not print: it is pinned against its own
+ * definition (quadrature of the mismatch spread), not against the paper.
  *
  * Units: amu, Angstrom, ps; omega in rad/ps; Phi in eV/Angstrom^m; Gamma in 1/ps.
  * Build: plain C11, no fast-math, no FMA contraction.

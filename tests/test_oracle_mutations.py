@@ -1,8 +1,8 @@
 """The oracle's pins must catch plausible mistakes.
 
 Each case plants one mistake in a copy of oracle.c (on the CPU, in a temporary
-directory), builds it, and runs the pin tests against that build; the pins must
-fail.  The unmodified source must pass the same selection.
+directory), builds it, and runs the pin tests (the physics pins and the
+golden-rule pin of the prefactors) against that build; the pins must fail.  The unmodified source must pass the same selection.
 """
 import os
 import subprocess
@@ -53,12 +53,19 @@ MUTATIONS = {
         "        for (int j = i + 1; j < m; ++j) {\n            const double* vi",
         "        for (int j = i + 1; j < (i == 1 ? m : 0); ++j) {\n            const double* vi", "adaptive"),
     "adaptive width taken before the floor": ("    return sp > sigma ? sp : sigma;", "    return sp;", "adaptive"),
+    "three-phonon prefactor pi hbar / 2N": ("if (m == 3) return M_PI * hb / (4.0 * (double)N);",
+                                            "if (m == 3) return M_PI * hb / (2.0 * (double)N);"),
+    "four-phonon prefactor with 1/N": ("return M_PI * hb * hb / (8.0 * (double)N * (double)N);",
+                                       "return M_PI * hb * hb / (8.0 * (double)N);"),
+    "four-phonon prefactor with hbar, not hbar^2": ("return M_PI * hb * hb / (8.0 * (double)N * (double)N);",
+                                                    "return M_PI * hb / (8.0 * (double)N * (double)N);"),
 }
 
 
 def _run_pins(lib_path, select=None):
     env = dict(os.environ, ORACLE_LIB=lib_path, OMP_NUM_THREADS="4")
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+           os.path.join(ROOT, "tests", "test_oracle_golden_rule.py"),
            os.path.join(ROOT, "tests", "test_oracle_pins.py")] + (["-k", select] if select else [])
     return subprocess.run(cmd, env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
 
