@@ -7,6 +7,7 @@ import sys
 import numpy as np
 import pytest
 
+import knob_util
 import oracle
 from paper_2510_00518_amd import fp
 from paper_2510_00518_amd.synth import make_config, row_modes, small_config
@@ -45,16 +46,14 @@ def gpu_grad(ctx, cfg, lists, T, dLdG, chunk=None, precision=fp.FP_FP64):
     p = RatePath(cfg, ctx=ctx)
     p.set_lists(lists)
     p.load_ifc(phi3=p.phi3, phi4=p.phi4)
-    if chunk:
-        fp.fp_set_knob(ctx, "grad_chunk", chunk)
     dl = torch.as_tensor(dLdG).cuda()
     d3 = torch.zeros_like(p.phi3) if p.phi3 is not None else None
     d4 = torch.zeros_like(p.phi4) if p.phi4 is not None else None
-    fp.fp_rates_backward(ctx, p.lists3 + p.lists4, T, cfg["sigma"], dl, d3 if p.lists3 else None,
-                         d4 if p.lists4 else None, precision=precision)
-    fp.fp_check(ctx)
-    torch.cuda.synchronize()
-    fp.fp_set_knob(ctx, "grad_chunk", 8192)
+    with knob_util.knobs(ctx, **({"grad_chunk": chunk} if chunk else {})):
+        fp.fp_rates_backward(ctx, p.lists3 + p.lists4, T, cfg["sigma"], dl, d3 if p.lists3 else None,
+                             d4 if p.lists4 else None, precision=precision)
+        fp.fp_check(ctx)
+        torch.cuda.synchronize()
     return (d3.cpu().numpy() if d3 is not None else None), (d4.cpu().numpy() if d4 is not None else None)
 
 

@@ -15,6 +15,7 @@ import sys
 import numpy as np
 import pytest
 
+import knob_util
 import oracle
 from paper_2510_00518_amd import fp
 from paper_2510_00518_amd.synth import SIGMA_FLOOR, adaptive_broadening, make_config, row_modes, small_config
@@ -66,19 +67,18 @@ def oracle_mode_rates(S, n_modes, lists, T, floor):
     return gam, wp
 
 
-def gpu_rates(ctx, cfg, b, lists, T, floor, variant=7, precision=fp.FP_FP64):
+def gpu_rates(ctx, cfg, b, lists, T, floor, variant=knob_util.DEFAULT_VARIANT, precision=fp.FP_FP64):
     import torch
     from paper_2510_00518_amd.driver import RatePath
-    fp.fp_set_knob(ctx, "variant", variant)
-    p = RatePath(dict(cfg, sigma=floor), ctx=ctx, precision=precision)
-    p.set_broadening(b)
-    p.set_lists(lists)
-    gam, wp = p.outputs(len(T))
-    p.load_ifc()
-    p.rates(T, gam, wp)
-    fp.fp_check(ctx)
-    torch.cuda.synchronize()
-    fp.fp_set_knob(ctx, "variant", 7)
+    with knob_util.knobs(ctx, variant=variant):
+        p = RatePath(dict(cfg, sigma=floor), ctx=ctx, precision=precision)
+        p.set_broadening(b)
+        p.set_lists(lists)
+        gam, wp = p.outputs(len(T))
+        p.load_ifc()
+        p.rates(T, gam, wp)
+        fp.fp_check(ctx)
+        torch.cuda.synchronize()
     return gam.cpu().numpy(), wp.cpu().numpy()
 
 
@@ -126,7 +126,7 @@ def four_phonon_case(mesh, floor, stride):
     return _CACHE4[key]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 4, 5, 7])
+@pytest.mark.parametrize("variant", [0, 1, 4, 5, 6, 7])
 @pytest.mark.parametrize("mesh,floor,stride", CASES)
 def test_adaptive_four_phonon(ctx, mesh, floor, stride, variant):
     cfg, b, lists, T, (go, wo) = four_phonon_case(mesh, floor, stride)
@@ -212,6 +212,7 @@ def test_adaptive_fcc8_full_size_sampled(ctx):
     in the default launch; two sampled modes against the oracle."""
     import torch
     from paper_2510_00518_amd.driver import RatePath, host_lists
+    assert fp.fp_get_knob(ctx, "variant") == knob_util.DEFAULT_VARIANT
     cfg = make_config("fcc8_4ph")
     b = adaptive_broadening(cfg)
     say("fcc8_4ph adaptive: enumerating (library, host)")

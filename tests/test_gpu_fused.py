@@ -14,6 +14,7 @@ import time
 import numpy as np
 import pytest
 
+import knob_util
 import oracle
 from paper_2510_00518_amd import fp
 from paper_2510_00518_amd.synth import make_config, row_modes, small_config
@@ -279,14 +280,13 @@ def test_fused_matches_lists_fcc8(ctx):
     cfg = make_config("fcc8_4ph")
     lists = host_lists(cfg, TYPES4)
     p = RatePath(cfg, ctx=ctx)
-    fp.fp_set_knob(ctx, "variant", 4)
+    assert fp.fp_get_knob(ctx, "variant") == knob_util.DEFAULT_VARIANT
     p.set_lists(lists)
     gam, _ = p.outputs(1)
     p.load_ifc()
     p.rates([300.0], gam, order=4)
     torch.cuda.synchronize()
     g_list = gam.cpu().numpy()
-    fp.fp_set_knob(ctx, "variant", 1)
     g, _, kept = fused_rates(ctx, cfg, row_modes(cfg), [300.0])
     n_proc, n_tup = fp.fp_fused_counts(ctx)
     n_rec = sum(int(v[1][-1]) for v in lists.values())

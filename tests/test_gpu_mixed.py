@@ -68,8 +68,6 @@ def gpu_rates(ctx, cfg, lists, T, precision, sigma=None):
     cfg = dict(cfg)
     if sigma is not None:
         cfg["sigma"] = sigma
-    for k, v in {"ppl": 2, "blocks_per_cu": 0, "variant": 1}.items():
-        fp.fp_set_knob(ctx, k, v)
     p = RatePath(cfg, ctx=ctx, precision=precision)
     p.set_lists(lists)
     gam, wp = p.outputs(len(T))

@@ -15,6 +15,7 @@ import sys
 import numpy as np
 import pytest
 
+import knob_util
 import oracle
 from paper_2510_00518_amd import fp
 from paper_2510_00518_amd.synth import make_config, row_modes, small_config
@@ -69,17 +70,14 @@ def gpu_rates(ctx, cfg, lists, T, sigma=None, knobs=None):
     cfg = dict(cfg)
     if sigma is not None:
         cfg["sigma"] = sigma
-    for k, v in (knobs or {}).items():
-        fp.fp_set_knob(ctx, k, v)
-    p = RatePath(cfg, ctx=ctx)
-    p.set_lists(lists)
-    gam, wp = p.outputs(len(T))
-    p.load_ifc()
-    p.rates(T, gam, wp)
-    fp.fp_check(ctx)
-    torch.cuda.synchronize()
-    for k in (knobs or {}):
-        fp.fp_set_knob(ctx, k, {"ppl": 2, "blocks_per_cu": 0, "variant": 1}[k])
+    with knob_util.knobs(ctx, **(knobs or {})):
+        p = RatePath(cfg, ctx=ctx)
+        p.set_lists(lists)
+        gam, wp = p.outputs(len(T))
+        p.load_ifc()
+        p.rates(T, gam, wp)
+        fp.fp_check(ctx)
+        torch.cuda.synchronize()
     return gam.cpu().numpy(), wp.cpu().numpy()
 
 
@@ -265,6 +263,7 @@ def test_fcc8_4ph_full_size_sampled(ctx):
     configuration; sampled modes checked against the oracle one by one."""
     import torch
     from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists
+    assert fp.fp_get_knob(ctx, "variant") == knob_util.DEFAULT_VARIANT
     cfg = make_config("fcc8_4ph")
     say("fcc8_4ph: enumerating (library, host)")
     lists = host_lists(cfg, TYPES3 + TYPES4)

@@ -17,6 +17,7 @@ import sys
 import numpy as np
 import pytest
 
+import knob_util
 import oracle
 from paper_2510_00518_amd import fp
 from paper_2510_00518_amd.synth import make_config
@@ -72,9 +73,8 @@ def test_uneven_autotuned_launch_matches_oracle(workload, tmp_path):
     g = rates(p, T)[0]
 
     # every mode: the chosen launch against the per-process FP64 form
-    for k, v in {"variant": 1, "ppl": 2, "blocks_per_cu": 0}.items():
-        fp.fp_set_knob(p.ctx, k, v)
-    g1 = rates(p, T)[0]
+    with knob_util.knobs(p.ctx, variant=1, ppl=2, blocks_per_cu=0):
+        g1 = rates(p, T)[0]
     scale = np.abs(g1).max()
     np.testing.assert_allclose(g, g1, rtol=1e-12, atol=1e-12 * scale)
 
