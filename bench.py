@@ -1,29 +1,38 @@
-"""Benchmark of the four-phonon rate path on one MI355X.
+"""Benchmark of the three- plus four-phonon rate path on one MI355X.
 
-Workload: the 8x8x8 four-phonon FP64 configuration (2-atom diamond cell,
-Oh-irreducible q1 set, 32 cubic + 94 quartic force-constant terms, Gaussian
-width 0.1 THz, |Delta| <= 3 sigma, T = 300 K).  Lists are enumerated once on
-the host by the library and uploaded before timing.  One step is the whole hot
-path: force-constant load (order 3 and 4, device-resident values), 3ph and 4ph
-rates accumulated into Gamma = Gamma3 + Gamma4, and kappa_RTA.
+Headline workload: the 16x16x16 two-atom diamond cell (145 Oh-irreducible q1,
+62 cubic + 164 quartic force-constant terms, Gaussian width 0.1 THz,
+|Delta| <= 3 sigma, T = 300/600/900 K) in FP64.  Its 4.9e10 four-phonon
+processes would need about 0.4 TB of lists, so they are generated on the GPU
+(fp_rates4_fused); the 3ph lists (6e5 records) come from the host enumerator and
+are resident before timing.
 
-Prints one JSON line.  value = 4ph processes per second of the whole FP64 step;
-"mixed" holds the same step with the order-4 rates in mixed precision (bf16
-split MFMA, FP32 contraction, FP64 weights) and its errors against FP64.
-roofline: the dominant kernel (the order-4 rate kernel) timed with HIP events
-on its own stream, with the algorithmic FLOP of the form that ran: (320 n4 + 60)
-per process for the per-process forms; 216 n4 per (lambda, q', q'') tuple on
-FP64 MFMA (and 312 n_groups + 60 per process on the VALU) for the tuple-batched
-form.  backward: kappa_RTA with dkappa/dGamma and the adjoint of both orders.
-adaptive: the same step with the per-process width sigma_p = max(0.1 sigma0_p,
-0.01 THz) from the group velocities (the paper's broadening scale 0.1) on lists
-the host enumerates with that width.
-cpu_baseline: the FP64 oracle (list mode) on a bounded sample of the same lists
-on this host's cores.  --paper-scale adds the 16x16x16 two-atom cell (every row,
-three types, T = 300/600/900 K) through GPU-side enumeration, FP64 and mixed,
-each with a roofline from the library's tuple count; with --paper-scale-adaptive
-the adaptive width too.  They hold the GPU for about a minute, so they are not
-part of the default run.
+A step is one pass of the whole hot path over one batch of the cell: the q1
+points are dealt round-robin into 20 batches, and step k takes batch k mod 20
+through force-constant loads (order 3 and 4, device-resident values), the 3ph
+rates, the fused 4ph rates accumulated into Gamma = Gamma3 + Gamma4, and the
+batch's share of kappa_RTA (kappa is a sum over q1).  Twenty steps therefore
+evaluate the whole cell once; kappa is the sum of the 20 batch shares.  An
+untimed reference pass over all batches gives the work counts per batch
+(processes, (lambda, q', q'') tuples) and the FP64 reference of Gamma and kappa.
+
+Prints one JSON line.  value = 4ph processes per second of the timed FP64 steps.
+roofline: the fused order-4 kernel, timed with HIP events on its stream, with
+the algorithmic FLOP of the tuple form that ran (216 per phase key per tuple on
+FP64 matrix cores, 312 per partner group + 60 per process on the VALU), against
+the FP64 peak; also its fraction of the FP32 vector peak and the per-process
+form's equivalent rate.
+mixed: one timed pass over all batches with the order-4 rates in mixed
+precision, and its error against the FP64 reference (per mode and kappa).
+backward: the adjoint workload (2-atom cell, 8^3 mesh, 62 cubic + 164 quartic
+terms, host lists): forward step and backward step (kappa with dkappa/dGamma,
+adjoint of both orders, V recomputed), median of the timed runs; bwd/fwd ratio.
+lists_8: the 8^3 four-phonon workload (32 + 94 terms) through host lists and the
+list-driven tuple-batched kernel.  adaptive_8: the same with the per-process
+width max(0.1 sigma0_p, 0.01 THz).  --paper-scale-adaptive adds one pass of the
+16^3 cell with the adaptive width.
+cpu_baseline: the FP64 oracle (list mode) on seeded slices of host-enumerated
+16^3 four-phonon rows, all host threads, and one thread beside it.
 """
 import argparse
 import hashlib
@@ -37,11 +46,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 FP64 lanes x 2 FLOP x 2.4 GHz (vector; FP64 MFMA the same)
+PEAK_FP64_TFLOPS = 78.6    # FP64 vector and FP64 matrix alike: 256 CU x 4 SIMD x 2.4 GHz x 32 FLOP/clk
+PEAK_FP32_TFLOPS = 157.3   # FP32 vector (packed); the kernels issue unpacked FP32, whose rate equals FP64's
 PEAK_BF16_TFLOPS = 2500.0  # dense bf16 MFMA
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rates4_fcc8_4ph.json")
-# device code of the tuple-batched FP64 kernel (its launch shape is the variant knob)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_00518_amd", "csrc", f) for f in ("fp_kernels.h", "fp_batched.h")]
+N_BATCH = 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused4_fcc16_34ph.json")
+# device code of the fused kernel and what it calls
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_00518_amd", "csrc", f)
+                  for f in ("fp_kernels.h", "fp_batched.h", "fp_mixed.h", "fp_fused.h")]
 
 
 def kernel_source_hash():
@@ -55,38 +67,53 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, lists, seconds, seed=251000518 + 6):
-    """Oracle list-mode throughput on seeded slices of the 4ph lists (bounded time)."""
+def cpu_baseline(cfg, seconds, seconds_single, seed=251000518 + 6):
+    """Oracle list-mode throughput on seeded slices of host-enumerated 16^3
+    four-phonon (+-) rows: all host threads for `seconds`, then one thread."""
     import oracle
     from paper_2510_00518_amd import fp
+    from paper_2510_00518_amd.synth import row_modes
     S = oracle.System(cfg)
-    rm, off, rec = lists[fp.FP_4PM]
     rng = np.random.default_rng(seed)
+    rows = rng.choice(row_modes(cfg), size=3, replace=False)
+    rm, off, rec = fp.enumerate_list(fp.FP_4PM, cfg, row_mode=rows)
     slice_len = 20000
-    done, spent, rows_used = 0, 0.0, 0
-    while spent < seconds:
-        r = int(rng.integers(len(rm)))
-        n = int(off[r + 1] - off[r])
-        if n == 0:
-            continue
-        a = int(off[r]) + int(rng.integers(max(1, n - slice_len)))
-        sub = rec[a:min(a + slice_len, int(off[r + 1]))]
-        t0 = time.perf_counter()
-        S.rates(fp.FP_4PM, rm[r:r + 1], [300.0], cfg["sigma"], row_off=np.array([0, len(sub)]), rec=sub)
-        spent += time.perf_counter() - t0
-        done += len(sub)
-        rows_used += 1
-    return {"value": done / spent, "unit": "processes/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{done} four-phonon (+-) records in {rows_used} seeded slices of {slice_len} from the "
-                      f"benchmark's lists, FP64 list mode, {spent:.1f} s"}
+
+    def run(budget):
+        done, spent, n_sl = 0, 0.0, 0
+        while spent < budget:
+            r = int(rng.integers(len(rm)))
+            n = int(off[r + 1] - off[r])
+            if n == 0:
+                continue
+            a = int(off[r]) + int(rng.integers(max(1, n - slice_len)))
+            sub = rec[a:min(a + slice_len, int(off[r + 1]))]
+            t0 = time.perf_counter()
+            S.rates(fp.FP_4PM, rm[r:r + 1], [float(x) for x in cfg["T"]], cfg["sigma"],
+                    row_off=np.array([0, len(sub)]), rec=sub)
+            spent += time.perf_counter() - t0
+            done += len(sub)
+            n_sl += 1
+        return done, spent, n_sl
+
+    cores = oracle.threads()
+    d_all, s_all, n_all = run(seconds)
+    oracle.set_threads(1)
+    try:
+        d_one, s_one, _ = run(seconds_single)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": d_all / s_all, "unit": "processes/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": d_one / s_one,
+            "sample": f"{d_all} four-phonon (+-) records of the 16^3 cell in {n_all} seeded slices of up to "
+                      f"{slice_len} from three host-enumerated rows (T = 300/600/900 K), FP64 list mode, "
+                      f"{s_all:.1f} s on {cores} threads; single thread {d_one} records in {s_one:.1f} s"}
 
 
-def tuple_stats(lists, nb, unit=128):
-    """Distinct (lambda, q', q'') tuples of the 4ph lists, and the tuples the
-    tuple-batched kernels form (a tuple split by a 128-record unit boundary
-    counts once per unit)."""
+def tuple_stats(lists, nb):
+    """Distinct (lambda, q', q'') tuples of the 4ph lists."""
     from paper_2510_00518_amd import fp
-    n_tup = n_unit_tup = 0
+    n_tup = 0
     for t, (rm, off, rec) in lists.items():
         if fp.ORDER[t] != 4 or len(rec) == 0:
             continue
@@ -94,161 +121,316 @@ def tuple_stats(lists, nb, unit=128):
         q2 = ((rec >> np.uint64(24)) & np.uint64(0xFFFFFF)).astype(np.int64) // nb
         key = q1 * (1 << 24) + q2
         del q1, q2
-        row_start = np.zeros(len(rec), dtype=bool)
-        row_start[off[:-1][np.diff(off) > 0]] = True
-        new = row_start.copy()
+        new = np.zeros(len(rec), dtype=bool)
+        new[off[:-1][np.diff(off) > 0]] = True
         new[1:] |= key[1:] != key[:-1]
         n_tup += int(new.sum())
-        pos = np.arange(len(rec), dtype=np.int64) - np.repeat(off[:-1], np.diff(off))
-        n_unit_tup += int((new | (pos % unit == 0)).sum())
-    return n_tup, n_unit_tup
+    return n_tup
 
 
-def partner_groups(ifc):
-    """Partner-atom groups of a force-constant list (distinct atoms of slots 1..m-1)."""
-    return len({tuple(a[1:]) for a in np.asarray(ifc["atoms"]).tolist()})
-
-
-def paper_scale(torch, fp, RatePath, adaptive=False, precision=None):
-    """The 16^3 two-atom cell: every active row and the three four-phonon types
-    in one fp_rates4_fused call (lists generated on the GPU), T = 300/600/900 K;
-    with adaptive, the per-process width max(0.1 sigma0_p, 0.01 THz)."""
-    from paper_2510_00518_amd.synth import SIGMA_FLOOR, adaptive_broadening, make_config, row_modes
-    cfg = make_config("fcc16_34ph")
-    if adaptive:
-        cfg = dict(cfg, sigma=SIGMA_FLOOR)
-    T = [float(x) for x in cfg["T"]]
-    p = RatePath(cfg, device=0, precision=fp.FP_FP64 if precision is None else precision)
-    if adaptive:
-        p.set_broadening(adaptive_broadening(cfg))
-    p.set_fused(row_modes(cfg), 7)
-    gam, wp = p.outputs(len(T))
-    p.load_ifc()
-    fp.fp_profile(p.ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p.rates(T, gam, wp, order=4)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    k_ms, n = fp.fp_profile_read(p.ctx, 34)
-    fp.fp_profile(p.ctx, False)
-    fp.fp_check(p.ctx)
-    kept = int(p.kept.cpu()[0])
-    n_proc, n_tup = fp.fp_fused_counts(p.ctx)
-    n4 = int(cfg["ifc4"]["n_terms"])
-    n_groups = partner_groups(cfg["ifc4"])
-    p.close()
-    mixed = precision == fp.FP_MIXED
-    # the fused kernel's algorithmic work in the tuple form that ran: 216 n4 FLOP per
-    # (lambda, q', q'') tuple on matrix cores, (312 n_groups + 60) per process on the VALU
-    sec = k_ms / max(1, n) * 1e-3
-    f_build = 216 * n4 * n_tup
-    f_contract = (312 * n_groups + 60) * n_proc
-    if mixed:
-        roof = {"bound": "mfma", "achieved": 6 * f_build / sec / 1e12, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "kernel": "k_fused4 mixed (bf16 split MFMA + FP32 VALU)",
-                "work": f"6 bf16 products per FP32-accurate product, 216*n4 FLOP per tuple, n4 = {n4}, {n_tup} tuples",
-                "fp32_equivalent_tflops": f_build / sec / 1e12}
+def form_work(fp, ctx, n_proc, n_tup, folded):
+    """Algorithmic FLOP of the tuple form that ran, over n_proc processes in
+    n_tup (lambda, q', q'') tuples, from the loaded order-4 tables.
+    List form: 216 per phase key and tuple (27 complex components of the
+    phase-weighted force constants) and 312 per partner group + 60 per process
+    (contraction, weights).  Folded fused form (keys and the first partner
+    folded per unit): 432 per pkey and tuple (54 complex components) and 96 per
+    pair group + 60 per process."""
+    info = fp.fp_ifc_info(ctx, 4)
+    if folded:
+        build = 432 * info["n_pkeys"] * n_tup
+        contract = (96 * info["n_pgroups"] + 60) * n_proc
+        desc = (f"432 FLOP per pkey per (lambda, q', q'') tuple ({info['n_pkeys']} pkeys from {info['n_terms']} "
+                f"terms, {n_tup} tuples) + (96 x {info['n_pgroups']} pair groups + 60) per process "
+                f"({n_proc} processes)")
     else:
-        roof = {"bound": "mfma", "achieved": f_build / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "kernel": "k_fused4 (GPU enumeration + tuple-batched FP64 MFMA + FP64 VALU)",
-                "work": f"216*n4 FLOP per (lambda, q', q'') tuple on FP64 MFMA, n4 = {n4}, {n_tup} tuples"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["valu_achieved"] = f_contract / sec / 1e12
-    roof["per_process_form_equivalent_tflops"] = (320 * n4 + 60) * n_proc / sec / 1e12
-    roof["kernel_ms"] = k_ms / max(1, n)
-    roof["traffic"] = None
-    log(f"bench: 16^3 fused{' adaptive' if adaptive else ''}{' mixed' if mixed else ''}: {kept} processes in {dt:.2f} s")
-    width = "adaptive width max(0.1 sigma0, 0.01 THz)" if adaptive else "sigma 0.1 THz"
-    return {"workload": f"4ph {'mixed' if mixed else 'FP64'}, 2-atom diamond cell, 16x16x16 mesh, "
-                        "Oh-irreducible q1 (145), 62 cubic + "
-                        f"{int(cfg['ifc4']['n_terms'])} quartic terms, T = 300/600/900 K, {width}, "
-                        "lists generated on the GPU",
-            "processes_4ph": kept, "tuples_4ph": n_tup, "seconds": dt, "value": kept / dt, "unit": "processes/s",
-            "kernel_ms": k_ms / max(1, n), "rows": int(len(row_modes(cfg))), "roofline": roof}
+        build = 216 * info["n_keys"] * n_tup
+        contract = (312 * info["n_groups"] + 60) * n_proc
+        desc = (f"216 FLOP per phase key per (lambda, q', q'') tuple ({info['n_keys']} keys from "
+                f"{info['n_terms']} terms, {n_tup} tuples) + (312 x {info['n_groups']} partner groups + 60) "
+                f"per process ({n_proc} processes)")
+    per_process_form = (320 * info["n_terms"] + 60) * n_proc
+    return build, contract, per_process_form, desc
 
 
-def run_forward(path, T, steps, warmup, tag, torch, fp):
-    """Warm up, then time `steps` whole steps; returns ms/step, the tagged
-    kernel's ms/launch, and the last step's Gamma and kappa (host copies)."""
+def roofline(fp, ctx, n_proc, n_tup, kernel_s, kernel, mixed=False, folded=False):
+    build, contract, f4, desc = form_work(fp, ctx, n_proc, n_tup, folded)
+    total = build + contract
+    r = {"bound": "mfma", "unit": "TFLOP/s", "kernel": kernel, "work": desc, "kernel_ms": kernel_s * 1e3}
+    if mixed:
+        r["achieved"] = (6 * build + contract) / kernel_s / 1e12
+        r["peak"] = PEAK_BF16_TFLOPS
+        r["work"] += "; 6 bf16 products per FP32-accurate product in the build"
+    else:
+        r["achieved"] = total / kernel_s / 1e12
+        r["peak"] = PEAK_FP64_TFLOPS
+    r["frac"] = r["achieved"] / r["peak"]
+    r["fp64_tflops"] = total / kernel_s / 1e12
+    r["frac_fp64"] = r["fp64_tflops"] / PEAK_FP64_TFLOPS
+    r["frac_fp32"] = r["fp64_tflops"] / PEAK_FP32_TFLOPS
+    r["mfma_part_tflops"] = build / kernel_s / 1e12
+    r["valu_part_tflops"] = contract / kernel_s / 1e12
+    r["per_process_form_equivalent_tflops"] = f4 / kernel_s / 1e12
+    return r
+
+
+class Batched16:
+    """The 16^3 cell as N_BATCH q1 batches, each with its own 3ph lists, fused
+    4ph rows, Gamma buffer and kappa share."""
+
+    def __init__(self, torch, fp, cfg, ctx, broadening=None):
+        from paper_2510_00518_amd.driver import TYPES3, host_lists
+        from paper_2510_00518_amd.synth import row_modes
+        self.torch, self.fp, self.cfg, self.ctx = torch, fp, cfg, ctx
+        dev = torch.device("cuda", 0)
+        self.T = [float(x) for x in cfg["T"]]
+        nb = cfg["nb"]
+        fp.fp_load_modes(ctx, cfg["mesh"], cfg["n_atoms"], cfg["lattice"], cfg["masses"], cfg["omega"], cfg["evec"],
+                         cfg["vel"], cfg["omega_floor"])
+        if broadening is not None:
+            fp.fp_set_broadening(ctx, broadening)
+        self.phi3 = torch.as_tensor(cfg["ifc3"]["phi"]).to(dev)
+        self.phi4 = torch.as_tensor(cfg["ifc4"]["phi"]).to(dev)
+        rows_all = np.asarray(row_modes(cfg))
+        q1, w = np.asarray(cfg["q1"]), np.asarray(cfg["q1_weight"], np.float64)
+        self.batches = []
+        for b in range(N_BATCH):
+            sel = np.arange(b, len(q1), N_BATCH)
+            rows = rows_all[np.isin(rows_all // nb, q1[sel])].astype(np.int32)
+            lists = host_lists(cfg, TYPES3, rows=rows, broadening=broadening)
+            pls = [fp.PList.from_host(t, rm, off, rec, dev) for t, (rm, off, rec) in sorted(lists.items())]
+            self.batches.append(dict(
+                rows=torch.as_tensor(rows).to(dev), lists3=pls, n3=sum(pl.n_rec for pl in pls),
+                q1=torch.as_tensor(np.ascontiguousarray(q1[sel], np.int32)).to(dev),
+                q1w=torch.as_tensor(np.ascontiguousarray(w[sel])).to(dev),
+                gam=torch.zeros((len(self.T), cfg["omega"].size), dtype=torch.float64, device=dev),
+                kap=torch.zeros((len(self.T), 9), dtype=torch.float64, device=dev),
+                kept=torch.zeros(1, dtype=torch.int64, device=dev)))
+
+    def step(self, b, precision):
+        fp, cfg, B = self.fp, self.cfg, self.batches[b]
+        fp.fp_load_ifc(self.ctx, 3, cfg["ifc3"]["atoms"], cfg["ifc3"]["cells"], self.phi3)
+        fp.fp_load_ifc(self.ctx, 4, cfg["ifc4"]["atoms"], cfg["ifc4"]["cells"], self.phi4)
+        fp.fp_rates3(self.ctx, B["lists3"], self.T, cfg["sigma"], fp.FP_FP64, B["gam"], None)
+        fp.fp_rates4_fused(self.ctx, B["rows"], 7, self.T, cfg["sigma"], cfg["nsigma"], precision | fp.FP_ACCUMULATE,
+                           B["gam"], None, n_kept=B["kept"])
+        fp.fp_kappa_rta(self.ctx, B["q1"], B["q1w"], self.T, B["gam"], B["kap"])
+
+    def reference_pass(self, precision):
+        """Every batch once, untimed: per-batch (4ph processes, tuples), Gamma
+        over all modes and kappa (sum of the batch shares)."""
+        torch, fp = self.torch, self.fp
+        counts = []
+        for b in range(N_BATCH):
+            self.step(b, precision)
+            counts.append(fp.fp_fused_counts(self.ctx))
+            fp.fp_check(self.ctx)
+        torch.cuda.synchronize()
+        return np.array(counts, np.int64), self.gamma(), self.kappa()
+
+    def gamma(self):
+        g = np.zeros((len(self.T), self.cfg["omega"].size))
+        for B in self.batches:
+            rows = B["rows"].cpu().numpy()
+            g[:, rows] = B["gam"].cpu().numpy()[:, rows]
+        return g
+
+    def kappa(self):
+        k = sum(B["kap"].cpu().numpy() for B in self.batches)
+        return (k[:, 0] + k[:, 4] + k[:, 8]) / 3
+
+    def timed(self, steps, warmup, precision, first=0):
+        """warmup untimed steps, then `steps` timed ones (batches cyclic from
+        `first`); returns per-step ms, the batches timed, and the fused and 3ph
+        kernels' summed ms."""
+        torch, fp = self.torch, self.fp
+        b = first
+        for i in range(warmup):
+            self.step(b % N_BATCH, precision)
+            torch.cuda.synchronize()
+            log(f"bench: warmup step {i + 1}/{warmup} done (batch {b % N_BATCH})")
+            b += 1
+        fp.fp_check(self.ctx)
+        fp.fp_profile(self.ctx, True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        done = []
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(steps):
+            self.step(b % N_BATCH, precision)
+            ev[i + 1].record()
+            done.append(b % N_BATCH)
+            b += 1
+        torch.cuda.synchronize()
+        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+        k4, n4 = fp.fp_profile_read(self.ctx, 34)
+        k3, n3 = fp.fp_profile_read(self.ctx, 3)
+        fp.fp_profile(self.ctx, False)
+        fp.fp_check(self.ctx)
+        return per, done, k4, k3
+
+
+def run_lists(torch, fp, path, T, steps, warmup, tag):
+    """Warm up, then time `steps` whole list-driven steps one by one; returns
+    per-step ms, the tagged kernel's ms per launch, and Gamma, kappa."""
     gamma = torch.zeros((len(T), path.n_modes), dtype=torch.float64, device="cuda")
     kappa = torch.zeros((len(T), 9), dtype=torch.float64, device="cuda")
-    for i in range(warmup):
+    for _ in range(warmup):
         path.step(T, gamma, kappa)
-        torch.cuda.synchronize()
-        log(f"bench: warmup step {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
     fp.fp_check(path.ctx)
     fp.fp_profile(path.ctx, True)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
         path.step(T, gamma, kappa)
-    e1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / steps
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     k_ms, launches = fp.fp_profile_read(path.ctx, tag)
     fp.fp_profile(path.ctx, False)
     fp.fp_check(path.ctx)
-    return ms_step, k_ms / max(1, launches), gamma, kappa
+    return per, k_ms / max(1, launches), gamma, kappa
+
+
+def trace_kappa(k):
+    k = k.cpu().numpy()
+    return (k[:, 0] + k[:, 4] + k[:, 8]) / 3
+
+
+def leg_lists_8(torch, fp, args, lists, n_tup):
+    """8^3 four-phonon workload on host lists (list-driven tuple-batched kernel)."""
+    from paper_2510_00518_amd.driver import RatePath
+    from paper_2510_00518_amd.synth import make_config
+    cfg = make_config("fcc8_4ph")
+    T = [float(x) for x in cfg["T"]]
+    path = RatePath(cfg, device=0)
+    if args.variant is not None:
+        fp.fp_set_knob(path.ctx, "variant", args.variant)
+    variant = fp.fp_get_knob(path.ctx, "variant")
+    path.set_lists(lists)
+    per, k_ms, _, kap = run_lists(torch, fp, path, T, args.steps_8, 2, 4)
+    n4 = path.n_proc4
+    out = {"workload": "4ph FP64, 2-atom diamond cell, 8x8x8 mesh, Oh-irreducible q1 (29), 32 cubic + "
+                       f"{int(cfg['ifc4']['n_terms'])} quartic terms, sigma 0.1 THz, T = 300 K, host lists",
+           "value": n4 / (np.median(per) * 1e-3), "unit": "processes/s", "ms_per_step_median": float(np.median(per)),
+           "ms_per_step_mean": float(per.mean()), "runs": len(per), "processes_4ph": n4,
+           "processes_3ph": path.n_proc3, "tuples_4ph": n_tup, "variant": variant,
+           "roofline": roofline(fp, path.ctx, n4, n_tup, k_ms * 1e-3,
+                                f"k_rates4b variant {variant} (list-driven tuple-batched FP64)")}
+    # mixed precision on the same lists
+    path.precision = fp.FP_MIXED
+    per_m, km_ms, _, kap_m = run_lists(torch, fp, path, T, args.steps_8, 1, 24)
+    k0, km = trace_kappa(kap), trace_kappa(kap_m)
+    out["mixed"] = {"value": n4 / (np.median(per_m) * 1e-3), "ms_per_step_median": float(np.median(per_m)),
+                    "kappa_rel_err_vs_fp64": float(np.max(np.abs(km - k0) / np.abs(k0))),
+                    "roofline": roofline(fp, path.ctx, n4, n_tup, km_ms * 1e-3, "k_rates4m (list-driven, mixed)",
+                                         mixed=True)}
+    path.close()
+    log(f"bench: 8^3 lists FP64 {np.median(per):.3f} ms/step (kernel {k_ms:.3f} ms), mixed {np.median(per_m):.3f}")
+    return out
+
+
+def leg_backward(torch, fp, args, lists):
+    """Adjoint workload: 8^3 lists, 62 cubic + 164 quartic terms, T = 300 K."""
+    from paper_2510_00518_amd.driver import RatePath
+    from paper_2510_00518_amd.synth import make_config
+    cfg = make_config("fcc8_adjoint")
+    T = [300.0]
+    path = RatePath(cfg, device=0)
+    path.set_lists(lists)
+    per_f, _, gamma, kappa = run_lists(torch, fp, path, T, args.steps_8, 2, 4)
+    dk = torch.zeros_like(gamma)
+    d3 = torch.zeros_like(path.phi3)
+    d4 = torch.zeros_like(path.phi4)
+
+    def backward_step():
+        path.kappa(T, gamma, kappa, dk)
+        fp.fp_rates_backward(path.ctx, path.lists3 + path.lists4, T, cfg["sigma"], dk, d3, d4)
+
+    backward_step()
+    torch.cuda.synchronize()
+    fp.fp_check(path.ctx)
+    fp.fp_profile(path.ctx, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps_8 + 1)]
+    ev[0].record()
+    for i in range(args.steps_8):
+        backward_step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per_b = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps_8)])
+    g4_ms, g4_n = fp.fp_profile_read(path.ctx, 14)
+    fp.fp_profile(path.ctx, False)
+    fp.fp_check(path.ctx)
+    path.close()
+    fwd, bwd = float(np.median(per_f)), float(np.median(per_b))
+    log(f"bench: adjoint workload forward {fwd:.3f} ms, backward {bwd:.3f} ms, ratio {bwd / fwd:.2f}")
+    return {"workload": "adjoint: 2-atom diamond cell, 8x8x8 mesh, 62 cubic + "
+                        f"{int(cfg['ifc4']['n_terms'])} quartic terms, T = 300 K, host lists",
+            "forward_ms_median": fwd, "backward_ms_median": bwd, "bwd_fwd_ratio": bwd / fwd, "runs": len(per_b),
+            "adjoint4_kernel_ms": g4_ms / max(1, g4_n),
+            "step": "kappa_RTA with dkappa/dGamma + adjoint of the 3ph and 4ph rates (V recomputed)"}
+
+
+def leg_adaptive_8(torch, fp, args):
+    from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists
+    from paper_2510_00518_amd.synth import ADAPTIVE_FACTOR, SIGMA_FLOOR, adaptive_broadening, make_config
+    cfg = make_config("fcc8_4ph")
+    T = [float(x) for x in cfg["T"]]
+    b = adaptive_broadening(cfg)
+    t0 = time.perf_counter()
+    lists = host_lists(cfg, TYPES3 + TYPES4, sigma=SIGMA_FLOOR, broadening=b)
+    t_enum = time.perf_counter() - t0
+    path = RatePath(dict(cfg, sigma=SIGMA_FLOOR), device=0)
+    path.set_broadening(b)
+    path.set_lists(lists)
+    del lists
+    per, k_ms, _, kap = run_lists(torch, fp, path, T, args.steps_8, 1, 4)
+    out = {"value": path.n_proc4 / (np.median(per) * 1e-3), "unit": "processes/s",
+           "ms_per_step_median": float(np.median(per)), "processes_4ph": path.n_proc4, "kernel_ms": k_ms,
+           "ns_per_process_kernel": k_ms * 1e6 / path.n_proc4, "factor": ADAPTIVE_FACTOR,
+           "floor_rad_per_ps": SIGMA_FLOOR, "host_enumeration_s": round(t_enum, 2),
+           "kappa_finite": bool(np.all(np.isfinite(trace_kappa(kap))))}
+    path.close()
+    log(f"bench: 8^3 adaptive {np.median(per):.3f} ms/step, kernel {k_ms:.3f} ms")
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps-8", type=int, default=7, help="timed runs of each 8^3 leg (median reported)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-single", type=float, default=6.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counter scaling)")
-    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--only-headline", action="store_true", help="the 16^3 FP64 steps only (for profiling)")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--no-8", action="store_true", help="skip the 8^3 legs (lists, adjoint, adaptive)")
     ap.add_argument("--paper-scale-adaptive", action="store_true",
-                    help="also run the 16^3 cell with the adaptive width (about a minute)")
-    ap.add_argument("--paper-scale", action="store_true",
-                    help="also run the 16^3 two-atom cell through GPU-side enumeration (about a minute)")
-    ap.add_argument("--ppl", type=int, default=None)
-    ap.add_argument("--blocks-per-cu", type=int, default=None)
-    ap.add_argument("--variant", type=int, default=None, help="order-4 contraction form (library knob)")
+                    help="also run one pass of the 16^3 cell with the adaptive width")
+    ap.add_argument("--variant", type=int, default=None, help="order-4 contraction form of the list kernel")
+    ap.add_argument("--fused-form", type=int, default=None, help="FP64 form of the fused kernel (library knob)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the rate path is built and timed on a single MI355X; "
               "multi-GPU sharding is a design in DESIGN.md, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.only_headline:
+        args.no_mixed = args.no_8 = args.no_cpu_baseline = True
 
     import torch
 
     from paper_2510_00518_amd import fp
-    from paper_2510_00518_amd.driver import TYPES3, TYPES4, RatePath, host_lists
-    from paper_2510_00518_amd.synth import ADAPTIVE_FACTOR, SIGMA_FLOOR, adaptive_broadening, make_config
+    from paper_2510_00518_amd.synth import SIGMA_FLOOR, adaptive_broadening, make_config
 
     if not os.path.exists(fp.LIB_PATH):
         from __graft_entry__ import build
         build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    cfg = make_config("fcc8_4ph")
-    n4 = int(cfg["ifc4"]["n_terms"])
-    n_groups = partner_groups(cfg["ifc4"])
-    T = [float(x) for x in cfg["T"]]
-    log("bench: enumerating lists on the host")
-    t0 = time.perf_counter()
-    lists = host_lists(cfg, TYPES3 + TYPES4)
-    t_enum = time.perf_counter() - t0
-    n_tup, n_unit_tup = tuple_stats(lists, cfg["nb"])
-    path = RatePath(cfg, device=0)
-    if args.ppl:
-        fp.fp_set_knob(path.ctx, "ppl", args.ppl)
-    if args.blocks_per_cu:
-        fp.fp_set_knob(path.ctx, "blocks_per_cu", args.blocks_per_cu)
-    if args.variant is not None:
-        fp.fp_set_knob(path.ctx, "variant", args.variant)
-    variant = fp.fp_get_knob(path.ctx, "variant")
-    path.set_lists(lists)
-    n_proc4, n_proc3 = path.n_proc4, path.n_proc3
-    log(f"bench: {n_proc4} 4ph + {n_proc3} 3ph processes in {n_tup} (lambda, q', q'') tuples, "
-        f"enumeration {t_enum:.1f} s")
 
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -258,164 +440,117 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- FP64 forward
-    ms_step, kern_ms, gamma, kappa = run_forward(path, T, args.steps, args.warmup, 4, torch, fp)
-    log(f"bench: FP64 {args.steps} steps, {ms_step:.3f} ms/step, order-4 rate kernel {kern_ms:.3f} ms/launch")
-    g64 = gamma.cpu().numpy()
-    k64 = kappa.cpu().numpy()
-    finite = bool(np.all(np.isfinite(k64)))
-
-    # algorithmic work of the order-4 kernel, per formulation
-    f4 = (320 * n4 + 60) * n_proc4                  # per-process form: 320 n4 + 60 FLOP per process
-    f_build = 216 * n4 * n_tup                      # tuple form: phase-weighted constants, 216 n4 per tuple
-    f_contract = (312 * n_groups + 60) * n_proc4    # tuple form: 39 complex MACs per group, + weights
-    sec = kern_ms * 1e-3
-    if variant >= 4:
-        roof = {"bound": "mfma", "achieved": f_build / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "kernel": f"k_rates4b variant {variant} (tuple-batched, FP64 MFMA + FP64 VALU)",
-                "work": f"216*n4 FLOP per (lambda, q', q'') tuple on FP64 MFMA, n4 = {n4}, {n_tup} tuples",
-                "valu_achieved": f_contract / sec / 1e12}
-    else:
-        roof = {"bound": "alu", "achieved": f4 / sec / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "kernel": f"k_rates<4,...> variant {variant} (per-process, FP64 VALU)",
-                "work": f"320*n4 + 60 FLOP per process, n4 = {n4}"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel_ms"] = kern_ms
-    roof["per_process_form_equivalent_tflops"] = f4 / sec / 1e12
+    # ---- headline: the 16^3 cell, FP64, batched by q1
+    cfg = make_config("fcc16_34ph")
+    ctx = fp.fp_create(0)
+    if args.fused_form is not None:
+        fp.fp_set_knob(ctx, "fused_form", args.fused_form)
+    t0 = time.perf_counter()
+    W = Batched16(torch, fp, cfg, ctx)
+    log(f"bench: 16^3 set-up ({N_BATCH} q1 batches, 3ph host lists) {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    counts, g_ref, k_ref = W.reference_pass(fp.FP_FP64)
+    t_ref = time.perf_counter() - t0
+    n4_all, tup_all = int(counts[:, 0].sum()), int(counts[:, 1].sum())
+    n3_all = sum(B["n3"] for B in W.batches)
+    log(f"bench: reference pass {t_ref:.2f} s: {n4_all} 4ph processes in {tup_all} tuples, {n3_all} 3ph; "
+        f"kappa {k_ref}")
+    per, done, k4_ms, k3_ms = W.timed(args.steps, args.warmup, fp.FP_FP64, first=0)
+    proc = np.array([counts[b, 0] for b in done], np.float64)
+    tup = int(sum(counts[b, 1] for b in done))
+    n4_timed = int(proc.sum())
+    t_total = per.sum() * 1e-3
+    value = n4_timed / t_total
+    log(f"bench: FP64 {args.steps} steps, {per.mean():.1f} ms/step, {value:.3e} 4ph processes/s, "
+        f"fused kernel {k4_ms:.1f} ms total")
+    form = fp.fp_get_knob(ctx, "fused_form")
+    roof = roofline(fp, ctx, n4_timed, tup, k4_ms * 1e-3,
+                    f"k_fused4 form {form} (GPU enumeration + tuple-batched FP64: matrix-core build, VALU "
+                    "contraction)", folded=form == 2)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("variant") == variant:
-            traffic = tr.get("hbm_bytes_per_launch")
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            # measured bytes per process, scaled to this run's launches
+            traffic = tr["hbm_bytes_per_process"] * n4_timed / max(1, len(done))
     roof["traffic"] = traffic
-
-    # ---- mixed-precision forward (order 4 on bf16-split MFMA + FP32 contraction)
-    mixed = None
-    if not args.no_mixed:
-        path.precision = fp.FP_MIXED
-        ms_m, kern_m, gam_m, kap_m = run_forward(path, T, args.steps, 1, 24, torch, fp)
-        path.precision = fp.FP_FP64
-        gm = gam_m.cpu().numpy()
-        km = kap_m.cpu().numpy()
-        big = np.abs(g64) > 1e-6 * np.abs(g64).max()
-        rel = np.abs(gm[big] - g64[big]) / np.abs(g64[big])
-        kr = (km[:, 0] + km[:, 4] + km[:, 8]) / 3
-        k0 = (k64[:, 0] + k64[:, 4] + k64[:, 8]) / 3
-        sec_m = kern_m * 1e-3
-        mixed = {
-            "value": n_proc4 / (ms_m * 1e-3), "unit": "processes/s", "ms_per_step": ms_m,
-            "speedup_vs_fp64": ms_step / ms_m,
-            "kappa_rel_err": float(np.max(np.abs(kr - k0) / np.abs(k0))),
-            "gamma_rel_err_max": float(rel.max()), "gamma_rel_err_median": float(np.median(rel)),
-            "error_reference": "the FP64 GPU path of this run (held to the oracle at 1e-10 per mode by the tests)",
-            "roofline": {"bound": "mfma", "achieved": 6 * f_build / sec_m / 1e12, "peak": PEAK_BF16_TFLOPS,
-                         "unit": "TFLOP/s", "frac": 6 * f_build / sec_m / 1e12 / PEAK_BF16_TFLOPS,
-                         "kernel": "k_rates4m (bf16 split MFMA + FP32 VALU)", "kernel_ms": kern_m,
-                         "work": "6 bf16 products per FP32-accurate product, 216*n4 FLOP per tuple",
-                         "fp32_equivalent_tflops": f_build / sec_m / 1e12,
-                         "valu_achieved": f_contract / sec_m / 1e12,
-                         "per_process_form_equivalent_tflops": f4 / sec_m / 1e12},
-        }
-        log(f"bench: mixed {ms_m:.3f} ms/step (kernel {kern_m:.3f} ms), kappa rel err {mixed['kappa_rel_err']:.2e}, "
-            f"Gamma rel err max {mixed['gamma_rel_err_max']:.2e}")
-
-    # ---- backward: dkappa/dGamma, then the adjoint of both rate orders
-    bwd = None
-    if not args.no_backward:
-        dk = torch.zeros_like(gamma)
-        d3 = torch.zeros_like(path.phi3)
-        d4 = torch.zeros_like(path.phi4)
-
-        def backward_step():
-            path.kappa(T, gamma, kappa, dk)
-            fp.fp_rates_backward(path.ctx, path.lists3 + path.lists4, T, cfg["sigma"], dk, d3, d4)
-
-        backward_step()
-        torch.cuda.synchronize()
-        fp.fp_check(path.ctx)
-        fp.fp_profile(path.ctx, True)
-        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        b0.record()
-        for _ in range(args.steps):
-            backward_step()
-        b1.record()
-        torch.cuda.synchronize()
-        g4_ms, g4_n = fp.fp_profile_read(path.ctx, 14)
-        fp.fp_profile(path.ctx, False)
-        fp.fp_check(path.ctx)
-        ms_bwd = b0.elapsed_time(b1) / args.steps
-        bwd = {"ms_per_step": ms_bwd, "bwd_fwd_ratio": ms_bwd / ms_step,
-               "adjoint4_kernel_ms": g4_ms / max(1, g4_n),
-               "step": "kappa_RTA with dkappa/dGamma + adjoint of the 3ph and 4ph rates (V recomputed)"}
-        log(f"bench: backward {ms_bwd:.3f} ms/step, ratio {ms_bwd / ms_step:.2f}")
-
-    # ---- adaptive broadening: per-process width, lists enumerated with it
-    adaptive = None
-    if not args.no_adaptive:
-        b = adaptive_broadening(cfg)
-        log("bench: enumerating adaptive-width lists on the host")
-        t0 = time.perf_counter()
-        lists_a = host_lists(cfg, TYPES3 + TYPES4, sigma=SIGMA_FLOOR, broadening=b)
-        t_enum_a = time.perf_counter() - t0
-        path_a = RatePath(dict(cfg, sigma=SIGMA_FLOOR), device=0)
-        if args.variant is not None:
-            fp.fp_set_knob(path_a.ctx, "variant", args.variant)
-        path_a.set_broadening(b)
-        path_a.set_lists(lists_a)
-        del lists_a
-        ms_a, kern_a, gam_a, kap_a = run_forward(path_a, T, args.steps, 1, 4, torch, fp)
-        adaptive = {
-            "value": path_a.n_proc4 / (ms_a * 1e-3), "unit": "processes/s", "ms_per_step": ms_a,
-            "processes_4ph": path_a.n_proc4, "processes_3ph": path_a.n_proc3, "kernel_ms": kern_a,
-            "ns_per_process_kernel": kern_a * 1e6 / path_a.n_proc4,
-            "ns_per_process_kernel_fixed_width": kern_ms * 1e6 / n_proc4,
-            "factor": ADAPTIVE_FACTOR, "floor_rad_per_ps": SIGMA_FLOOR, "host_enumeration_s": round(t_enum_a, 2),
-            "kappa_finite": bool(np.all(np.isfinite(kap_a.cpu().numpy()))),
-        }
-        path_a.close()
-        log(f"bench: adaptive {ms_a:.3f} ms/step, {path_a.n_proc4} 4ph processes, kernel {kern_a:.3f} ms")
-
     out = {
         "metric": "4ph processes/sec at 1 GPU, FP64 vs mixed (rel err vs oracle); bwd/fwd time ratio",
-        "value": n_proc4 / (ms_step * 1e-3),
+        "value": value,
         "unit": "processes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": float(per.mean()),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "4ph FP64, 2-atom diamond cell, 8x8x8 mesh, Oh-irreducible q1 (29), "
-                        f"32 cubic + {n4} quartic terms, sigma 0.1 THz, |Delta| <= 3 sigma, T = 300 K",
-            "processes_4ph": n_proc4,
-            "processes_3ph": n_proc3,
-            "tuples_4ph": n_tup,
-            "tuples_4ph_per_unit": n_unit_tup,
-            "partner_groups_4ph": n_groups,
-            "variant": variant,
-            "step": "load_ifc(3,4) + rates3 + rates4 (Gamma3+Gamma4) + kappa_RTA",
-            "host_enumeration_s": round(t_enum, 2),
+            "workload": "3ph+4ph FP64, 2-atom diamond cell, 16x16x16 mesh, Oh-irreducible q1 (145), "
+                        f"{int(cfg['ifc3']['n_terms'])} cubic + {int(cfg['ifc4']['n_terms'])} quartic terms, "
+                        "sigma 0.1 THz, |Delta| <= 3 sigma, T = 300/600/900 K; 4ph lists generated on the GPU, "
+                        "3ph host lists",
+            "step": f"one of {N_BATCH} q1 batches: load_ifc(3,4) + rates3 + fused rates4 (Gamma3+Gamma4) + "
+                    "kappa_RTA share",
+            "batches": N_BATCH,
+            "processes_4ph_cell": n4_all, "tuples_4ph_cell": tup_all, "processes_3ph_cell": n3_all,
+            "processes_4ph_timed": n4_timed,
+            "full_cell_pass_s": t_ref,
         },
+        "per_step_processes_per_s_median": float(np.median(proc / (per * 1e-3))),
+        "kernel_only_processes_per_s": n4_timed / (k4_ms * 1e-3),
+        "call_level_ms_per_step": float(per.mean()),
+        "kernel_only_ms_per_step": (k4_ms + k3_ms) / len(done),
+        "kappa_rta_W_per_mK": [float(x) for x in k_ref],
         "roofline": roof,
-        "kappa_finite": finite,
-        "mixed": mixed,
-        "bwd_fwd_ratio": None if bwd is None else bwd["bwd_fwd_ratio"],
-        "backward": bwd,
-        "adaptive": adaptive,
     }
-    if args.paper_scale:
-        out["paper_scale"] = paper_scale(torch, fp, RatePath)
-        out["paper_scale_mixed"] = paper_scale(torch, fp, RatePath, precision=fp.FP_MIXED)
+    if not args.no_mixed:
+        per_m, done_m, km_ms, _ = W.timed(N_BATCH, 1, fp.FP_MIXED, first=0)
+        g_m, k_m = W.gamma(), W.kappa()
+        big = np.abs(g_ref) > 1e-6 * np.abs(g_ref).max()
+        rel = np.abs(g_m[big] - g_ref[big]) / np.abs(g_ref[big])
+        n4m = int(sum(counts[b, 0] for b in done_m))
+        tupm = int(sum(counts[b, 1] for b in done_m))
+        out["mixed"] = {
+            "value": n4m / (per_m.sum() * 1e-3), "unit": "processes/s", "ms_per_step": float(per_m.mean()),
+            "steps": len(done_m), "speedup_vs_fp64": float(per.mean() / per_m.mean()),
+            "kappa_rel_err": float(np.max(np.abs(k_m - k_ref) / np.abs(k_ref))),
+            "gamma_rel_err_max": float(rel.max()), "gamma_rel_err_median": float(np.median(rel)),
+            "error_reference": "the FP64 pass of this run (held to the oracle at 1e-10 per mode by the tests)",
+            "roofline": roofline(fp, ctx, n4m, tupm, km_ms * 1e-3, "k_fused4 mixed (bf16 split MFMA + FP32 VALU)",
+                                 mixed=True)}
+        log(f"bench: mixed {per_m.mean():.1f} ms/step, kappa rel err {out['mixed']['kappa_rel_err']:.2e}")
     if args.paper_scale_adaptive:
-        out["paper_scale_adaptive"] = paper_scale(torch, fp, RatePath, adaptive=True)
+        b = adaptive_broadening(cfg)
+        ctx_a = fp.fp_create(0)
+        Wa = Batched16(torch, fp, dict(cfg, sigma=SIGMA_FLOOR), ctx_a, broadening=b)
+        per_a, done_a, ka_ms, _ = Wa.timed(N_BATCH, 1, fp.FP_FP64, first=0)
+        ca, _, _ = Wa.reference_pass(fp.FP_FP64)
+        n4a = int(ca[:, 0].sum())
+        out["paper_scale_adaptive"] = {"value": n4a / (per_a.sum() * 1e-3), "unit": "processes/s",
+                                       "processes_4ph": n4a, "seconds": float(per_a.sum() * 1e-3),
+                                       "kernel_ms": ka_ms}
+        fp.fp_destroy(ctx_a)
+    fp.fp_destroy(ctx)
+    del W
+
+    if not args.no_8:
+        from paper_2510_00518_amd.driver import TYPES3, TYPES4, host_lists
+        cfg8 = make_config("fcc8_4ph")
+        t0 = time.perf_counter()
+        lists = host_lists(cfg8, TYPES3 + TYPES4)
+        log(f"bench: 8^3 host lists {time.perf_counter() - t0:.1f} s")
+        n_tup8 = tuple_stats(lists, cfg8["nb"])
+        out["lists_8"] = leg_lists_8(torch, fp, args, lists, n_tup8)
+        out["backward"] = leg_backward(torch, fp, args, lists)
+        out["bwd_fwd_ratio"] = out["backward"]["bwd_fwd_ratio"]
+        del lists
+        out["adaptive_8"] = leg_adaptive_8(torch, fp, args)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(cfg, lists, args.cpu_seconds)
-    path.close()
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, args.cpu_seconds_single)
     print(json.dumps(out), flush=True)
 
 

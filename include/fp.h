@@ -173,6 +173,21 @@ fp_status fp_load_modes(fp_ctx* ctx, const int32_t mesh[3], int32_t n_atoms, con
 fp_status fp_load_ifc(fp_ctx* ctx, int32_t order, int64_t n_terms, const int32_t* atoms, const int32_t* cells,
                       const double* phi, int32_t phi_on_device, void* hip_stream);
 
+/* Structure of the loaded force constants of one order, for work accounting.
+ * The phase of a term in any process depends only on its partner atoms and on
+ * its phase vectors A = R1 - R_last (and B = R2 - R_last for order 4) modulo
+ * the mesh (Methodology, the matrix element inlined in Algorithm 4); terms that
+ * agree in these form one phase key, whose per-row table is the sum of theirs,
+ * and the rate kernels run over keys.  out (HOST int64 [5]) receives
+ *   out[0] terms, out[1] phase keys, out[2] partner groups (the keys of one
+ *   partner-atom tuple, at most 16 per group), and for order 4 the tables of
+ *   the default FP64 form of fp_rates4_fused: out[3] pkeys (distinct B among
+ *   the keys of one pair of slot-2 and slot-3 atoms), out[4] pair groups (at
+ *   most 16 pkeys per group); 0 for order 3.
+ * FP_ERR_ARG for a NULL context or out or an order other than 3 or 4,
+ * FP_ERR_STATE if that order is not loaded. */
+fp_status fp_ifc_info(fp_ctx* ctx, int32_t order, int64_t out[5]);
+
 /* Broadening of the rate, adjoint and autotune calls that follow (see
  * fp_broadening); NULL or adaptive = 0 selects the fixed width of each call.
  * The context keeps the per-mode projections v . b_d / N_d on the device
@@ -331,6 +346,10 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *                    blocks per CU (6, the default), or three records per
  *                    lane (7)
  *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
+ *   "fused_form"     FP64 form of fp_rates4_fused: 0 = phase keys folded over
+ *                    A per (lambda, q') unit, 2 (the default) = keys and the
+ *                    first partner's eigenvector folded per unit, pair groups
+ *                    over the atoms of slots 2 and 3
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
 

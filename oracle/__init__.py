@@ -46,6 +46,8 @@ def lib():
         L.orc_constants.argtypes = [vp]
         L.orc_threads.argtypes = []
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_bose.argtypes = [dbl, dbl]
         L.orc_bose.restype = dbl
         L.orc_gauss.argtypes = [dbl, dbl]
@@ -75,6 +77,11 @@ def constants():
 
 def threads():
     return int(lib().orc_threads())
+
+
+def set_threads(n):
+    """Threads of the rate sums that follow."""
+    lib().orc_set_threads(int(n))
 
 
 def bose(omega, T):

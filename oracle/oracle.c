@@ -135,6 +135,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* thread count of the rate sums that follow (n > 0) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void orc_constants(double out[4]) {
     out[0] = c_hbar();
     out[1] = c_kb();

@@ -2,13 +2,14 @@
 // Included once, by fp_lib.hip, after fp_kernels.h.
 //
 // All listed processes of one (lambda, q', q'') tuple share the phases
-// ph_t = exp(2 pi i (Q1.A_t + Q2.B_t)/L), so the phase-weighted force constants
-//   A_g[c](tuple) = sum_{t in group g} ph_t(tuple) phit_t[c]     (c = beta gamma delta)
+// ph_k = exp(2 pi i (Q1.A_k + Q2.B_k)/L) of every phase key k, so the
+// phase-weighted force constants
+//   A_g[c](tuple) = sum_{k in group g} ph_k(tuple) phit_k[c]     (c = beta gamma delta)
 // are formed once per tuple and partner-atom group g, and each process only
 // contracts them with its partner eigenvectors:
 //   V = sum_g sum_{beta gamma delta} A_g[beta gamma delta] eps1(b_g)_beta eps2(c_g)_gamma eps3(d_g)_delta.
 // Over a block of tuples, A_g is a complex matrix product (27 components x
-// tuples, K = the group's terms) and runs on FP64 MFMA
+// tuples, K = the group's phase keys) and runs on FP64 MFMA
 // (v_mfma_f64_16x16x4f64); the per-process contraction (39 complex MACs per
 // group) runs on the VALU.  The two pipes overlap across the waves of a SIMD.
 //
@@ -24,28 +25,28 @@ namespace fpk {
 constexpr int kBU = 128;            // records per unit
 constexpr int kBR = kBU / kWave;    // records per lane
 constexpr int kTB = 32;             // tuples staged per batch
-constexpr int kMaxKs = 4;           // K-steps of four terms per partner group (groups hold <= 16 terms)
-constexpr int kStageTerms = 512;    // term tables up to this size are staged in LDS
+constexpr int kMaxKs = 4;           // K-steps of four keys per partner group (groups hold <= 16 keys)
+constexpr int kStageTerms = 512;    // key tables up to this size are staged in LDS
 
 // Dynamic LDS of the tuple-batched kernels: the root table (L entries), then the
-// term table (8 int32 per term) when it has at most kStageTerms terms.
-inline size_t tb_dyn_lds(int32_t L, int64_t n_terms) {
-    return (size_t)L * sizeof(double2) + (n_terms <= kStageTerms ? (size_t)n_terms * 8 * sizeof(int32_t) : 0);
+// key table (8 int32 per phase key) when it has at most kStageTerms keys.
+inline size_t tb_dyn_lds(int32_t L, int64_t n_keys) {
+    return (size_t)L * sizeof(double2) + (n_keys <= kStageTerms ? (size_t)n_keys * 8 * sizeof(int32_t) : 0);
 }
 
-// Copy the root table (and the term table when it fits) into the block's
-// dynamic LDS; returns the term table to read, staged or global.
-__device__ inline const int32_t* tb_stage_terms(void* at, const int32_t* __restrict__ tmeta, int32_t n_terms) {
-    if (n_terms > kStageTerms) return tmeta;
+// Copy the root table (and the key table when it fits) into the block's
+// dynamic LDS; returns the key table to read, staged or global.
+__device__ inline const int32_t* tb_stage_terms(void* at, const int32_t* __restrict__ tmeta, int32_t n_keys) {
+    if (n_keys > kStageTerms) return tmeta;
     int32_t* stm = reinterpret_cast<int32_t*>(at);
-    for (int i = threadIdx.x; i < n_terms * 8; i += kBlock) stm[i] = tmeta[i];
+    for (int i = threadIdx.x; i < n_keys * 8; i += kBlock) stm[i] = tmeta[i];
     return stm;
 }
 
 __device__ inline const int32_t* tb_stage(double2* sroots, const double2* __restrict__ roots, int32_t L,
-                                          const int32_t* __restrict__ tmeta, int32_t n_terms) {
+                                          const int32_t* __restrict__ tmeta, int32_t n_keys) {
     for (int i = threadIdx.x; i < L; i += kBlock) sroots[i] = roots[i];
-    return tb_stage_terms(sroots + L, tmeta, n_terms);
+    return tb_stage_terms(sroots + L, tmeta, n_keys);
 }
 
 
@@ -56,7 +57,12 @@ __device__ inline const int32_t* tb_stage(double2* sroots, const double2* __rest
 // accg/accw; with GRAD it also writes h_p = c_p conj(V_p) to hout[k * 64 + lane]
 // for the valid records, c_p = 2 pref w G / prod(omega) sum_T dl[T] occ_T.
 // g0, type and count are wave-uniform; A and Qs are this wave's LDS staging.
-template <int MAXT, bool GRAD, int BR = kBR, int TB = kTB>
+// FOLD (the fused path, where every record of the batch shares q'): `groups`
+// are the fused groups over B-keys, `tmeta` the B-key table (B at [4..6]), and
+// `phit_row` this wave's folded table of the unit, already in the MFMA
+// A-operand layout (K-step, component tile, lane), so the per-tuple phase is
+// exp(2 pi i Q2.B / L) alone.
+template <int MAXT, bool GRAD, int BR = kBR, int TB = kTB, bool FOLD = false>
 __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0, int type,
                                 const double2* __restrict__ phit_row, const double* __restrict__ omega,
                                 const double2* __restrict__ evec, const double* __restrict__ occ,
@@ -108,7 +114,7 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
     for (int gi = 0; gi < a.n_groups; ++gi) {
         const int32_t* G = groups + gi * 8;
         const int32_t ab = G[0], ac = G[1], ad = G[2], t0 = G[3], t1 = G[4];
-        const int n_ks = (t1 - t0 + 3) >> 2;  // <= kMaxKs: groups hold at most 16 terms
+        const int n_ks = (t1 - t0 + 3) >> 2;  // <= kMaxKs: groups hold at most 16 keys
         // this group's force constants and phase vectors for every K-step, one load
         double2 Fk[kMaxKs][2];
         bool kv[kMaxKs];
@@ -119,7 +125,11 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
                 const int comp = mt * 16 + li;
-                Fk[ks][mt] = (kv[ks] && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
+                if (FOLD)  // zero where the key or the component does not exist
+                    Fk[ks][mt] = ks < n_ks ? phit_row[((int64_t)(G[5] + ks) * 2 + mt) * kWave + lane]
+                                           : make_double2(0.0, 0.0);
+                else
+                    Fk[ks][mt] = (kv[ks] && comp < 27) ? phit_row[(int64_t)term * 27 + comp] : make_double2(0.0, 0.0);
             }
         }
         // with one record per lane, this group's partner eigenvector components are
@@ -188,7 +198,7 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
                         uint32_t kk = 0;
                         const int32_t* tmp = tmeta + (t0 + 4 * ks + lk) * 8;
 #pragma unroll
-                        for (int d = 0; d < 6; ++d) kk += (uint32_t)(qv[d] * tmp[1 + d]);
+                        for (int d = FOLD ? 3 : 0; d < 6; ++d) kk += (uint32_t)(qv[d] * tmp[1 + d]);
                         ph = sroots[mod_l(kk, geo.L, geo.magic)];
                     }
                     const double pd = ph.y - ph.x, ps = ph.x + ph.y;
@@ -303,7 +313,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_rates4b(FP_RATES_PARAMS, const 
     extern __shared__ double2 sroots[];
     __shared__ double2 sA[kWavesPerBlock][TB][27];
     __shared__ int32_t sQ[kWavesPerBlock][TB][2];
-    const int32_t* tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_terms);
+    const int32_t* tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_keys);
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -334,7 +344,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_rates4b(FP_RATES_PARAMS, const 
             double dl[MAXT];
 #pragma unroll
             for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
-            tb_batch<MAXT, GRAD, BR, TB>(rec, count, g0, type, phit + (int64_t)row * a.n_terms * 27, omega, evec, occ, tm,
+            tb_batch<MAXT, GRAD, BR, TB>(rec, count, g0, type, phit + (int64_t)row * a.n_keys * 27, omega, evec, occ, tm,
                                  groups, flag, a, sroots, sA[wave], sQ[wave], accg, accw, dl, pref,
                                  GRAD ? hbuf + ri.hbase + ud.start : nullptr);
         }

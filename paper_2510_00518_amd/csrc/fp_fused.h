@@ -112,6 +112,230 @@ __device__ __noinline__ bool fused_adaptive_pass(double ad, int32_t g1, int32_t 
     return ad <= f.nsigma * (sp > f.sigma ? sp : f.sigma);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 form with the first partner folded per unit.  Within a unit (lambda, q')
+// the partner lambda' = (q', j') ranges over the branches of q' only, so its
+// eigenvector and the phase exp(2 pi i Q1.A_k / L) of every phase key k are
+// fixed.  Folding both into the force constants once per unit gives, per pair
+// group p (the atoms c, d of slots 2 and 3) and pkey (a distinct B in p),
+//   H_p[pk][j' gamma delta] = sum_{k in pk} exp(2 pi i Q1.A_k/L)
+//                             sum_beta phit_k[beta gamma delta] eps1(j', b_k)_beta,
+// so the keys of the two slot-1 atoms share one table.  Per tuple tau (q'', and
+// with it the last partner's q, fixed) the build on FP64 MFMA is
+//   A_p[j' gamma delta](tau) = sum_{pk in p} exp(2 pi i Q2(tau).B_pk / L) H_p[pk][j' gamma delta]
+// (M = 54 components in four tiles, N = 16 tuples, K = the pkeys, four at a
+// time), and each process contracts
+//   V = sum_p sum_{gamma delta} A_p[j' gamma delta](tau) eps2(c_p)_gamma eps3(d_p)_delta,
+// 12 complex MACs per pair group against 39 per partner-atom group without the fold.
+constexpr int kXM = 54;   // components j' gamma delta of one pair group
+constexpr int kXMT = 4;   // M-tiles of 16
+constexpr int kXTB = 16;  // tuples per batch tile (the MFMA N)
+
+// H of this unit for every pair group, written to fw in the MFMA A-operand
+// layout ((K-step, M-tile), lane), zero where the pkey or component does not
+// exist.  c1 = +1 or -1 conjugates the eigenvectors of an emitted lambda'.
+__device__ inline void tbx_fold(double2* __restrict__ fw, const double2* __restrict__ phit_row,
+                                const double2* __restrict__ evec, int32_t iq1, double c1, int32_t Q10, int32_t Q11,
+                                int32_t Q12, const int32_t* __restrict__ tm, const int32_t* __restrict__ ptab,
+                                const int32_t* __restrict__ plist, const int32_t* __restrict__ pgroups, int n_pgroups,
+                                const double2* sroots, const ModeGeom& geo) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int li = lane & 15, lk = lane >> 4;
+    const int nb = geo.nb;
+    for (int gi = 0; gi < n_pgroups; ++gi) {
+        const int32_t* G = pgroups + gi * 8;
+        const int32_t p0 = G[2], p1 = G[3], kb = G[4];
+        const int n_ks = (p1 - p0 + 3) >> 2;
+        for (int ks = 0; ks < n_ks; ++ks) {
+            const int32_t pk = p0 + 4 * ks + lk;
+            for (int mt = 0; mt < kXMT; ++mt) {
+                const int mc = mt * 16 + li;
+                double2 F = make_double2(0.0, 0.0);
+                if (pk < p1 && mc < kXM) {
+                    const int jp = mc / 9, gd = mc % 9;
+                    const int32_t e0 = ptab[pk * 8], e1 = e0 + ptab[pk * 8 + 1];
+                    for (int32_t e = e0; e < e1; ++e) {
+                        const int32_t k = plist[2 * e], ab = plist[2 * e + 1];
+                        const int32_t* t = tm + k * 8;
+                        const uint32_t kq = (uint32_t)(Q10 * t[1] + Q11 * t[2] + Q12 * t[3]);
+                        const double2* x = evec + ((int64_t)iq1 * nb + jp) * nb + 3 * ab;
+                        const double2* h = phit_row + (int64_t)k * 27 + gd;
+                        double2 hx = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) hx = cfma(hx, h[b * 9], ld_eps(x + b, c1));
+                        F = cfma(F, sroots[mod_l(kq, geo.L, geo.magic)], hx);
+                    }
+                }
+                fw[((int64_t)(kb + ks) * kXMT + mt) * kWave + lane] = F;
+            }
+        }
+    }
+}
+
+// One batch of up to 128 records of one unit (record k * 64 + lane in rec[k];
+// `count` valid), all with the unit's q': decode, find the tuples (a change of
+// q'' between consecutive records), build A_p per pair group and 16-tuple tile
+// on FP64 MFMA from the folded table fw, contract per process on the VALU,
+// weight in FP64.  ptab is the pkey table (B at [4..6]); A and Qs are this
+// wave's LDS staging.
+template <int MAXT>
+__device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t g0, int type,
+                                 const double2* __restrict__ fw, const double* __restrict__ omega,
+                                 const double2* __restrict__ evec, const double* __restrict__ occ,
+                                 const int32_t* __restrict__ ptab, const int32_t* __restrict__ pgroups,
+                                 int n_pgroups, int* __restrict__ flag, const RatesArgs& a, const double2* sroots,
+                                 double2 (*A)[kXM], int32_t* Qs, double (&accg)[MAXT], double (&accw)[MAXT]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int li = lane & 15, lk = lane >> 4;
+    const ModeGeom& geo = a.geo;
+    const int nb = geo.nb;
+    int s1, s2, s3;
+    type_signs(type, s1, s2, s3);
+    const double c2 = s2 > 0 ? 1.0 : -1.0;
+    const double c3 = s3 > 0 ? 1.0 : -1.0;
+    const int32_t iq0 = g0 / nb;
+    const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
+    const double w0 = omega[g0];
+
+    // ---- records, tuple boundaries (q'' changes) and slots
+    Proc pr[kBR];
+    bool have[kBR], first[kBR];
+    int slot[kBR], jp[kBR];
+    int32_t prev_last = -1;
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < kBR; ++k) {
+        const int idx = k * kWave + lane;
+        have[k] = idx < count;
+        pr[k] = setup_proc<4>(have[k], rec[k], type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
+                              flag, a.br);
+        jp[k] = pr[k].g1 % nb;
+        const int32_t key = have[k] ? pr[k].g2 / nb : -2;
+        int32_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
+        if (lane == 0) up = prev_last;
+        first[k] = have[k] && key != up;
+        const uint64_t mask = __ballot(first[k]);
+        const uint64_t le = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+        slot[k] = base + __popcll(mask & le) - 1;
+        base += __popcll(mask);
+        prev_last = __shfl(key, kWave - 1, kWave);
+    }
+    const int n_tup = __builtin_amdgcn_readfirstlane(base);
+
+    double2 V[kBR];
+#pragma unroll
+    for (int k = 0; k < kBR; ++k) V[k] = make_double2(0.0, 0.0);
+    for (int gi = 0; gi < n_pgroups; ++gi) {
+        const int32_t* G = pgroups + gi * 8;
+        const int32_t ac = G[0], ad = G[1], p0 = G[2], p1 = G[3], kb = G[4];
+        const int n_ks = (p1 - p0 + 3) >> 2;  // <= kMaxKs: groups hold at most 16 pkeys
+        for (int tb = 0; tb < n_tup; tb += kXTB) {
+            const int nbt = n_tup - tb < kXTB ? n_tup - tb : kXTB;
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) {
+                const int s = slot[k] - tb;
+                if (first[k] && s >= 0 && s < kXTB) Qs[s] = pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20);
+            }
+            lds_fence();
+            // A_p for this tile: two passes of two M-tiles (Karatsuba, three real
+            // MFMAs per complex product: k1 = (Fr + Fi) pr, k2 = Fr (pi - pr),
+            // k3 = Fi (pr + pi); Re = k1 - k3, Im = k1 + k2)
+            __builtin_amdgcn_s_setprio(0);
+            const bool tval = li < nbt;
+            const int32_t qa = Qs[tval ? li : 0];
+            const int32_t qb0 = qa & 1023, qb1 = (qa >> 10) & 1023, qb2 = (qa >> 20) & 1023;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                d4 k1[2], k2[2], k3[2];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) k1[mt] = k2[mt] = k3[mt] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < kMaxKs; ++ks) {
+                    if (ks >= n_ks) break;
+                    const int32_t pk = p0 + 4 * ks + lk;
+                    double2 ph = make_double2(0.0, 0.0);
+                    if (pk < p1 && tval) {
+                        const int32_t* b = ptab + pk * 8;
+                        const uint32_t kq = (uint32_t)(qb0 * b[4] + qb1 * b[5] + qb2 * b[6]);
+                        ph = sroots[mod_l(kq, geo.L, geo.magic)];
+                    }
+                    const double pd = ph.y - ph.x, ps = ph.x + ph.y;
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        const double2 F = fw[((int64_t)(kb + ks) * kXMT + 2 * half + mt) * kWave + lane];
+                        k1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.x + F.y, ph.x, k1[mt], 0, 0, 0);
+                        k2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.x, pd, k2[mt], 0, 0, 0);
+                        k3[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.y, ps, k3[mt], 0, 0, 0);
+                    }
+                }
+                // D[i = 4r + lk][j = li]: component (2 half + mt) 16 + 4r + lk of tuple li
+                if (tval) {
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int mc = (2 * half + mt) * 16 + 4 * r + lk;
+                            if (mc < kXM) A[li][mc] = make_double2(k1[mt][r] - k3[mt][r], k1[mt][r] + k2[mt][r]);
+                        }
+                }
+            }
+            lds_fence();
+            __builtin_amdgcn_s_setprio(3);
+            // per process: 9 + 3 complex MACs with the partners of slots 2 and 3
+#pragma unroll
+            for (int k = 0; k < kBR; ++k) {
+                const int s = slot[k] - tb;
+                if (have[k] && s >= 0 && s < nbt) {
+                    const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
+                    const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
+                    double2 y[3], z[3];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        y[q] = ld_eps(e2 + q, c2);
+                        z[q] = ld_eps(e3 + q, c3);
+                    }
+                    const double2* Ar = A[s] + jp[k] * 9;
+                    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double2 vc = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) vc = cfma(vc, Ar[c * 3 + d], z[d]);
+                        acc = cfma(acc, vc, y[c]);
+                    }
+                    V[k].x += acc.x;
+                    V[k].y += acc.y;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            lds_fence();
+        }
+    }
+
+    // ---- weights and occupations (FP64)
+#pragma unroll
+    for (int k = 0; k < kBR; ++k) {
+        const double V2 = V[k].x * V[k].x + V[k].y * V[k].y;
+#pragma unroll
+        for (int it = 0; it < MAXT; ++it) {
+            if (it < a.n_T) {
+                const double* n = occ + (int64_t)it * a.n_modes;
+                const double n1 = n[pr[k].g1], n2 = n[pr[k].g2], nl = n[pr[k].gl];
+                double oc;
+                if (type == 2)
+                    oc = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
+                else if (type == 3)
+                    oc = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
+                else
+                    oc = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
+                const double xw = pr[k].base * oc;
+                accw[it] += xw;
+                accg[it] += xw * V2;
+            }
+        }
+    }
+}
+
 // Row and unit tables of a fused call: fused row fr = ti * n_rows + r.
 __global__ void k_fused_rows(const int32_t* __restrict__ row_mode, FusedArgs f, int64_t nq, int64_t n_modes,
                              RowInfo* __restrict__ rows, int64_t* __restrict__ unit_off, int* flag) {
@@ -151,10 +375,26 @@ __device__ inline int select_bit(uint64_t w, int n) {
     return pos;
 }
 
-// MIXED: the kept records are evaluated by the mixed-precision batch (split
-// bf16 MFMA build, FP32 contraction, FP64 weights) instead of the FP64 one.
-template <int MAXT, bool ADAPT, bool MIXED>
-__global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
+// Tables of the FP64 forms of the fused kernel (built by fp_load_ifc): the
+// B-key form (FORM 0: keys folded over A per unit, tb_batch) and the x-folded
+// form (FORM 2: keys and the first partner folded per unit, tbx_batch); fold
+// is one table per wave, rewritten per unit, of n_fold_ks K-steps.
+struct FusedTabs {
+    const int32_t* btab;
+    const int32_t* fgroups;
+    const int32_t* ptab;
+    const int32_t* plist;
+    const int32_t* pgroups;
+    double2* fold;
+    int32_t n_bkeys, n_pkeys, n_pgroups, n_fold_ks;
+};
+
+// FORM 0: FP64, B-keys (tb_batch, 24-tuple batches, three blocks per CU);
+// FORM 1: mixed precision (tbm_batch: split bf16 MFMA build, FP32 contraction,
+// FP64 weights); FORM 2: FP64 with the first partner folded (tbx_batch,
+// batches of at most 16 tuples, two blocks per CU).
+template <int MAXT, bool ADAPT, int FORM>
+__global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
                                                      const double* __restrict__ occ, const double2* __restrict__ roots,
                                                      const double2* __restrict__ phit,
                                                      const int32_t* __restrict__ tmeta,
@@ -162,19 +402,26 @@ __global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* 
                                                      const RowInfo* __restrict__ rows, double* __restrict__ partial,
                                                      int64_t* __restrict__ unit_kept, int64_t* __restrict__ unit_tup,
                                                      int* __restrict__ flag, RatesArgs a, FusedArgs f, const float2* __restrict__ evec32,
-                                                     const uint4* __restrict__ fsp, int32_t n_kblk) {
+                                                     const uint4* __restrict__ fsp, int32_t n_kblk, FusedTabs ft) {
     constexpr int NB = kFusedNb;
+    constexpr bool MIXED = FORM == 1;
+    constexpr int STB = FORM == 1 ? kTB : (FORM == 0 ? kFusedTB : kXTB);  // tuples staged per wave
+    constexpr int SNC = FORM == 2 ? kXM : 27;                             // components staged per tuple
     // dynamic LDS: the root table (FP64, or its bf16 splits: 16 bytes an entry
-    // either way), then the term table
+    // either way), then the key table, then (FP64) the B-key or pkey table
     extern __shared__ double2 sroots[];
-    __shared__ std::conditional_t<MIXED, float2, double2> sA[kWavesPerBlock][MIXED ? kTB : kFusedTB][27];
-    __shared__ int32_t sQ[kWavesPerBlock][MIXED ? kTB : kFusedTB][2];
+    __shared__ std::conditional_t<MIXED, float2, double2> sA[kWavesPerBlock][STB][SNC];
+    __shared__ int32_t sQ[kWavesPerBlock][STB][2];
     const int32_t* tm;
+    const int32_t* bt = FORM == 2 ? ft.ptab : ft.btab;
     if constexpr (MIXED) {
         tbm_roots(reinterpret_cast<uint4*>(sroots), roots, a.geo.L);
-        tm = tb_stage_terms(sroots + a.geo.L, tmeta, a.n_terms);
+        tm = tb_stage_terms(sroots + a.geo.L, tmeta, a.n_keys);
     } else {
-        tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_terms);
+        tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_keys);
+        if (a.n_keys <= kStageTerms)
+            bt = tb_stage_terms(reinterpret_cast<int32_t*>(sroots + a.geo.L) + a.n_keys * 8, bt,
+                                FORM == 2 ? ft.n_pkeys : ft.n_bkeys);
     }
     __syncthreads();
 
@@ -183,6 +430,9 @@ __global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* 
     const int xcd = blockIdx.x % kXcd;
     const int64_t wstride = (int64_t)(gridDim.x / kXcd) * kWavesPerBlock;
     const ModeGeom geo = a.geo;
+    // this wave's folded force-constant table (FP64 forms), rewritten per unit
+    constexpr int FMT = FORM == 2 ? kXMT : 2;  // M-tiles per K-step of the folded table
+    double2* __restrict__ fw = ft.fold + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * ft.n_fold_ks * FMT * kWave;
     const int32_t N0 = geo.N0, N1 = geo.N1, N2 = geo.N2;
     const int32_t nq = N0 * N1 * N2;
     // Each XCD takes one slice of the q' range of every fused row.  The kept
@@ -220,12 +470,51 @@ __global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* 
             const int32_t iq0 = g0 / NB;
             const int32_t q00 = iq0 / (N1 * N2), q01 = (iq0 / N2) % N1, q02 = iq0 % N2;
             const int32_t q10 = iq1 / (N1 * N2), q11 = (iq1 / N2) % N1, q12 = iq1 % N2;
-            const double2* __restrict__ phit_row = phit + fr * a.n_terms * 27;
+            const double2* __restrict__ phit_row = phit + fr * a.n_keys * 27;
             double w1[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) w1[j] = omega[iq1 * NB + j];
             double pm1[3] = {0.0, 0.0, 0.0};
             if (ADAPT) fused_proj_max(f.vel, iq1, f, geo, pm1);
+            // The folded table of the FP64 forms is built at the unit's first
+            // batch: most units of the ++ and -- types keep no process at all.
+            bool folded = false;
+            auto fold_unit = [&]() {
+                const int32_t Q10 = s1 > 0 ? q10 : wrapn(-q10, N0);
+                const int32_t Q11 = s1 > 0 ? q11 : wrapn(-q11, N1);
+                const int32_t Q12 = s1 > 0 ? q12 : wrapn(-q12, N2);
+                if constexpr (FORM == 2) {
+                    tbx_fold(fw, phit_row, evec, iq1, s1 > 0 ? 1.0 : -1.0, Q10, Q11, Q12, tm, ft.ptab, ft.plist,
+                             ft.pgroups, ft.n_pgroups, sroots, geo);
+                } else if constexpr (FORM == 0) {
+                    // F[b][c] = sum_{k in b} exp(2 pi i Q1.A_k / L) phit_k[c], in the
+                    // MFMA A-operand layout that tb_batch reads (K-step, component
+                    // tile, lane); zero for a missing key or component
+                    const int li = lane & 15, lk = lane >> 4;
+                    for (int gi = 0; gi < a.n_groups; ++gi) {
+                        const int32_t* G = ft.fgroups + gi * 8;
+                        const int32_t b0 = G[3], b1 = G[4], kb = G[5];
+                        const int n_ks = (b1 - b0 + 3) >> 2;
+                        for (int ks = 0; ks < n_ks; ++ks) {
+                            const int32_t b = b0 + 4 * ks + lk;
+                            double2 F0 = make_double2(0.0, 0.0), F1 = make_double2(0.0, 0.0);
+                            if (b < b1) {
+                                const int32_t k0 = bt[b * 8], k1 = k0 + bt[b * 8 + 7];
+                                for (int32_t k = k0; k < k1; ++k) {
+                                    const int32_t* e = tm + k * 8;
+                                    const uint32_t kk = (uint32_t)(Q10 * e[1] + Q11 * e[2] + Q12 * e[3]);
+                                    const double2 uu = sroots[mod_l(kk, geo.L, geo.magic)];
+                                    F0 = cfma(F0, uu, phit_row[(int64_t)k * 27 + li]);
+                                    if (li < 11) F1 = cfma(F1, uu, phit_row[(int64_t)k * 27 + 16 + li]);
+                                }
+                            }
+                            fw[((int64_t)(kb + ks) * 2 + 0) * kWave + lane] = F0;
+                            fw[((int64_t)(kb + ks) * 2 + 1) * kWave + lane] = F1;
+                        }
+                    }
+                }
+                folded = true;
+            };
 
             // kept records wait in buf (position k * 64 + lane in buf[k], pend of
             // them) until 128 have gathered, across chunks of q''; one pass past
@@ -234,6 +523,7 @@ __global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* 
 #pragma unroll
             for (int k = 0; k < kBR; ++k) buf[k] = 0;
             int pend = 0;
+            int ptup = 0;  // tuples in buf (FORM 2 flushes at kXTB of them)
             for (int32_t start = tri12 ? iq1 : 0;; start += kWave) {
                 const bool last = start >= nq;
                 // ---- candidate masks: lane = q''
@@ -368,8 +658,23 @@ __global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* 
                 ntup += __popcll(__ballot(cnt > 0));
                 // ---- batches of 128 kept records, in (q'', j', j'', j''') order
                 int used = 0;
+                const uint64_t nz = __ballot(cnt > 0);  // lanes (tuples) with kept records
                 do {
-                    const int take = kBU - pend < total - used ? kBU - pend : total - used;
+                    int take = kBU - pend < total - used ? kBU - pend : total - used;
+                    if (FORM == 2 && take > 0) {
+                        // at most kXTB - ptup more tuples: every lane the take touches is
+                        // one new tuple of the buffer (a take starts at a lane boundary,
+                        // or mid-lane right after a flush)
+                        const uint64_t from = __ballot(incl > used) & nz;  // lanes at or after record `used`
+                        const int room = kXTB - ptup;
+                        if (__popcll(from) > room) {
+                            const int l1 = select_bit(from, room - 1);  // the room-th such lane
+                            const int end = __shfl(incl, l1, kWave);
+                            take = end - used < take ? end - used : take;
+                        }
+                        const uint64_t upto = __ballot(excl < used + take) & nz;  // lanes before the take's end
+                        ptup += __popcll(from & upto);
+                    }
                     if (take > 0) {
 #pragma unroll
                         for (int k = 0; k < kBR; ++k) {
@@ -411,16 +716,22 @@ __global__ __launch_bounds__(kBlock, MIXED ? 2 : 3) void k_fused4(const double* 
                     }
                     pend += take;
                     used += take;
-                    if (pend == kBU || (last && pend > 0)) {
-                        if constexpr (MIXED)
+                    if (pend == kBU || (FORM == 2 && ptup == kXTB) || (last && pend > 0)) {
+                        if (!MIXED && !folded) fold_unit();
+                        if constexpr (FORM == 1)
                             tbm_batch<MAXT, false>(buf, pend, g0, type, fsp + fr * n_kblk * 4 * kWave * 3, omega,
                                                    evec32, occ, tm, groups, flag, a,
                                                    reinterpret_cast<const uint4*>(sroots), sA[wave], sQ[wave], accg,
                                                    accw, dl, 0.0, nullptr);
+                        else if constexpr (FORM == 0)
+                            tb_batch<MAXT, false, kBR, kFusedTB, true>(buf, pend, g0, type, fw, omega, evec, occ, bt,
+                                                                       ft.fgroups, flag, a, sroots, sA[wave],
+                                                                       sQ[wave], accg, accw, dl, 0.0, nullptr);
                         else
-                            tb_batch<MAXT, false, kBR, kFusedTB>(buf, pend, g0, type, phit_row, omega, evec, occ, tm, groups, flag, a,
-                                                  sroots, sA[wave], sQ[wave], accg, accw, dl, 0.0, nullptr);
+                            tbx_batch<MAXT>(buf, pend, g0, type, fw, omega, evec, occ, bt, ft.pgroups, ft.n_pgroups,
+                                            flag, a, sroots, sA[wave], &sQ[wave][0][0], accg, accw);
                         pend = 0;
+                        ptup = 0;
                     }
                 } while (used < total);
                 if (last) break;

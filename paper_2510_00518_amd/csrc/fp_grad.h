@@ -97,7 +97,7 @@ __device__ inline double2 vertex_one(const Proc& pr, double c1, double c2, doubl
 struct GradArgs {
     int64_t n_units;   // chunk descriptors
     int64_t n_modes;
-    int32_t n_terms, n_groups, n_pairs;
+    int32_t n_terms, n_keys, n_groups, n_pairs;  // terms (partials), phase keys (tables)
     int32_t n_T;
     ModeGeom geo;
     Broad br;
@@ -105,7 +105,7 @@ struct GradArgs {
     Temps dummy;
 };
 
-// Pair table entry: {group, first term, term count (<= 16), first component}.
+// Pair table entry: {group, first key, key count (<= 16), first component}.
 #define FP_GRAD_PARAMS                                                                                           \
     const double* __restrict__ omega, const double2* __restrict__ evec, const double* __restrict__ occ,         \
         const double2* __restrict__ roots, const double2* __restrict__ phit, const int32_t* __restrict__ tmeta,    \
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_grad(FP_GRAD_PARAMS) {
         const int32_t iq0 = g0 / nb;
         const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
         const double w0 = omega[g0];
-        const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * NC;
+        const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_keys * NC;
         double dl[MAXT];
 #pragma unroll
         for (int it = 0; it < MAXT; ++it) dl[it] = it < a.n_T ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
@@ -258,17 +258,21 @@ __global__ __launch_bounds__(kBlock, 1) void k_grad(FP_GRAD_PARAMS) {
                     for (int r = 0; r < 4; ++r) {
                         const int ti = 4 * r + lk;  // D row held in register r of this lane
                         if (ti < tcnt && cc < NC) {
-                            const int t = tbeg + ti;
-                            const int32_t a0 = tmeta[t * 8];
-                            const uint32_t kq = (uint32_t)(c00 * tc[t * 4] + c01 * tc[t * 4 + 1] + c02 * tc[t * 4 + 2]);
-                            const double2 phq = sroots[mod_l(kq, geo.L, geo.magic)];
-                            const double2 D = cmul(phq, make_double2(Cr[j][r], Ci[j][r]));
-                            const double sc = tscale[t];
-                            double* out = mypart + (int64_t)t * NCOMP + cc;
+                            // D belongs to a phase key: every term of the key takes it
+                            const int key = tbeg + ti;
+                            const int32_t k0 = tmeta[key * 8], k1 = k0 + tmeta[key * 8 + 7];
+                            for (int32_t t = k0; t < k1; ++t) {
+                                const int32_t* tt = tc + (int64_t)t * 4;
+                                const uint32_t kq = (uint32_t)(c00 * tt[0] + c01 * tt[1] + c02 * tt[2]);
+                                const double2 phq = sroots[mod_l(kq, geo.L, geo.magic)];
+                                const double2 D = cmul(phq, make_double2(Cr[j][r], Ci[j][r]));
+                                const double sc = tscale[t];
+                                double* out = mypart + (int64_t)t * NCOMP + cc;
 #pragma unroll
-                            for (int al = 0; al < 3; ++al) {
-                                const double2 e = evec[(int64_t)g0 * nb + 3 * a0 + al];
-                                out[al * NC] += sc * (e.x * D.x - e.y * D.y);
+                                for (int al = 0; al < 3; ++al) {
+                                    const double2 e = evec[(int64_t)g0 * nb + 3 * tt[3] + al];
+                                    out[al * NC] += sc * (e.x * D.x - e.y * D.y);
+                                }
                             }
                         }
                     }
@@ -291,7 +295,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_grad(FP_GRAD_PARAMS) {
 // accumulates on FP64 MFMA (three real products per complex one); after the
 // chunk it is folded with e_lambda and exp(i q.C_t) into the wave's own partial
 // dPhi, so the final block-order reduction makes the result deterministic.
-// Groups hold at most 16 terms: one 16-term A tile.
+// Groups hold at most 16 phase keys: one 16-key A tile.
 __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict__ evec, const double2* __restrict__ roots,
                                                      const int32_t* __restrict__ tmeta, const int32_t* __restrict__ tc,
                                                      const int32_t* __restrict__ groups,
@@ -441,18 +445,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
             const int c = mt * 16 + li;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int t = t0 + 4 * r + lk;
-                if (t < t1 && c < 27) {
+                const int key = t0 + 4 * r + lk;
+                if (key < t1 && c < 27) {
+                    // D belongs to a phase key: every term of the key takes it
                     const double2 D = make_double2(k1[mt][r] - k3[mt][r], k1[mt][r] + k2[mt][r]);
-                    const int32_t a0 = tmeta[t * 8];
-                    const uint32_t kq = (uint32_t)(c00 * tc[t * 4] + c01 * tc[t * 4 + 1] + c02 * tc[t * 4 + 2]);
-                    const double2 Dq = cmul(sroots[mod_l(kq, geo.L, geo.magic)], D);
-                    const double sc = tscale[t];
-                    double* out = mypart + (int64_t)t * 81 + c;
+                    const int32_t kb = tmeta[key * 8], ke = kb + tmeta[key * 8 + 7];
+                    for (int32_t t = kb; t < ke; ++t) {
+                        const int32_t* tt = tc + (int64_t)t * 4;
+                        const uint32_t kq = (uint32_t)(c00 * tt[0] + c01 * tt[1] + c02 * tt[2]);
+                        const double2 Dq = cmul(sroots[mod_l(kq, geo.L, geo.magic)], D);
+                        const double sc = tscale[t];
+                        double* out = mypart + (int64_t)t * 81 + c;
 #pragma unroll
-                    for (int al = 0; al < 3; ++al) {
-                        const double2 e = evec[(int64_t)g0 * nb + 3 * a0 + al];
-                        out[al * 27] += sc * (e.x * Dq.x - e.y * Dq.y);
+                        for (int al = 0; al < 3; ++al) {
+                            const double2 e = evec[(int64_t)g0 * nb + 3 * tt[3] + al];
+                            out[al * 27] += sc * (e.x * Dq.x - e.y * Dq.y);
+                        }
                     }
                 }
             }

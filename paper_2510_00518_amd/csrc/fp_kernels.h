@@ -6,12 +6,13 @@
 //   occ    f64 [n_T][n_modes]            Bose-Einstein occupation per temperature
 //   roots  f64x2 [L]                     exp(2 pi i k / L), L = lcm(N0, N1, N2)
 //   ifc    f64 [n_terms][3^m]            phi * eV / sqrt(prod M), terms sorted by
-//                                        the atoms of slots 1..m-1 ("groups")
-//          i32 [n_terms][8]              a0, phase vectors A (3), B (3), pad
-//          i32 [n_terms][4]              C (3): phase vector of the mode's own q
-//          i32 [n_groups][8]             atoms b, c, d, first term, end term
-//   phit   f64x2 [rows][n_terms][3^(m-1)] force constants contracted with the
-//                                        row mode's eigenvector and q-phase
+//                                        phase key (see below)
+//          i32 [n_terms][4]              C (3): phase vector of the mode's own q; a0
+//          i32 [n_keys][8]               first term, phase vectors A (3), B (3), term count
+//          i32 [n_groups][8]             atoms b, c, d, first key, end key
+//   phit   f64x2 [rows][n_keys][3^(m-1)] force constants contracted with the
+//                                        row mode's eigenvector and q-phase,
+//                                        summed over the terms of each key
 //   units  {start, row, count}           work units: <= U consecutive records of one row
 //   partial f64 [units][2][n_T]          per-unit sums of Gamma and WP terms
 //
@@ -21,7 +22,10 @@
 //       phit_t[beta gamma delta] eps1(b_t)_beta eps2(c_t)_gamma eps3(d_t)_delta
 // with A_t = R1 - R3, B_t = R2 - R3, C_t = -R3 (each scaled by L/N_d, mod L);
 // order 3 uses A_t = R1 - R2, C_t = -R2.  The q.C_t phase and the contraction
-// with e_lambda are folded into phit once per row.
+// with e_lambda are folded into phit once per row.  Terms with the same partner
+// atoms and the same (A, B) -- a phase key -- share the phase of every process,
+// so their folded tables are summed into one entry per key and every kernel
+// after the fold runs over keys.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -245,36 +249,42 @@ struct ModeGeom {
     int32_t s0, s1, s2;  // L / N_d
 };
 
-// phit[row][t][c] = exp(2 pi i q.C_t / L) sum_alpha phi_s[t][alpha][c] e_lambda(a0_t)_alpha
+// phit[row][k][c] = sum_{t in key k} exp(2 pi i q.C_t / L) sum_alpha phi_s[t][alpha][c] e_lambda(a0_t)_alpha
 template <int M>
 __global__ void k_precontract(const RowInfo* __restrict__ rows, int64_t n_rows, const double2* __restrict__ evec,
                               const double2* __restrict__ roots, ModeGeom geo, const double* __restrict__ phi_s,
-                              const int32_t* __restrict__ tmeta, const int32_t* __restrict__ tc, int64_t n_terms,
+                              const int32_t* __restrict__ tmeta, const int32_t* __restrict__ tc, int64_t n_keys,
                               double2* __restrict__ phit) {
     constexpr int NC = M == 3 ? 9 : 27;
-    const int64_t total = n_rows * n_terms * NC;
+    const int64_t total = n_rows * n_keys * NC;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i % NC);
-        const int64_t t = (i / NC) % n_terms;
-        const int64_t r = i / (NC * n_terms);
+        const int64_t k = (i / NC) % n_keys;
+        const int64_t r = i / (NC * n_keys);
         const int32_t g = rows[r].mode;
         double2 acc = make_double2(0.0, 0.0);
         if (g >= 0) {
             const int32_t iq = g / geo.nb;
             const int32_t n2 = iq % geo.N2, n1 = (iq / geo.N2) % geo.N1, n0 = iq / (geo.N1 * geo.N2);
-            const int32_t a0 = tmeta[t * 8 + 0];
-            const double* p = phi_s + t * (NC * 3);
-            const double2* e = evec + (int64_t)g * geo.nb + 3 * a0;
+            const int32_t t0 = tmeta[k * 8], t1 = t0 + tmeta[k * 8 + 7];
+            for (int32_t t = t0; t < t1; ++t) {
+                const int32_t* tt = tc + (int64_t)t * 4;
+                const double* p = phi_s + (int64_t)t * (NC * 3);
+                const double2* e = evec + (int64_t)g * geo.nb + 3 * tt[3];
+                double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double f = p[a * NC + c];
-                const double2 ev = e[a];
-                acc.x += f * ev.x;
-                acc.y += f * ev.y;
+                for (int a = 0; a < 3; ++a) {
+                    const double f = p[a * NC + c];
+                    const double2 ev = e[a];
+                    s.x += f * ev.x;
+                    s.y += f * ev.y;
+                }
+                const uint32_t kq = (uint32_t)(n0 * tt[0] + n1 * tt[1] + n2 * tt[2]);
+                s = cmul(roots[mod_l(kq, geo.L, geo.magic)], s);
+                acc.x += s.x;
+                acc.y += s.y;
             }
-            const uint32_t k = (uint32_t)(n0 * tc[t * 4 + 0] + n1 * tc[t * 4 + 1] + n2 * tc[t * 4 + 2]);
-            acc = cmul(roots[mod_l(k, geo.L, geo.magic)], acc);
         }
         phit[i] = acc;
     }
@@ -296,7 +306,7 @@ struct Broad {
 struct RatesArgs {
     int64_t n_units;
     int64_t n_modes;
-    int32_t n_terms, n_groups;
+    int32_t n_keys, n_groups;  // phase keys (entries of the per-row tables), partner groups
     int32_t n_T;
     int32_t ppl;  // records per lane per unit
     ModeGeom geo;
@@ -547,7 +557,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
             const int32_t iq0 = g0 / nb;
             const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
             const double w0 = omega[g0];
-            const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_terms * NC;
+            const double2* __restrict__ phit_row = phit + (int64_t)row * a.n_keys * NC;
             for (int p0 = 0; p0 * kWave < count; p0 += NP) {
                 Proc pr[NP];
                 uint32_t evf[NP];  // event flags (FP_3E records): bit 0 the 3+ processes, bit 1 the 3- one

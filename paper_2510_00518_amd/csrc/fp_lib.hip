@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -107,16 +108,33 @@ struct StreamSlot {
 struct IfcState {
     int32_t order = 0;
     int64_t n_terms = 0;
+    int64_t n_keys = 0;  // phase keys (entries of the per-row tables)
     int32_t n_groups = 0;
     std::vector<int32_t> atoms, cells;  // structure as loaded, to skip re-uploads
     DevBuf<double> raw, phi_s, scale;
+    // perm, scale, tc: per sorted term (tc = C scaled by L/N_d mod L, then a0);
+    // tmeta: per phase key {first term, A, B, term count}; groups, pairs, kblk: over keys
     DevBuf<int32_t> perm, tmeta, tc, groups, pairs, kblk;
-    int32_t n_pairs = 0;  // 16-term x 16-component tiles of the adjoint, within groups
-    int32_t n_kblk = 0;   // 16-term K-blocks of the mixed-precision kernel, within groups
+    int32_t n_pairs = 0;  // 16-key x 16-component tiles of the adjoint, within groups
+    int32_t n_kblk = 0;   // 16-key K-blocks of the mixed-precision kernel, within groups
+    // order 4, fused path: B-keys (runs of keys with the same partner atoms and B),
+    // btab [n_bkeys][8] = {first key, 0, 0, 0, B (3), key count}; fgroups over
+    // B-keys [n][8] = {atoms b, c, d, first B-key, end B-key, first K-step, 0, 0}
+    DevBuf<int32_t> btab, fgroups;
+    int32_t n_bkeys = 0, n_fgroups = 0, n_fks = 0;
+    // order 4, fused path with the first partner folded per unit: pair groups over
+    // the atoms of slots 2 and 3, each over "pkeys" (distinct B within the pair);
+    // ptab [n_pkeys][8] = {first plist entry, entry count, 0, 0, B (3), 0},
+    // plist [n][2] = {key, atom of slot 1}, pgroups [n][8] = {atoms c, d, first
+    // pkey, end pkey, first K-step, 0, 0, 0}
+    DevBuf<int32_t> ptab, plist, pgroups;
+    int32_t n_pkeys = 0, n_pgroups = 0, n_pks = 0;
     void release() {
         raw.release(); phi_s.release(); scale.release();
         perm.release(); tmeta.release(); tc.release(); groups.release(); pairs.release(); kblk.release();
-        order = 0; n_terms = 0; n_groups = 0; n_pairs = 0; n_kblk = 0;
+        btab.release(); fgroups.release(); ptab.release(); plist.release(); pgroups.release();
+        order = 0; n_terms = 0; n_keys = 0; n_groups = 0; n_pairs = 0; n_kblk = 0;
+        n_bkeys = 0; n_fgroups = 0; n_fks = 0; n_pkeys = 0; n_pgroups = 0; n_pks = 0;
         atoms.clear(); cells.clear();
     }
 };
@@ -157,6 +175,7 @@ struct fp_ctx {
     DevBuf<double> gpart;
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
+    DevBuf<double2> fold;     // fused FP64 path: one folded force-constant table per wave
     DevBuf<int64_t> unit_kept;  // fused enumeration: kept records per unit
     DevBuf<int64_t> unit_tup;   // fused enumeration: tuples with a kept record per unit
     DevBuf<int64_t> fused_cnt;  // last fused call: processes, tuples
@@ -167,6 +186,7 @@ struct fp_ctx {
     int32_t blocks_per_cu = 0;  // 0: as many resident blocks as the kernel's occupancy allows
     int32_t variant = 6;        // order-4 contraction form: 0-3 per-process (k_rates), 4-7 tuple-batched
     int32_t grad_chunk = 8192;  // records per adjoint chunk (a multiple of 256)
+    int32_t fused_form = 2;     // FP64 form of fp_rates4_fused: 0 B-keys, 2 first partner folded
     // kernel timing
     bool profile = false;
     std::vector<hipEvent_t> ev_pool;
@@ -275,7 +295,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
     c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release();
-    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->unit_kept.release();
+    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release(); c->unit_kept.release();
     c->unit_tup.release(); c->fused_cnt.release();
     c->slot[0].release(); c->slot[1].release();
     if (c->flag) (void)hipFree(c->flag);
@@ -303,6 +323,9 @@ extern "C" fp_status fp_set_knob(fp_ctx* c, const char* name, int64_t value) {
     } else if (!strcmp(name, "variant")) {
         if (value < 0 || value > 7) return fail(c, FP_ERR_ARG, "variant must be in [0, 7]");
         c->variant = (int32_t)value;
+    } else if (!strcmp(name, "fused_form")) {
+        if (value != 0 && value != 2) return fail(c, FP_ERR_ARG, "fused_form must be 0 or 2");
+        c->fused_form = (int32_t)value;
     } else {
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
     }
@@ -319,6 +342,8 @@ extern "C" fp_status fp_get_knob(fp_ctx* c, const char* name, int64_t* value) {
         *value = c->grad_chunk;
     else if (!strcmp(name, "variant"))
         *value = c->variant;
+    else if (!strcmp(name, "fused_form"))
+        *value = c->fused_form;
     else
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
     return FP_OK;
@@ -441,20 +466,35 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
                       std::equal(atoms, atoms + n_terms * m, S.atoms.begin()) &&
                       std::equal(cells, cells + n_terms * (m - 1) * 3, S.cells.begin());
     if (!same) {
-        // Structure: sort terms by the atoms of slots 1..m-1 (stable), build groups,
-        // phase vectors and scale factors on the host.
+        // Structure.  The phase of term t in a process depends only on the
+        // partner atoms and on the lattice vectors A = R1 - R_last (and
+        // B = R2 - R_last for order 4) reduced modulo the mesh: exp(i Q.R) takes
+        // the same value for R and R + N_d a_d.  Terms that agree in these (a
+        // "phase key") share every phase, so once each is contracted with
+        // e_lambda(a0) and exp(i q.C_t) per row, their tables add and the rate
+        // kernels see one entry per key.  Terms are sorted by key (partner
+        // atoms, then B, then A), keys are grouped by partner atoms.
         std::vector<int32_t> perm((size_t)n_terms);
         std::iota(perm.begin(), perm.end(), 0);
+        const int64_t L = c->L;
+        const int64_t sc[3] = {L / c->mesh[0], L / c->mesh[1], L / c->mesh[2]};
+        auto phase_vec = [&](int32_t t, int r, int d) {  // (R_r - R_last)_d scaled by L/N_d, mod L; r = 1, 2
+            const int32_t* ce = cells + (int64_t)t * (m - 1) * 3;
+            const int32_t* Rl = ce + (m - 2) * 3;
+            return (int32_t)wrapi((int64_t)(ce[(r - 1) * 3 + d] - Rl[d]) * sc[d], L);
+        };
         auto key = [&](int32_t t) {
-            int64_t k = 0;
-            for (int r = 1; r < m; ++r) k = k * 64 + atoms[(int64_t)t * m + r];
+            std::vector<int64_t> k;
+            for (int r = 1; r < m; ++r) k.push_back(atoms[(int64_t)t * m + r]);
+            if (m == 4)
+                for (int d = 0; d < 3; ++d) k.push_back(phase_vec(t, 2, d));
+            for (int d = 0; d < 3; ++d) k.push_back(phase_vec(t, 1, d));
             return k;
         };
         std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
-        std::vector<int32_t> tmeta((size_t)n_terms * 8, 0), tc((size_t)n_terms * 4, 0), groups;
+        std::vector<int32_t> tmeta, tc((size_t)n_terms * 4, 0), groups;
         std::vector<double> scale((size_t)n_terms);
-        const int64_t L = c->L;
-        const int64_t sc[3] = {L / c->mesh[0], L / c->mesh[1], L / c->mesh[2]};
+        std::vector<int64_t> prev;
         for (int64_t i = 0; i < n_terms; ++i) {
             const int32_t t = perm[(size_t)i];
             const int32_t* at = atoms + (int64_t)t * m;
@@ -463,25 +503,35 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
             double msc = 1.0;
             for (int r = 0; r < m; ++r) msc *= c->masses[at[r]];
             scale[(size_t)i] = kEv / std::sqrt(msc);
-            tmeta[(size_t)i * 8 + 0] = at[0];
-            for (int d = 0; d < 3; ++d) {
-                // A = R1 - R_last, B = R2 - R_last (order 4), C = -R_last, scaled by L/N_d mod L
-                tmeta[(size_t)i * 8 + 1 + d] = (int32_t)wrapi((int64_t)(ce[d] - Rl[d]) * sc[d], L);
-                if (m == 4) tmeta[(size_t)i * 8 + 4 + d] = (int32_t)wrapi((int64_t)(ce[3 + d] - Rl[d]) * sc[d], L);
-                tc[(size_t)i * 4 + d] = (int32_t)wrapi(-(int64_t)Rl[d] * sc[d], L);
+            for (int d = 0; d < 3; ++d) tc[(size_t)i * 4 + d] = (int32_t)wrapi(-(int64_t)Rl[d] * sc[d], L);
+            tc[(size_t)i * 4 + 3] = at[0];
+            const std::vector<int64_t> k = key(t);
+            if (i > 0 && k == prev) {
+                ++tmeta[tmeta.size() - 1];  // one more term of this key
+                continue;
             }
-            const int64_t k = key(t);
-            // a group holds at most 16 terms (larger ones are split), so one
-            // group's operands fit the rate kernels' registers in one load
-            if (groups.empty() || key(perm[(size_t)groups[groups.size() - 8 + 3]]) != k ||
-                groups[groups.size() - 8 + 4] - groups[groups.size() - 8 + 3] >= 16) {
-                const int32_t g[8] = {at[1], at[2], m == 4 ? at[3] : 0, (int32_t)i, (int32_t)i + 1, 0, 0, 0};
-                groups.insert(groups.end(), g, g + 8);
+            prev = k;
+            // a new key: {first sorted term, A (3), B (3), term count}
+            const int32_t e[8] = {(int32_t)i, phase_vec(t, 1, 0), phase_vec(t, 1, 1), phase_vec(t, 1, 2),
+                                  m == 4 ? phase_vec(t, 2, 0) : 0, m == 4 ? phase_vec(t, 2, 1) : 0,
+                                  m == 4 ? phase_vec(t, 2, 2) : 0, 1};
+            tmeta.insert(tmeta.end(), e, e + 8);
+            const int32_t ki = (int32_t)(tmeta.size() / 8) - 1;
+            // a group holds the keys of one partner-atom tuple, at most 16 of them
+            // (larger ones are split), so one group's operands fit the rate
+            // kernels' registers in one load
+            const bool same_atoms = !groups.empty() && groups[groups.size() - 8] == at[1] &&
+                                    groups[groups.size() - 7] == at[2] &&
+                                    groups[groups.size() - 6] == (m == 4 ? at[3] : 0);
+            if (same_atoms && groups[groups.size() - 8 + 4] - groups[groups.size() - 8 + 3] < 16) {
+                groups[groups.size() - 8 + 4] = ki + 1;
             } else {
-                groups[groups.size() - 8 + 4] = (int32_t)i + 1;
+                const int32_t g[8] = {at[1], at[2], m == 4 ? at[3] : 0, ki, ki + 1, 0, 0, 0};
+                groups.insert(groups.end(), g, g + 8);
             }
         }
-        // K-blocks of the mixed-precision kernel: 16 consecutive terms of one group;
+        const int64_t n_keys = (int64_t)(tmeta.size() / 8);
+        // K-blocks of the mixed-precision kernel: 16 consecutive keys of one group;
         // groups[g][5] is the group's first block, kblk[b] = {group, block within group}
         std::vector<int32_t> kblk;
         for (size_t g = 0; g + 8 <= groups.size(); g += 8) {
@@ -491,7 +541,7 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
                 kblk.push_back(ks);
             }
         }
-        // adjoint tiles: 16 consecutive terms of one group x 16 components
+        // adjoint tiles: 16 consecutive keys of one group x 16 components
         std::vector<int32_t> pairs;
         const int nc = m == 3 ? 9 : 27;
         for (size_t g = 0; g + 8 <= groups.size(); g += 8) {
@@ -502,7 +552,109 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
                     pairs.insert(pairs.end(), e, e + 4);
                 }
         }
+        // B-keys of the fused path: within a unit (lambda, q') the phase
+        // exp(i Q1.A) of every key is fixed, so the keys that share partner atoms
+        // and B fold into one entry per unit and the per-tuple phase is exp(i Q2.B)
+        std::vector<int32_t> btab, fgroups;
+        int32_t n_fks = 0;
+        if (m == 4) {
+            for (size_t g = 0; g + 8 <= groups.size(); g += 8)
+                for (int32_t k = groups[g + 3]; k < groups[g + 4]; ++k) {
+                    const int32_t* e = tmeta.data() + (size_t)k * 8;
+                    const bool same_b = !btab.empty() && e[4] == btab[btab.size() - 4] &&
+                                        e[5] == btab[btab.size() - 3] && e[6] == btab[btab.size() - 2] &&
+                                        k == btab[btab.size() - 8] + btab[btab.size() - 1] &&
+                                        !fgroups.empty() && fgroups[fgroups.size() - 8] == groups[g] &&
+                                        fgroups[fgroups.size() - 7] == groups[g + 1] &&
+                                        fgroups[fgroups.size() - 6] == groups[g + 2];
+                    if (same_b) {
+                        ++btab[btab.size() - 1];
+                        continue;
+                    }
+                    const int32_t b[8] = {k, 0, 0, 0, e[4], e[5], e[6], 1};
+                    btab.insert(btab.end(), b, b + 8);
+                    const int32_t bi = (int32_t)(btab.size() / 8) - 1;
+                    const bool same_atoms = !fgroups.empty() && fgroups[fgroups.size() - 8] == groups[g] &&
+                                            fgroups[fgroups.size() - 7] == groups[g + 1] &&
+                                            fgroups[fgroups.size() - 6] == groups[g + 2];
+                    if (same_atoms && fgroups[fgroups.size() - 4] - fgroups[fgroups.size() - 5] < 16) {
+                        fgroups[fgroups.size() - 4] = bi + 1;
+                    } else {
+                        const int32_t f[8] = {groups[g], groups[g + 1], groups[g + 2], bi, bi + 1, 0, 0, 0};
+                        fgroups.insert(fgroups.end(), f, f + 8);
+                    }
+                }
+            for (size_t g = 0; g + 8 <= fgroups.size(); g += 8) {
+                fgroups[g + 5] = n_fks;
+                n_fks += (fgroups[g + 4] - fgroups[g + 3] + 3) / 4;
+            }
+        }
+        // pair groups of the x-folded fused form: keys sorted by (atoms c, d; B;
+        // atom b; key), runs of equal (c, d, B) form a pkey, at most 16 pkeys a group
+        std::vector<int32_t> ptab, plist, pgroups;
+        int32_t n_pks = 0;
+        if (m == 4) {
+            std::vector<std::array<int32_t, 6>> kk;  // c, d, B0, B1, B2, b ; then key
+            std::vector<int32_t> kid;
+            for (size_t g = 0; g + 8 <= groups.size(); g += 8)
+                for (int32_t k = groups[g + 3]; k < groups[g + 4]; ++k) {
+                    const int32_t* e = tmeta.data() + (size_t)k * 8;
+                    kk.push_back({groups[g + 1], groups[g + 2], e[4], e[5], e[6], groups[g]});
+                    kid.push_back(k);
+                }
+            std::vector<size_t> ord(kk.size());
+            std::iota(ord.begin(), ord.end(), 0);
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+                return kk[x] != kk[y] ? kk[x] < kk[y] : kid[x] < kid[y];
+            });
+            for (size_t i = 0; i < ord.size(); ++i) {
+                const auto& e = kk[ord[i]];
+                const bool new_pkey = i == 0 || e[0] != kk[ord[i - 1]][0] || e[1] != kk[ord[i - 1]][1] ||
+                                      e[2] != kk[ord[i - 1]][2] || e[3] != kk[ord[i - 1]][3] ||
+                                      e[4] != kk[ord[i - 1]][4];
+                if (new_pkey) {
+                    const int32_t pe[8] = {(int32_t)(plist.size() / 2), 0, 0, 0, e[2], e[3], e[4], 0};
+                    ptab.insert(ptab.end(), pe, pe + 8);
+                    const int32_t pi = (int32_t)(ptab.size() / 8) - 1;
+                    const bool same_pair = !pgroups.empty() && pgroups[pgroups.size() - 8] == e[0] &&
+                                           pgroups[pgroups.size() - 7] == e[1];
+                    if (same_pair && pgroups[pgroups.size() - 5] - pgroups[pgroups.size() - 6] < 16) {
+                        pgroups[pgroups.size() - 5] = pi + 1;
+                    } else {
+                        const int32_t pg[8] = {e[0], e[1], pi, pi + 1, 0, 0, 0, 0};
+                        pgroups.insert(pgroups.end(), pg, pg + 8);
+                    }
+                }
+                ++ptab[ptab.size() - 8 + 1];
+                plist.push_back(kid[ord[i]]);
+                plist.push_back(e[5]);
+            }
+            for (size_t g = 0; g + 8 <= pgroups.size(); g += 8) {
+                pgroups[g + 4] = n_pks;
+                n_pks += (pgroups[g + 3] - pgroups[g + 2] + 3) / 4;
+            }
+        }
         HIP_TRY(c, hipStreamSynchronize(st));  // previous launches may still read the old tables
+        if (m == 4) {
+            HIP_TRY(c, S.ptab.ensure(ptab.size()));
+            HIP_TRY(c, hipMemcpy(S.ptab.p, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice));
+            HIP_TRY(c, S.plist.ensure(plist.size()));
+            HIP_TRY(c, hipMemcpy(S.plist.p, plist.data(), plist.size() * 4, hipMemcpyHostToDevice));
+            HIP_TRY(c, S.pgroups.ensure(pgroups.size()));
+            HIP_TRY(c, hipMemcpy(S.pgroups.p, pgroups.data(), pgroups.size() * 4, hipMemcpyHostToDevice));
+        }
+        S.n_pkeys = (int32_t)(ptab.size() / 8);
+        S.n_pgroups = (int32_t)(pgroups.size() / 8);
+        S.n_pks = n_pks;
+        if (m == 4) {
+            HIP_TRY(c, S.btab.ensure(btab.size()));
+            HIP_TRY(c, hipMemcpy(S.btab.p, btab.data(), btab.size() * 4, hipMemcpyHostToDevice));
+            HIP_TRY(c, S.fgroups.ensure(fgroups.size()));
+            HIP_TRY(c, hipMemcpy(S.fgroups.p, fgroups.data(), fgroups.size() * 4, hipMemcpyHostToDevice));
+        }
+        S.n_bkeys = (int32_t)(btab.size() / 8);
+        S.n_fgroups = (int32_t)(fgroups.size() / 8);
+        S.n_fks = n_fks;
         HIP_TRY(c, S.perm.ensure((size_t)n_terms));
         HIP_TRY(c, S.scale.ensure((size_t)n_terms));
         HIP_TRY(c, S.tmeta.ensure(tmeta.size()));
@@ -522,6 +674,7 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
         S.n_kblk = (int32_t)(kblk.size() / 2);
         S.order = m;
         S.n_terms = n_terms;
+        S.n_keys = n_keys;
         S.n_groups = (int32_t)(groups.size() / 8);
         S.atoms.assign(atoms, atoms + n_terms * m);
         S.cells.assign(cells, cells + n_terms * (m - 1) * 3);
@@ -536,6 +689,19 @@ extern "C" fp_status fp_load_ifc(fp_ctx* c, int32_t order, int64_t n_terms, cons
     hipLaunchKernelGGL(fpk::k_ifc_scale, dim3(grid_for(n_terms * ncomp)), dim3(256), 0, st, src, S.perm.p,
                        S.scale.p, n_terms, ncomp, S.phi_s.p);
     HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
+extern "C" fp_status fp_ifc_info(fp_ctx* c, int32_t order, int64_t out[5]) {
+    if (!c) return FP_ERR_ARG;
+    if (!out || (order != 3 && order != 4)) return fail(c, FP_ERR_ARG, "out must be non-null, order 3 or 4");
+    const IfcState& S = c->ifc[order - 3];
+    if (S.order != order) return fail(c, FP_ERR_STATE, "force constants of order %d not loaded", order);
+    out[0] = S.n_terms;
+    out[1] = S.n_keys;
+    out[2] = S.n_groups;
+    out[3] = S.n_pkeys;
+    out[4] = S.n_pgroups;
     return FP_OK;
 }
 
@@ -605,7 +771,7 @@ fp_status launch_mixed_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::
 template <int T, int BR, int TB, int OCC>
 fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S) {
     auto kern = fpk::k_rates4b<T, false, BR, TB, OCC>;
-    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
+    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_keys);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
@@ -627,7 +793,7 @@ template <int T>
 fp_status launch_batched_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::RatesArgs& a, const IfcState& S,
                            const double* dldg, double pref) {
     auto kern = fpk::k_rates4b<T, true, 2, 24, 3>;
-    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
+    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_keys);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
@@ -723,7 +889,7 @@ fp_status prepare(fp_ctx* c, int m, const fp_plist* lists, const std::vector<int
     HIP_TRY(c, c->row_units.ensure((size_t)total_rows + 1));
     HIP_TRY(c, c->unit_off.ensure((size_t)total_rows + 1));
     HIP_TRY(c, c->units.ensure((size_t)std::max<int64_t>(n_units, 1)));
-    HIP_TRY(c, c->phit.ensure((size_t)total_rows * S.n_terms * ncomp));
+    HIP_TRY(c, c->phit.ensure((size_t)total_rows * S.n_keys * ncomp));
     fpk::Temps tx;
     for (int i = 0; i < 8; ++i) tx.x[i] = i < n_T ? kHbar / (kBoltz * T_K[i]) : 0.0;
     hipLaunchKernelGGL(fpk::k_occ, dim3(grid_for(n_T * nm)), dim3(256), 0, st, c->omega.p, nm, n_T, tx, c->floor_,
@@ -733,13 +899,13 @@ fp_status prepare(fp_ctx* c, int m, const fp_plist* lists, const std::vector<int
     hipLaunchKernelGGL(fpk::k_scan, dim3(1), dim3(fpk::kBlock), 0, st, c->row_units.p, total_rows, c->unit_off.p);
     hipLaunchKernelGGL(fpk::k_units, dim3(grid_for(n_units)), dim3(256), 0, st, c->unit_off.p, total_rows, c->rows.p,
                        unit, n_units, c->units.p);
-    const int64_t npre = total_rows * S.n_terms * ncomp;
+    const int64_t npre = total_rows * S.n_keys * ncomp;
     if (m == 3)
         hipLaunchKernelGGL(fpk::k_precontract<3>, dim3(grid_for(npre)), dim3(256), 0, st, c->rows.p, total_rows,
-                           c->evec.p, c->roots.p, pp->geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+                           c->evec.p, c->roots.p, pp->geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_keys, c->phit.p);
     else
         hipLaunchKernelGGL(fpk::k_precontract<4>, dim3(grid_for(npre)), dim3(256), 0, st, c->rows.p, total_rows,
-                           c->evec.p, c->roots.p, pp->geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+                           c->evec.p, c->roots.p, pp->geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_keys, c->phit.p);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -766,6 +932,13 @@ fp_status timer_stop(fp_ctx* c, hipStream_t st, int tag, hipEvent_t ev0, hipEven
     return FP_OK;
 }
 
+// Records per lane of a work unit (units hold 64 times this many records): the
+// tuple-batched and mixed kernels fix it, the per-process forms take the knob.
+int64_t unit_ppl(const fp_ctx* c, int m, bool mixed) {
+    const int np = m == 3 ? 1 : kVariants[c->variant].np;
+    return mixed ? fpk::kBR : (m == 4 && c->variant >= 4) ? batched_br(c->variant) : (c->ppl + np - 1) / np * np;
+}
+
 fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                     double sigma, int32_t precision, double* gamma_out, double* wp_out, void* stream) {
     if (!c) return FP_ERR_ARG;
@@ -786,10 +959,7 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
             return fail(c, FP_ERR_UNSUPPORTED, "event lists take the fixed width only");
         sel.push_back(l);
     }
-    const int np = m == 3 ? 1 : kVariants[c->variant].np;
-    // the tuple-batched kernel works on units of exactly 128 records
-    const int64_t ppl = mixed ? fpk::kBR
-                        : (m == 4 && c->variant >= 4) ? batched_br(c->variant) : (c->ppl + np - 1) / np * np;
+    const int64_t ppl = unit_ppl(c, m, mixed);
     const int64_t unit = (int64_t)fpk::kWave * ppl;
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -810,7 +980,7 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     fpk::RatesArgs a;
     a.n_units = pp.n_units;
     a.n_modes = nm;
-    a.n_terms = (int32_t)S.n_terms;
+    a.n_keys = (int32_t)S.n_keys;
     a.n_groups = S.n_groups;
     a.n_T = n_T;
     a.ppl = (int32_t)ppl;
@@ -825,7 +995,7 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
         const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
         HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
         hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, pp.total_rows, c->phit.p,
-                           S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_terms, c->fsp.p);
+                           S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_keys, c->fsp.p);
         HIP_TRY(c, hipGetLastError());
     }
     hipEvent_t ev0, ev1;
@@ -927,9 +1097,16 @@ namespace {
 template <int T>
 fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const fpk::FusedArgs& f,
                        const IfcState& S, bool mixed) {
-    auto kern = mixed ? (f.vel ? fpk::k_fused4<T, true, true> : fpk::k_fused4<T, false, true>)
-                      : (f.vel ? fpk::k_fused4<T, true, false> : fpk::k_fused4<T, false, false>);
-    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_terms);
+    // form: 1 mixed; FP64 0 (B-keys) or 2 (first partner folded), the fused_form knob
+    const int form = mixed ? 1 : c->fused_form;
+    auto kern = form == 1 ? (f.vel ? fpk::k_fused4<T, true, 1> : fpk::k_fused4<T, false, 1>)
+                : form == 0 ? (f.vel ? fpk::k_fused4<T, true, 0> : fpk::k_fused4<T, false, 0>)
+                            : (f.vel ? fpk::k_fused4<T, true, 2> : fpk::k_fused4<T, false, 2>);
+    // the FP64 forms also stage the B-key or pkey table when the key table is staged
+    const int32_t n_tab = form == 2 ? S.n_pkeys : S.n_bkeys;
+    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_keys) +
+                       (form != 1 && S.n_keys <= fpk::kStageTerms && n_tab <= fpk::kStageTerms
+                            ? (size_t)n_tab * 8 * sizeof(int32_t) : 0);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
@@ -937,9 +1114,27 @@ fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const
     const int64_t want = (f.n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
+    // one folded table per wave (FP64 forms)
+    fpk::FusedTabs ft;
+    ft.btab = S.btab.p;
+    ft.fgroups = S.fgroups.p;
+    ft.ptab = S.ptab.p;
+    ft.plist = S.plist.p;
+    ft.pgroups = S.pgroups.p;
+    ft.n_bkeys = S.n_bkeys;
+    ft.n_pkeys = S.n_pkeys;
+    ft.n_pgroups = S.n_pgroups;
+    ft.n_fold_ks = form == 2 ? S.n_pks : S.n_fks;
+    const int64_t nfold = form == 1 ? 1
+                                    : nblk * fpk::kWavesPerBlock * (int64_t)ft.n_fold_ks * (form == 2 ? fpk::kXMT : 2) *
+                                          fpk::kWave;
+    HIP_TRY(c, c->fold.ensure((size_t)nfold));
+    ft.fold = c->fold.p;
+    fpk::RatesArgs af = a;
+    if (form == 0) af.n_groups = S.n_fgroups;
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->partial.p, c->unit_kept.p,
-                       c->unit_tup.p, c->flag, a, f, c->evec32.p, c->fsp.p, S.n_kblk);
+                       c->unit_tup.p, c->flag, af, f, c->evec32.p, c->fsp.p, S.n_kblk, ft);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -1023,7 +1218,7 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     HIP_TRY(c, c->occ.ensure((size_t)n_T * nm));
     HIP_TRY(c, c->rows.ensure((size_t)n_frows));
     HIP_TRY(c, c->unit_off.ensure((size_t)n_frows + 1));
-    HIP_TRY(c, c->phit.ensure((size_t)n_frows * S.n_terms * 27));
+    HIP_TRY(c, c->phit.ensure((size_t)n_frows * S.n_keys * 27));
     HIP_TRY(c, c->partial.ensure((size_t)f.n_units * 2 * n_T));
     HIP_TRY(c, c->unit_kept.ensure((size_t)f.n_units));
     HIP_TRY(c, c->unit_tup.ensure((size_t)f.n_units));
@@ -1034,20 +1229,20 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     hipLaunchKernelGGL(fpk::k_fused_rows, dim3(grid_for(n_frows + 1)), dim3(256), 0, st, row_mode, f, (int64_t)c->nq,
                        nm, c->rows.p, c->unit_off.p, c->flag);
     const fpk::ModeGeom geo = geometry(c);
-    hipLaunchKernelGGL(fpk::k_precontract<4>, dim3(grid_for(n_frows * S.n_terms * 27)), dim3(256), 0, st, c->rows.p,
-                       n_frows, c->evec.p, c->roots.p, geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_terms, c->phit.p);
+    hipLaunchKernelGGL(fpk::k_precontract<4>, dim3(grid_for(n_frows * S.n_keys * 27)), dim3(256), 0, st, c->rows.p,
+                       n_frows, c->evec.p, c->roots.p, geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_keys, c->phit.p);
     if (mixed) {
         const int64_t nf = n_frows * S.n_kblk * 4 * fpk::kWave;
         HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
         hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, n_frows, c->phit.p, S.groups.p,
-                           S.kblk.p, S.n_kblk, (int32_t)S.n_terms, c->fsp.p);
+                           S.kblk.p, S.n_kblk, (int32_t)S.n_keys, c->fsp.p);
     }
     HIP_TRY(c, hipGetLastError());
     fpk::RatesArgs a;
     memset(&a, 0, sizeof a);
     a.n_units = f.n_units;
     a.n_modes = nm;
-    a.n_terms = (int32_t)S.n_terms;
+    a.n_keys = (int32_t)S.n_keys;
     a.n_groups = S.n_groups;
     a.n_T = n_T;
     a.ppl = fpk::kBR;
@@ -1222,7 +1417,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
             memset(&ra, 0, sizeof ra);
             ra.n_units = pp.n_units;
             ra.n_modes = c->n_modes;
-            ra.n_terms = (int32_t)S.n_terms;
+            ra.n_keys = (int32_t)S.n_keys;
             ra.n_groups = S.n_groups;
             ra.n_T = n_T;
             ra.ppl = fpk::kBR;
@@ -1233,7 +1428,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
                 const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
                 HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
                 hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, pp.total_rows, c->phit.p,
-                                   S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_terms, c->fsp.p);
+                                   S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_keys, c->fsp.p);
                 ps = tsel == 1 ? launch_mixed_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
                                : (tsel == 4 ? launch_mixed_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
                                             : launch_mixed_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
@@ -1251,6 +1446,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
         a.n_units = pp.n_units;
         a.n_modes = c->n_modes;
         a.n_terms = (int32_t)S.n_terms;
+        a.n_keys = (int32_t)S.n_keys;
         a.n_groups = S.n_groups;
         a.n_pairs = S.n_pairs;
         a.n_T = n_T;

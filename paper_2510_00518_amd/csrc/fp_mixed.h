@@ -54,7 +54,7 @@ __device__ inline bf16x8 as_bf16x8(uint4 w) { return __builtin_bit_cast(bf16x8, 
 // A[i = l % 16][k = 8 (l / 16) + v], v = 0..7, with i = 2 (c - 8 mt) + ri and
 // k = 2 (term - first term of the block) + part.
 __global__ void k_split_phit(int64_t total_rows, const double2* __restrict__ phit, const int32_t* __restrict__ groups,
-                             const int32_t* __restrict__ kblk, int32_t n_kblk, int32_t n_terms, uint4* __restrict__ fsp) {
+                             const int32_t* __restrict__ kblk, int32_t n_kblk, int32_t n_keys, uint4* __restrict__ fsp) {
     const int64_t n = total_rows * n_kblk * 4 * kWave;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
         const int lane = (int)(x % kWave);
@@ -72,7 +72,7 @@ __global__ void k_split_phit(int64_t total_rows, const double2* __restrict__ phi
             const int t = t0 + 16 * ks + 4 * kq + (v >> 1);
             const int part = v & 1;
             double2 F = make_double2(0.0, 0.0);
-            if (t < t1 && comp < 27) F = phit[((int64_t)row * n_terms + t) * 27 + comp];
+            if (t < t1 && comp < 27) F = phit[((int64_t)row * n_keys + t) * 27 + comp];
             const double a = ri == 0 ? (part == 0 ? F.x : -F.y) : (part == 0 ? F.y : F.x);
             uint32_t h[3];
             split3(a, h);

@@ -24,7 +24,8 @@ FP_MAX_LISTS = 8
 
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
            "fp_rates4_fused", "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
-           "fp_enumerate_count", "fp_enumerate_fill", "fp_set_broadening", "fp_rates_streamed", "fp_fused_counts"]
+           "fp_enumerate_count", "fp_enumerate_fill", "fp_set_broadening", "fp_rates_streamed", "fp_fused_counts",
+           "fp_ifc_info"]
 
 
 class FpError(RuntimeError):
@@ -90,6 +91,7 @@ def lib():
             f.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp]
         L.fp_rates4_fused.argtypes = [vp, i64, vp, i32, i32, vp, dbl, dbl, i32, vp, vp, vp, vp]
         L.fp_fused_counts.argtypes = [vp, vp, vp]
+        L.fp_ifc_info.argtypes = [vp, i32, vp]
         L.fp_rates_backward.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp, vp]
         L.fp_kappa_rta.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
         L.fp_check.argtypes = [vp, vp]
@@ -242,6 +244,15 @@ def fp_rates4_fused(ctx, row_mode, type_mask, T, sigma, nsigma, precision=FP_FP6
                                       float(sigma), float(nsigma), int(precision), _dp(gamma_out), _dp(wp_out),
                                       _dp(n_kept), _stream(stream)))
 
+
+
+def fp_ifc_info(ctx, order):
+    """{"n_terms", "n_keys", "n_groups", "n_pkeys", "n_pgroups"} of the loaded
+    force constants of `order`."""
+    out = np.zeros(5, np.int64)
+    _check(ctx, lib().fp_ifc_info(ctx, int(order), _hp(out)))
+    return {"n_terms": int(out[0]), "n_keys": int(out[1]), "n_groups": int(out[2]), "n_pkeys": int(out[3]),
+            "n_pgroups": int(out[4])}
 
 
 def fp_fused_counts(ctx, stream=None):

@@ -95,14 +95,18 @@ def assert_modes(g, go, what, rtol=1e-10):
     assert err.max() <= rtol, what
 
 
+@pytest.mark.parametrize("form", [0, 2])
 @pytest.mark.parametrize("mesh,sigma,stride", [(4, None, 5), (4, 10.0, 11), (3, 4.0, 2)])
-def test_fused_matches_oracle_brute_force(ctx, mesh, sigma, stride):
+def test_fused_matches_oracle_brute_force(ctx, mesh, sigma, stride, form):
+    """Both FP64 forms of the fused launch (keys folded per unit; keys and the
+    first partner folded per unit, the default)."""
     cfg = small_config(mesh)
     sig = cfg["sigma"] if sigma is None else sigma
     rows = np.asarray(row_modes(cfg)[::stride], np.int32)
     T = [300.0, 1200.0]
-    g, w, kept = fused_rates(ctx, cfg, rows, T, sigma=sig)
-    n_proc, n_tup = fp.fp_fused_counts(ctx)
+    with knob_util.knobs(ctx, fused_form=form):
+        g, w, kept = fused_rates(ctx, cfg, rows, T, sigma=sig)
+        n_proc, n_tup = fp.fp_fused_counts(ctx)
     go, wo, ko, to = oracle_rows(cfg, TYPES4, rows, T, sig)
     say(f"fused {mesh}^3 sigma={sig}: {kept} processes in {n_tup} tuples (oracle {ko} in {to})")
     assert kept == ko and n_proc == ko
@@ -111,8 +115,9 @@ def test_fused_matches_oracle_brute_force(ctx, mesh, sigma, stride):
     assert_modes(w, wo, "WP4")
 
 
+@pytest.mark.parametrize("form", [0, 2])
 @pytest.mark.parametrize("mesh,factor,floor,stride", [(4, 0.5, 0.3, 13), ((2, 3, 4), 0.7, 0.2, 5), (3, 2.0, 0.5, 4)])
-def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride):
+def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride, form):
     """Adaptive width in the on-GPU filter: the kept count equals the oracle's
     adaptive enumeration exactly, and the rates its list-mode sums."""
     import torch
@@ -127,9 +132,10 @@ def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride):
     p.set_fused(rows, 7)
     gam, wp = p.outputs(len(T))
     p.load_ifc()
-    p.rates(T, gam, wp, order=4)
-    fp.fp_check(ctx)
-    torch.cuda.synchronize()
+    with knob_util.knobs(ctx, fused_form=form):
+        p.rates(T, gam, wp, order=4)
+        fp.fp_check(ctx)
+        torch.cuda.synchronize()
     kept = int(p.kept.cpu()[0])
     S = oracle.System(cfg, broadening=b)
     n = cfg["omega"].size
@@ -301,10 +307,11 @@ def test_fused_matches_lists_fcc8(ctx):
 @pytest.fixture(scope="module")
 def fcc16_fp64(ctx):
     """The 16^3 two-atom cell (145 irreducible q1, 62 + 164 terms, T = 300, 600,
-    900 K): every row in one FP64 fused launch, shared by the parity and the
-    mixed-precision tests below."""
+    900 K): every row in one FP64 fused launch (Gamma4), and the 3ph rates of
+    every row from the host enumerator's lists (Gamma3), shared by the tests
+    below."""
     import torch
-    from paper_2510_00518_amd.driver import RatePath
+    from paper_2510_00518_amd.driver import TYPES3, RatePath, host_lists
     cfg = make_config("fcc16_34ph")
     T = [float(x) for x in cfg["T"]]
     rows = np.asarray(row_modes(cfg), np.int32)
@@ -313,6 +320,7 @@ def fcc16_fp64(ctx):
     gam, wp = p.outputs(len(T))
     p.load_ifc()
     torch.cuda.synchronize()
+    say(f"fcc16_34ph: fused FP64 launch over {len(rows)} rows")
     t0 = time.perf_counter()
     p.rates(T, gam, wp, order=4)
     fp.fp_check(ctx)
@@ -323,23 +331,20 @@ def fcc16_fp64(ctx):
     assert n_proc == kept and 0 < n_tup <= kept
     say(f"fcc16_34ph fused: {len(rows)} rows, {kept} processes in {n_tup} tuples, {dt:.2f} s "
         f"({kept / dt:.3e} processes/s)")
-    return cfg, T, rows, p, gam, kept
+    lists3 = host_lists(cfg, TYPES3)
+    p3 = RatePath(cfg, ctx=ctx)
+    p3.set_lists(lists3)
+    gam3, _ = p3.outputs(len(T))
+    p3.load_ifc()
+    p3.rates(T, gam3)
+    fp.fp_check(ctx)
+    torch.cuda.synchronize()
+    say(f"fcc16_34ph 3ph: {p3.n_proc3} processes from host lists")
+    return dict(cfg=cfg, T=T, rows=rows, p=p, gam4=gam, kept=kept, lists3=lists3, gam3=gam3)
 
 
-@pytest.mark.slow
-def test_fused_paper_scale_fcc16(fcc16_fp64):
-    """All rows finite and non-negative; one sampled row against the oracle."""
-    cfg, T, rows, p, gam, kept = fcc16_fp64
-    g = gam.cpu().numpy()
-    assert np.all(np.isfinite(g)) and np.all(g[:, rows] >= 0)
-    # the sampled row: the one with the fewest processes among six seeded candidates
-    rng = np.random.default_rng(251000518 + 7)
-    cand = rng.choice(rows, size=6, replace=False)
-    counts = []
-    for gm in cand:
-        counts.append(sum(int(fp.fp_enumerate_count(t, cfg["mesh"], cfg["nb"], cfg["omega"], cfg["omega_floor"],
-                                                    [int(gm)], cfg["sigma"], cfg["nsigma"])[-1]) for t in TYPES4))
-    gm = int(cand[int(np.argmin(counts))])
+def fcc16_oracle_row(cfg, T, gm):
+    """The oracle's list-mode Gamma4 of row gm over the enumerator's full lists."""
     S = oracle.System(cfg)
     want = np.zeros(len(T))
     n_rec = 0
@@ -349,18 +354,57 @@ def test_fused_paper_scale_fcc16(fcc16_fp64):
         if len(rec):
             go, _, _, _ = S.rates(t, rm, T, cfg["sigma"], row_off=off, rec=rec)
             want += go[0]
-    err = np.abs(g[:, gm] - want) / np.abs(want)
-    say(f"row g={gm}: {n_rec} processes, fused {g[:, gm]} oracle {want} rel {err}")
-    assert err.max() <= 1e-10
+        del rec
+    return want, n_rec
+
+
+@pytest.mark.slow
+def test_fused_paper_scale_fcc16(fcc16_fp64):
+    """All rows finite and non-negative; a median-length row against the
+    oracle (5.7e7 processes)."""
+    W = fcc16_fp64
+    cfg, T, rows = W["cfg"], W["T"], W["rows"]
+    g = W["gam4"].cpu().numpy()
+    assert np.all(np.isfinite(g)) and np.all(g[:, rows] >= 0)
+    rng = np.random.default_rng(251000518 + 7)
+    # the median-length row among 15 seeded candidates (+- counts; the +- lists
+    # hold almost every process of the cell)
+    cand = rng.choice(rows, size=15, replace=False)
+    pm = [int(fp.fp_enumerate_count(fp.FP_4PM, cfg["mesh"], cfg["nb"], cfg["omega"], cfg["omega_floor"], [int(gm)],
+                                    cfg["sigma"], cfg["nsigma"])[-1]) for gm in cand]
+    median = int(cand[int(np.argsort(pm)[len(pm) // 2])])
+    for gm, what in ((median, "median +- length of fifteen"),):
+        t0 = time.perf_counter()
+        want, n_rec = fcc16_oracle_row(cfg, T, gm)
+        err = np.abs(g[:, gm] - want) / np.abs(want)
+        say(f"row g={gm} ({what}): {n_rec} processes, fused {g[:, gm]} oracle {want} rel {err} "
+            f"(oracle {time.perf_counter() - t0:.1f} s)")
+        assert err.max() <= 1e-10
+
+
+@pytest.mark.slow
+def test_three_phonon_fcc16(fcc16_fp64):
+    """The 16^3 cell's 3ph rates (62 cubic terms, three temperatures) from host
+    lists, every row against the oracle's list-mode sums of the same lists."""
+    W = fcc16_fp64
+    cfg, T = W["cfg"], W["T"]
+    S = oracle.System(cfg)
+    go = np.zeros((len(T), cfg["omega"].size))
+    for t, (rm, off, rec) in W["lists3"].items():
+        g, _, _, _ = S.rates(t, rm, T, cfg["sigma"], row_off=off, rec=rec)
+        go[:, rm] += g.T
+    assert_modes(W["gam3"].cpu().numpy(), go, "Gamma3 16^3, every row")
 
 
 @pytest.mark.slow
 def test_fused_paper_scale_fcc16_mixed(ctx, fcc16_fp64):
     """The mixed-precision launch on the same cell: the same processes, every
-    non-negligible rate within 2e-5 and kappa_RTA within 1e-5 of FP64."""
+    non-negligible rate within 2e-5, and kappa_RTA from Gamma3 + Gamma4 within
+    1e-5 of FP64 at every temperature."""
     import torch
     from paper_2510_00518_amd.driver import RatePath
-    cfg, T, rows, p, gam, kept = fcc16_fp64
+    W = fcc16_fp64
+    cfg, T, rows, p, gam, kept = W["cfg"], W["T"], W["rows"], W["p"], W["gam4"], W["kept"]
     g = gam.cpu().numpy()
     pm = RatePath(cfg, ctx=ctx, precision=fp.FP_MIXED)
     pm.set_fused(rows, 7)
@@ -375,7 +419,7 @@ def test_fused_paper_scale_fcc16_mixed(ctx, fcc16_fp64):
     kap = {}
     for name, gg in (("fp64", gam), ("mixed", gm_)):
         k = torch.zeros((len(T), 9), dtype=torch.float64, device="cuda")
-        p.kappa(T, gg, k)
+        p.kappa(T, gg + W["gam3"], k)
         torch.cuda.synchronize()
         k = k.cpu().numpy()
         kap[name] = (k[:, 0] + k[:, 4] + k[:, 8]) / 3
@@ -384,7 +428,8 @@ def test_fused_paper_scale_fcc16_mixed(ctx, fcc16_fp64):
     big = np.abs(g) > 1e-6 * np.abs(g).max()
     rel = np.abs(gmx[big] - g[big]) / np.abs(g[big])
     say(f"fcc16_34ph fused mixed: {int(pm.kept.cpu()[0])} processes in {dtm:.2f} s ({kept / dtm:.3e} processes/s); "
-        f"kappa rel err {kerr}, Gamma rel err max {rel.max():.2e}")
+        f"kappa(Gamma3 + Gamma4) {kap['fp64']} W/mK, mixed rel err {kerr}, Gamma4 rel err max {rel.max():.2e}")
+    assert np.all(np.isfinite(kap["fp64"])) and np.all(kap["fp64"] > 0)
     assert int(pm.kept.cpu()[0]) == kept
     assert kerr.max() <= 1e-5
     assert rel.max() <= 2e-5
