@@ -131,56 +131,44 @@ constexpr int kXM = 54;   // components j' gamma delta of one pair group
 constexpr int kXMT = 4;   // M-tiles of 16
 constexpr int kXTB = 16;  // tuples per batch tile (the MFMA N)
 
-// H of this unit for every pair group, written to fw in the MFMA A-operand
-// layout ((K-step, M-tile), lane), zero where the pkey or component does not
-// exist.  c1 = +1 or -1 conjugates the eigenvectors of an emitted lambda'.
-__device__ inline void tbx_fold(double2* __restrict__ fw, const double2* __restrict__ phit_row,
+// H of this unit for every pkey, written to the block's LDS table sF[pk][54]
+// (component j' * 9 + gamma delta) by all threads of the block together.  c1 =
+// +1 or -1 conjugates the eigenvectors of an emitted lambda'.
+__device__ inline void tbx_fold(double2* sF, int32_t n_pkeys, const double2* __restrict__ phit_row,
                                 const double2* __restrict__ evec, int32_t iq1, double c1, int32_t Q10, int32_t Q11,
                                 int32_t Q12, const int32_t* __restrict__ tm, const int32_t* __restrict__ ptab,
-                                const int32_t* __restrict__ plist, const int32_t* __restrict__ pgroups, int n_pgroups,
-                                const double2* sroots, const ModeGeom& geo) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int li = lane & 15, lk = lane >> 4;
+                                const int32_t* __restrict__ plist, const double2* sroots, const ModeGeom& geo) {
     const int nb = geo.nb;
-    for (int gi = 0; gi < n_pgroups; ++gi) {
-        const int32_t* G = pgroups + gi * 8;
-        const int32_t p0 = G[2], p1 = G[3], kb = G[4];
-        const int n_ks = (p1 - p0 + 3) >> 2;
-        for (int ks = 0; ks < n_ks; ++ks) {
-            const int32_t pk = p0 + 4 * ks + lk;
-            for (int mt = 0; mt < kXMT; ++mt) {
-                const int mc = mt * 16 + li;
-                double2 F = make_double2(0.0, 0.0);
-                if (pk < p1 && mc < kXM) {
-                    const int jp = mc / 9, gd = mc % 9;
-                    const int32_t e0 = ptab[pk * 8], e1 = e0 + ptab[pk * 8 + 1];
-                    for (int32_t e = e0; e < e1; ++e) {
-                        const int32_t k = plist[2 * e], ab = plist[2 * e + 1];
-                        const int32_t* t = tm + k * 8;
-                        const uint32_t kq = (uint32_t)(Q10 * t[1] + Q11 * t[2] + Q12 * t[3]);
-                        const double2* x = evec + ((int64_t)iq1 * nb + jp) * nb + 3 * ab;
-                        const double2* h = phit_row + (int64_t)k * 27 + gd;
-                        double2 hx = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < n_pkeys * kXM; i += kBlock) {
+        const int32_t pk = i / kXM;
+        const int mc = i % kXM;
+        const int jp = mc / 9, gd = mc % 9;
+        const int32_t e0 = ptab[pk * 8], e1 = e0 + ptab[pk * 8 + 1];
+        double2 F = make_double2(0.0, 0.0);
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t k = plist[2 * e], ab = plist[2 * e + 1];
+            const int32_t* t = tm + k * 8;
+            const uint32_t kq = (uint32_t)(Q10 * t[1] + Q11 * t[2] + Q12 * t[3]);
+            const double2* x = evec + ((int64_t)iq1 * nb + jp) * nb + 3 * ab;
+            const double2* h = phit_row + (int64_t)k * 27 + gd;
+            double2 hx = make_double2(0.0, 0.0);
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) hx = cfma(hx, h[b * 9], ld_eps(x + b, c1));
-                        F = cfma(F, sroots[mod_l(kq, geo.L, geo.magic)], hx);
-                    }
-                }
-                fw[((int64_t)(kb + ks) * kXMT + mt) * kWave + lane] = F;
-            }
+            for (int bb = 0; bb < 3; ++bb) hx = cfma(hx, h[bb * 9], ld_eps(x + bb, c1));
+            F = cfma(F, sroots[mod_l(kq, geo.L, geo.magic)], hx);
         }
+        sF[i] = F;
     }
 }
 
 // One batch of up to 128 records of one unit (record k * 64 + lane in rec[k];
 // `count` valid), all with the unit's q': decode, find the tuples (a change of
 // q'' between consecutive records), build A_p per pair group and 16-tuple tile
-// on FP64 MFMA from the folded table fw, contract per process on the VALU,
+// on FP64 MFMA from the block's folded table sF, contract per process on the VALU,
 // weight in FP64.  ptab is the pkey table (B at [4..6]); A and Qs are this
 // wave's LDS staging.
 template <int MAXT>
 __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t g0, int type,
-                                 const double2* __restrict__ fw, const double* __restrict__ omega,
+                                 const double2* sF, const double* __restrict__ omega,
                                  const double2* __restrict__ evec, const double* __restrict__ occ,
                                  const int32_t* __restrict__ ptab, const int32_t* __restrict__ pgroups,
                                  int n_pgroups, int* __restrict__ flag, const RatesArgs& a, const double2* sroots,
@@ -227,7 +215,7 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t 
     for (int k = 0; k < kBR; ++k) V[k] = make_double2(0.0, 0.0);
     for (int gi = 0; gi < n_pgroups; ++gi) {
         const int32_t* G = pgroups + gi * 8;
-        const int32_t ac = G[0], ad = G[1], p0 = G[2], p1 = G[3], kb = G[4];
+        const int32_t ac = G[0], ad = G[1], p0 = G[2], p1 = G[3];
         const int n_ks = (p1 - p0 + 3) >> 2;  // <= kMaxKs: groups hold at most 16 pkeys
         for (int tb = 0; tb < n_tup; tb += kXTB) {
             const int nbt = n_tup - tb < kXTB ? n_tup - tb : kXTB;
@@ -262,7 +250,8 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t 
                     const double pd = ph.y - ph.x, ps = ph.x + ph.y;
 #pragma unroll
                     for (int mt = 0; mt < 2; ++mt) {
-                        const double2 F = fw[((int64_t)(kb + ks) * kXMT + 2 * half + mt) * kWave + lane];
+                        const int mc = (2 * half + mt) * 16 + li;
+                        const double2 F = pk < p1 && mc < kXM ? sF[pk * kXM + mc] : make_double2(0.0, 0.0);
                         k1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.x + F.y, ph.x, k1[mt], 0, 0, 0);
                         k2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.x, pd, k2[mt], 0, 0, 0);
                         k3[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(F.y, ps, k3[mt], 0, 0, 0);
@@ -412,16 +401,23 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
     extern __shared__ double2 sroots[];
     __shared__ std::conditional_t<MIXED, float2, double2> sA[kWavesPerBlock][STB][SNC];
     __shared__ int32_t sQ[kWavesPerBlock][STB][2];
+    // FORM 2: the unit's folded table, shared by the block's four waves (after
+    // the staged tables, 16-byte aligned), and the per-wave unit sums
+    __shared__ double sRed[FORM == 2 ? kWavesPerBlock : 1][2 * MAXT];
+    __shared__ int64_t sCnt[FORM == 2 ? kWavesPerBlock : 1][2];
     const int32_t* tm;
     const int32_t* bt = FORM == 2 ? ft.ptab : ft.btab;
+    double2* sF = nullptr;
     if constexpr (MIXED) {
         tbm_roots(reinterpret_cast<uint4*>(sroots), roots, a.geo.L);
         tm = tb_stage_terms(sroots + a.geo.L, tmeta, a.n_keys);
     } else {
         tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_keys);
-        if (a.n_keys <= kStageTerms)
-            bt = tb_stage_terms(reinterpret_cast<int32_t*>(sroots + a.geo.L) + a.n_keys * 8, bt,
-                                FORM == 2 ? ft.n_pkeys : ft.n_bkeys);
+        const int32_t n_tab = FORM == 2 ? ft.n_pkeys : ft.n_bkeys;
+        const bool staged = a.n_keys <= kStageTerms && n_tab <= kStageTerms;
+        if (staged) bt = tb_stage_terms(reinterpret_cast<int32_t*>(sroots + a.geo.L) + a.n_keys * 8, bt, n_tab);
+        if (FORM == 2)
+            sF = sroots + a.geo.L + ((staged ? (a.n_keys + n_tab) * 8 : 0) + 3) / 4;
     }
     __syncthreads();
 
@@ -450,7 +446,10 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
 #pragma unroll
     for (int it = 0; it < MAXT; ++it) dl[it] = 0.0;
 
-    for (int64_t w = (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave; w < w_end; w += wstride) {
+    // FORM 2: a unit per block (the four waves split its q'' range); else a unit per wave
+    const int64_t w_first = FORM == 2 ? (int64_t)(blockIdx.x / kXcd) : (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave;
+    const int64_t w_step = FORM == 2 ? (int64_t)(gridDim.x / kXcd) : wstride;
+    for (int64_t w = w_first; w < w_end; w += w_step) {
         const int64_t fr = w / q_cnt;
         const int32_t iq1 = q_beg + (int32_t)(w % q_cnt);
         const int64_t u = fr * nq + iq1;
@@ -483,10 +482,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                 const int32_t Q10 = s1 > 0 ? q10 : wrapn(-q10, N0);
                 const int32_t Q11 = s1 > 0 ? q11 : wrapn(-q11, N1);
                 const int32_t Q12 = s1 > 0 ? q12 : wrapn(-q12, N2);
-                if constexpr (FORM == 2) {
-                    tbx_fold(fw, phit_row, evec, iq1, s1 > 0 ? 1.0 : -1.0, Q10, Q11, Q12, tm, ft.ptab, ft.plist,
-                             ft.pgroups, ft.n_pgroups, sroots, geo);
-                } else if constexpr (FORM == 0) {
+                if constexpr (FORM == 0) {
                     // F[b][c] = sum_{k in b} exp(2 pi i Q1.A_k / L) phit_k[c], in the
                     // MFMA A-operand layout that tb_batch reads (K-step, component
                     // tile, lane); zero for a missing key or component
@@ -516,6 +512,16 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                 folded = true;
             };
 
+            if constexpr (FORM == 2) {
+                // the block folds the unit's table together (it is read by all
+                // four waves); the barrier before keeps the previous unit's
+                // readers, the one after every writer
+                __syncthreads();
+                tbx_fold(sF, ft.n_pkeys, phit_row, evec, iq1, s1 > 0 ? 1.0 : -1.0, s1 > 0 ? q10 : wrapn(-q10, N0),
+                         s1 > 0 ? q11 : wrapn(-q11, N1), s1 > 0 ? q12 : wrapn(-q12, N2), tm, bt, ft.plist,
+                         sroots, geo);
+                __syncthreads();
+            }
             // kept records wait in buf (position k * 64 + lane in buf[k], pend of
             // them) until 128 have gathered, across chunks of q''; one pass past
             // the last chunk (no candidates) evaluates the remainder
@@ -524,7 +530,10 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
             for (int k = 0; k < kBR; ++k) buf[k] = 0;
             int pend = 0;
             int ptup = 0;  // tuples in buf (FORM 2 flushes at kXTB of them)
-            for (int32_t start = tri12 ? iq1 : 0;; start += kWave) {
+            // FORM 2: wave w of the block takes the chunks w, w + 4, ... of q''
+            const int32_t c_first = (tri12 ? iq1 : 0) + (FORM == 2 ? wave * kWave : 0);
+            const int32_t c_step = FORM == 2 ? kBlock : kWave;
+            for (int32_t start = c_first;; start += c_step) {
                 const bool last = start >= nq;
                 // ---- candidate masks: lane = q''
                 const int32_t iq2 = start + lane;
@@ -717,7 +726,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                     pend += take;
                     used += take;
                     if (pend == kBU || (FORM == 2 && ptup == kXTB) || (last && pend > 0)) {
-                        if (!MIXED && !folded) fold_unit();
+                        if (FORM == 0 && !folded) fold_unit();
                         if constexpr (FORM == 1)
                             tbm_batch<MAXT, false>(buf, pend, g0, type, fsp + fr * n_kblk * 4 * kWave * 3, omega,
                                                    evec32, occ, tm, groups, flag, a,
@@ -728,7 +737,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                                                                        ft.fgroups, flag, a, sroots, sA[wave],
                                                                        sQ[wave], accg, accw, dl, 0.0, nullptr);
                         else
-                            tbx_batch<MAXT>(buf, pend, g0, type, fw, omega, evec, occ, bt, ft.pgroups, ft.n_pgroups,
+                            tbx_batch<MAXT>(buf, pend, g0, type, sF, omega, evec, occ, bt, ft.pgroups, ft.n_pgroups,
                                             flag, a, sroots, sA[wave], &sQ[wave][0][0], accg, accw);
                         pend = 0;
                         ptup = 0;
@@ -738,20 +747,58 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
             }
         }
         double* out = partial + u * (2 * a.n_T);
+        if constexpr (FORM == 2) {
+            // the unit's sums: each wave's, then the four in wave order
 #pragma unroll
-        for (int it = 0; it < MAXT; ++it) {
-            if (it < a.n_T) {
+            for (int it = 0; it < MAXT; ++it) {
                 const double sg = wave_sum(accg[it]);
                 const double sw = wave_sum(accw[it]);
                 if (lane == 0) {
-                    out[it] = sg;
-                    out[a.n_T + it] = sw;
+                    sRed[wave][it] = sg;
+                    sRed[wave][MAXT + it] = sw;
                 }
             }
-        }
-        if (lane == 0) {
-            unit_kept[u] = kept;
-            unit_tup[u] = ntup;
+            if (lane == 0) {
+                sCnt[wave][0] = kept;
+                sCnt[wave][1] = ntup;
+            }
+            __syncthreads();
+            if (threadIdx.x < (unsigned)a.n_T) {
+                const int it = threadIdx.x;
+                double sg = 0.0, sw = 0.0;
+                for (int wv = 0; wv < kWavesPerBlock; ++wv) {
+                    sg += sRed[wv][it];
+                    sw += sRed[wv][MAXT + it];
+                }
+                out[it] = sg;
+                out[a.n_T + it] = sw;
+            }
+            if (threadIdx.x == 0) {
+                int64_t kk = 0, tt = 0;
+                for (int wv = 0; wv < kWavesPerBlock; ++wv) {
+                    kk += sCnt[wv][0];
+                    tt += sCnt[wv][1];
+                }
+                unit_kept[u] = kk;
+                unit_tup[u] = tt;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int it = 0; it < MAXT; ++it) {
+                if (it < a.n_T) {
+                    const double sg = wave_sum(accg[it]);
+                    const double sw = wave_sum(accw[it]);
+                    if (lane == 0) {
+                        out[it] = sg;
+                        out[a.n_T + it] = sw;
+                    }
+                }
+            }
+            if (lane == 0) {
+                unit_kept[u] = kept;
+                unit_tup[u] = ntup;
+            }
         }
     }
 }

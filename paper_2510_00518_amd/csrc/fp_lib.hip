@@ -1097,21 +1097,27 @@ namespace {
 template <int T>
 fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const fpk::FusedArgs& f,
                        const IfcState& S, bool mixed) {
-    // form: 1 mixed; FP64 0 (B-keys) or 2 (first partner folded), the fused_form knob
-    const int form = mixed ? 1 : c->fused_form;
+    // form: 1 mixed; FP64 0 (B-keys) or 2 (first partner folded), the fused_form
+    // knob; form 2 keeps the unit's folded table in LDS (n_pkeys x 54 complex),
+    // so tables beyond 48 KB take form 0
+    const int form = mixed ? 1 : (c->fused_form == 2 && (size_t)S.n_pkeys * fpk::kXM * 16 > (48u << 10) ? 0
+                                                                                                       : c->fused_form);
     auto kern = form == 1 ? (f.vel ? fpk::k_fused4<T, true, 1> : fpk::k_fused4<T, false, 1>)
                 : form == 0 ? (f.vel ? fpk::k_fused4<T, true, 0> : fpk::k_fused4<T, false, 0>)
                             : (f.vel ? fpk::k_fused4<T, true, 2> : fpk::k_fused4<T, false, 2>);
     // the FP64 forms also stage the B-key or pkey table when the key table is staged
     const int32_t n_tab = form == 2 ? S.n_pkeys : S.n_bkeys;
-    const size_t shm = fpk::tb_dyn_lds(c->L, S.n_keys) +
-                       (form != 1 && S.n_keys <= fpk::kStageTerms && n_tab <= fpk::kStageTerms
-                            ? (size_t)n_tab * 8 * sizeof(int32_t) : 0);
+    const bool staged = S.n_keys <= fpk::kStageTerms && n_tab <= fpk::kStageTerms;
+    size_t shm = fpk::tb_dyn_lds(c->L, S.n_keys) + (form != 1 && staged ? (size_t)n_tab * 8 * sizeof(int32_t) : 0);
+    if (form == 2)  // the folded table, 16-byte aligned after the staged tables
+        shm = (size_t)c->L * sizeof(double2) + (staged ? ((size_t)(S.n_keys + n_tab) * 8 + 3) / 4 * 16 : 0) +
+              (size_t)S.n_pkeys * fpk::kXM * sizeof(double2);
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
     const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
-    const int64_t want = (f.n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    // a unit per wave (form 2: per block)
+    const int64_t want = form == 2 ? f.n_units : (f.n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     // one folded table per wave (FP64 forms)
@@ -1125,9 +1131,7 @@ fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const
     ft.n_pkeys = S.n_pkeys;
     ft.n_pgroups = S.n_pgroups;
     ft.n_fold_ks = form == 2 ? S.n_pks : S.n_fks;
-    const int64_t nfold = form == 1 ? 1
-                                    : nblk * fpk::kWavesPerBlock * (int64_t)ft.n_fold_ks * (form == 2 ? fpk::kXMT : 2) *
-                                          fpk::kWave;
+    const int64_t nfold = form != 0 ? 1 : nblk * fpk::kWavesPerBlock * (int64_t)ft.n_fold_ks * 2 * fpk::kWave;
     HIP_TRY(c, c->fold.ensure((size_t)nfold));
     ft.fold = c->fold.p;
     fpk::RatesArgs af = a;
