@@ -237,6 +237,26 @@ fp_status fp_rates3(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t
 fp_status fp_rates4(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                     double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
 
+/* fp_rates4 for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops and harnesses that forbid allocation.  Arguments,
+ * checks and results are those of fp_rates4 (the same kernels, bit for bit).
+ * Every per-call device table (Bose-Einstein table, row and work-unit tables,
+ * per-row force-constant tables, per-unit partial sums, and the bf16 planes of
+ * FP_MIXED) is placed in a fixed workspace compiled into the library,
+ * FP_NOALLOC_BYTES per device, which each device holds from its first context
+ * until the process ends; the call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine) and records no fp_profile timing.
+ * FP_ERR_UNSUPPORTED if the lists need more workspace than that (the message
+ * gives the size), FP_ERR_HIP if the workspace has no device address.  All
+ * contexts on one device share its workspace and the next call overwrites it:
+ * calls that overlap in time on one device (other streams, contexts or host
+ * threads) race, so the caller must serialise them.  Load calls (fp_load_modes,
+ * fp_load_ifc) still allocate and are made beforehand.  Asynchronous on
+ * hip_stream like fp_rates4. */
+#define FP_NOALLOC_BYTES ((int64_t)128 << 20)
+fp_status fp_rates4_noalloc(fp_ctx* ctx, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
+                            double sigma, int32_t precision, double* gamma_out, double* wp_out, void* hip_stream);
+
 /* Four-phonon rates with the process lists generated on the GPU: enumeration
  * (Algorithm 3) fused with the evaluation, for meshes whose lists would not fit
  * in memory.  For every mode of row_mode (DEVICE int32 [n_rows], distinct modes)

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -43,8 +44,10 @@ template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    bool borrowed = false;  // memory the buffer does not own (never freed or grown)
     hipError_t ensure(size_t want) {
         if (want <= n && p) return hipSuccess;
+        if (borrowed) return hipErrorOutOfMemory;
         if (p) {
             // work queued on any stream may still read the old buffer
             hipError_t e = hipDeviceSynchronize();
@@ -60,9 +63,10 @@ struct DevBuf {
         return e;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        borrowed = false;
     }
 };
 
@@ -141,8 +145,22 @@ struct IfcState {
 
 }  // namespace
 
+// Fixed workspace of fp_rates4_noalloc: every device that runs the library
+// holds its own copy until the process ends.  In host code `scratch` is a
+// stand-in, not a device address; the address comes from hipGetSymbolAddress,
+// taken once per device when the first context is created on it.
+constexpr size_t kNoAllocBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // per device, nullptr until looked up
+}  // namespace
+
 struct fp_ctx {
     int device = 0;
+    void* scratch = nullptr;  // this device's address of `scratch`, or nullptr
     int n_cu = 256;
     std::string err;
     bool validate = false;
@@ -267,6 +285,20 @@ extern "C" fp_status fp_create(fp_ctx** out, int32_t device) {
     fp_ctx* c = new (std::nothrow) fp_ctx();
     if (!c) return FP_ERR_NOMEM;
     c->device = device;
+    {
+        // the no-allocation workspace of this device (device current)
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        void* ptr = device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+        if (!ptr) {
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+                ptr = nullptr;
+                (void)hipGetLastError();
+            } else if (device < kMaxDevices) {
+                g_scratch_ptr[device] = ptr;
+            }
+        }
+        c->scratch = ptr;
+    }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->n_cu = ncu;
@@ -1089,6 +1121,86 @@ extern "C" fp_status fp_rates3(fp_ctx* c, const fp_plist* lists, int32_t n_lists
 
 extern "C" fp_status fp_rates4(fp_ctx* c, const fp_plist* lists, int32_t n_lists, int32_t n_T, const double* T_K,
                                double sigma, int32_t precision, double* gamma_out, double* wp_out, void* stream) {
+    return run_rates(c, 4, lists, n_lists, n_T, T_K, sigma, precision, gamma_out, wp_out, stream);
+}
+
+namespace {
+
+// Buffers of one ctx swapped for views into the fixed workspace for the length
+// of one call, and restored when the call returns on any path.
+struct WorkspaceLoan {
+    fp_ctx* c;
+    DevBuf<double> occ, partial;
+    DevBuf<fpk::RowInfo> rows;
+    DevBuf<int64_t> row_units, unit_off;
+    DevBuf<fpk::UnitDesc> units;
+    DevBuf<double2> phit;
+    DevBuf<uint4> fsp;
+    bool profile;
+    template <class T>
+    static void lend(DevBuf<T>& b, DevBuf<T>& keep, unsigned char* base, size_t off, size_t n) {
+        keep = b;
+        b.p = reinterpret_cast<T*>(base + off);
+        b.n = n;
+        b.borrowed = true;
+    }
+    ~WorkspaceLoan() {
+        c->occ = occ; c->partial = partial; c->rows = rows; c->row_units = row_units;
+        c->unit_off = unit_off; c->units = units; c->phit = phit; c->fsp = fsp;
+        c->profile = profile;
+    }
+};
+
+}  // namespace
+
+extern "C" fp_status fp_rates4_noalloc(fp_ctx* c, const fp_plist* lists, int32_t n_lists, int32_t n_T,
+                                       const double* T_K, double sigma, int32_t precision, double* gamma_out,
+                                       double* wp_out, void* stream) {
+    if (!c) return FP_ERR_ARG;
+    if (!c->scratch) return fail(c, FP_ERR_HIP, "the no-allocation workspace has no device address");
+    fp_status cs = check_common(c, n_lists, lists, n_T, T_K, sigma);
+    if (cs != FP_OK) return cs;
+    const IfcState& S = c->ifc[1];
+    if (S.order != 4) return fail(c, FP_ERR_STATE, "force constants of order 4 not loaded");
+    const bool mixed = (precision & ~FP_ACCUMULATE) == FP_MIXED;
+    // the sizes run_rates will ask for, laid out in the workspace (256-byte aligned)
+    const int64_t unit = (int64_t)fpk::kWave * unit_ppl(c, 4, mixed);
+    int64_t total_rows = 0, n_units = 0;
+    for (int l = 0; l < n_lists; ++l) {
+        total_rows += lists[l].n_rows;
+        n_units += (lists[l].n_rec + unit - 1) / unit + lists[l].n_rows;
+    }
+    const int64_t nu = std::max<int64_t>(n_units, 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        return at;
+    };
+    const size_t o_occ = take((size_t)n_T * c->n_modes * 8);
+    const size_t o_rows = take((size_t)total_rows * sizeof(fpk::RowInfo));
+    const size_t o_ru = take((size_t)(total_rows + 1) * 8);
+    const size_t o_uo = take((size_t)(total_rows + 1) * 8);
+    const size_t o_units = take((size_t)nu * sizeof(fpk::UnitDesc));
+    const size_t o_phit = take((size_t)total_rows * S.n_keys * 27 * sizeof(double2));
+    const size_t o_part = take((size_t)nu * 2 * n_T * 8);
+    const size_t n_fsp = mixed ? (size_t)total_rows * S.n_kblk * 4 * fpk::kWave * 3 : 1;
+    const size_t o_fsp = take(n_fsp * sizeof(uint4));
+    if (off > kNoAllocBytes)
+        return fail(c, FP_ERR_UNSUPPORTED, "fp_rates4_noalloc needs %zu bytes of workspace, the maximum is %zu",
+                    off, kNoAllocBytes);
+    HIP_TRY(c, hipSetDevice(c->device));
+    unsigned char* base = static_cast<unsigned char*>(c->scratch);
+    WorkspaceLoan loan{c, {}, {}, {}, {}, {}, {}, {}, {}, c->profile};
+    WorkspaceLoan::lend(c->occ, loan.occ, base, o_occ, (size_t)n_T * c->n_modes);
+    WorkspaceLoan::lend(c->rows, loan.rows, base, o_rows, (size_t)std::max<int64_t>(total_rows, 1));
+    WorkspaceLoan::lend(c->row_units, loan.row_units, base, o_ru, (size_t)total_rows + 1);
+    WorkspaceLoan::lend(c->unit_off, loan.unit_off, base, o_uo, (size_t)total_rows + 1);
+    WorkspaceLoan::lend(c->units, loan.units, base, o_units, (size_t)nu);
+    WorkspaceLoan::lend(c->phit, loan.phit, base, o_phit, (size_t)std::max<int64_t>(total_rows * S.n_keys * 27, 1));
+    WorkspaceLoan::lend(c->partial, loan.partial, base, o_part, (size_t)nu * 2 * n_T);
+    WorkspaceLoan::lend(c->fsp, loan.fsp, base, o_fsp, n_fsp);
+    c->profile = false;  // kernel timing would create events
     return run_rates(c, 4, lists, n_lists, n_T, T_K, sigma, precision, gamma_out, wp_out, stream);
 }
 

@@ -21,11 +21,12 @@ FP_3P, FP_3M, FP_4PP, FP_4PM, FP_4MM, FP_3E = 0, 1, 2, 3, 4, 5
 ORDER = {FP_3P: 3, FP_3M: 3, FP_4PP: 4, FP_4PM: 4, FP_4MM: 4, FP_3E: 3}
 FP_MAX_T = 8
 FP_MAX_LISTS = 8
+FP_NOALLOC_BYTES = 128 << 20
 
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
            "fp_rates4_fused", "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
            "fp_enumerate_count", "fp_enumerate_fill", "fp_set_broadening", "fp_rates_streamed", "fp_fused_counts",
-           "fp_ifc_info"]
+           "fp_ifc_info", "fp_rates4_noalloc"]
 
 
 class FpError(RuntimeError):
@@ -87,7 +88,7 @@ def lib():
         L.fp_last_error.restype = ctypes.c_char_p
         L.fp_load_modes.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, dbl]
         L.fp_load_ifc.argtypes = [vp, i32, i64, vp, vp, vp, i32, vp]
-        for f in (L.fp_rates3, L.fp_rates4):
+        for f in (L.fp_rates3, L.fp_rates4, L.fp_rates4_noalloc):
             f.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp]
         L.fp_rates4_fused.argtypes = [vp, i64, vp, i32, i32, vp, dbl, dbl, i32, vp, vp, vp, vp]
         L.fp_fused_counts.argtypes = [vp, vp, vp]
@@ -234,6 +235,11 @@ def fp_rates3(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=No
 
 def fp_rates4(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=None, stream=None):
     _rates(lib().fp_rates4, ctx, lists, T, sigma, precision, gamma_out, wp_out, stream)
+
+
+def fp_rates4_noalloc(ctx, lists, T, sigma, precision=FP_FP64, gamma_out=None, wp_out=None, stream=None):
+    """fp_rates4 with every per-call table in the library's fixed workspace (no allocation)."""
+    _rates(lib().fp_rates4_noalloc, ctx, lists, T, sigma, precision, gamma_out, wp_out, stream)
 
 
 def fp_rates4_fused(ctx, row_mode, type_mask, T, sigma, nsigma, precision=FP_FP64, gamma_out=None, wp_out=None,
