@@ -50,8 +50,9 @@
  * the 3- rate of g'' (weight 1/2 if g' == g), each with its own occupations
  * and Gaussian.  With every active mode of the mesh as a row, FP_3E lists give
  * the Gamma and WP of FP_3P + FP_3M lists over all modes from a third of the
- * matrix elements.  The contributions to g' and g'' are added with device
- * atomics (their rounding depends on timing).  Fixed width only (not with an
+ * matrix elements.  The contributions to g' and g'' are kept per record and
+ * added per mode after the row sums, in the order of a stable sort by mode, so
+ * the result does not depend on timing.  Fixed width only (not with an
  * adaptive fp_broadening); not accepted by fp_rates_backward.
  * Rates (FP_3P/FP_3M: prefactor pi hbar/(4N), ordered-sum weights 1, 1/2;
  * 4ph: pi hbar^2/(8N^2), weights 1/2, 1/2, 1/6; N = N0*N1*N2):

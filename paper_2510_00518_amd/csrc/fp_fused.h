@@ -473,6 +473,9 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
             double w1[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) w1[j] = omega[iq1 * NB + j];
+            double w1max = w1[0];
+#pragma unroll
+            for (int j = 1; j < NB; ++j) w1max = fmax(w1max, w1[j]);
             double pm1[3] = {0.0, 0.0, 0.0};
             if (ADAPT) fused_proj_max(f.vel, iq1, f, geo, pm1);
             // The folded table of the FP64 forms is built at the unit's first
@@ -561,16 +564,35 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                         fused_proj_max(f.vel, iq3, f, geo, pm3);
                         cut_q = fused_cut_bound(pm1, pm2, pm3, f);
                     }
+                    // Frequency bounds: every mismatch of this lane with branch j1 lies in
+                    // [d1 + lo2 + lo3, d1 + hi2 + hi3] (lo_r, hi_r: the extremes of s_r w_r
+                    // over the branches), up to rounding far below `marg`.  A block of
+                    // candidates whose interval misses [-cut, cut] keeps nothing, so the
+                    // wave skips it when none of its lanes can keep one.
+                    double mn2 = w2[0], mx2 = w2[0], mn3 = w3[0], mx3 = w3[0];
+#pragma unroll
+                    for (int j = 1; j < NB; ++j) {
+                        mn2 = fmin(mn2, w2[j]);
+                        mx2 = fmax(mx2, w2[j]);
+                        mn3 = fmin(mn3, w3[j]);
+                        mx3 = fmax(mx3, w3[j]);
+                    }
+                    const double lo2 = s2 > 0 ? mn2 : -mx2, hi2 = s2 > 0 ? mx2 : -mn2;
+                    const double lo3 = s3 > 0 ? mn3 : -mx3, hi3 = s3 > 0 ? mx3 : -mn3;
+                    const double marg = 1e-9 * (w0 + w1max + mx2 + mx3);
+                    const double cmax = (ADAPT ? cut_q : f.cut) + marg;
 #pragma unroll
                     for (int j1 = 0; j1 < NB; ++j1) {
                         const int32_t g1 = iq1 * NB + j1;
                         const bool ok1 = w1[j1] >= f.floor_;
                         const double d1 = s1 > 0 ? w0 + w1[j1] : w0 - w1[j1];
+                        if (!__ballot(ok1 && d1 + lo2 + lo3 <= cmax && d1 + hi2 + hi3 >= -cmax)) continue;
 #pragma unroll
                         for (int j2 = 0; j2 < NB; ++j2) {
                             const int32_t g2 = iq2 * NB + j2;
                             const bool ok2 = ok1 && !(tri12 && g2 < g1) && w2[j2] >= f.floor_;
                             const double d2 = s2 > 0 ? d1 + w2[j2] : d1 - w2[j2];
+                            if (!__ballot(ok2 && d2 + lo3 <= cmax && d2 + hi3 >= -cmax)) continue;
 #pragma unroll
                             for (int j3 = 0; j3 < NB; ++j3) {
                                 const int32_t g3 = iq3 * NB + j3;

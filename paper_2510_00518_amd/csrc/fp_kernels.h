@@ -311,11 +311,15 @@ struct RatesArgs {
     int32_t ppl;  // records per lane per unit
     ModeGeom geo;
     Broad br;
-    // three-phonon event lists: the contributions to the partner modes are added
-    // straight into the outputs, scaled by the final prefactors
+    // three-phonon event lists: the contributions of each record to its two
+    // partner modes, scaled by the final prefactors, go to ev_val[(2 rec + slot)
+    // * 2 n_T + {it, n_T + it}] with the target mode in ev_key[2 rec + slot]
+    // (slot 0: the 3+ partner, slot 1: the 3- product; 0x7FFFFFFF for none),
+    // rec being the record's index among all records of the call; k_event_reduce
+    // adds them per mode in a fixed order
     double pref, wpref;
-    double* gamma_out;
-    double* wp_out;
+    double* ev_val;
+    int32_t* ev_key;
 };
 
 // Pointers travel as separate restrict-qualified arguments so that the compiler
@@ -707,10 +711,14 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
                     }
                 }
 
-                // ---- three-phonon events: one matrix element for all three modes
+                // ---- three-phonon events: one matrix element for all three modes;
+                // the partners' rates go to the call's event buffers (k_event_reduce)
                 if (M == 3 && type == 5) {
 #pragma unroll
                     for (int i = 0; i < NP; ++i) {
+                        const int idx = (p0 + i) * kWave + lane;
+                        if (!(idx < count && p0 + i < a.ppl)) continue;
+                        const int64_t rg = ri.hbase + ud.start + idx;  // record index in the call
                         const double V2 = V[i].x * V[i].x + V[i].y * V[i].y;
                         const int32_t gb = pr[i].g1, gc = pr[i].gl;
                         const double wb = omega[gb], wc = omega[gc];
@@ -718,29 +726,29 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_rates(FP_RATES_PARAMS) {
                         const double dm = (wc - w0) - wb;
                         const double bm = (gb == g0 ? 0.5 : 1.0) * exp(-(dm * dm) * a.br.inv_sigma2) * a.br.gnorm /
                                           (w0 * wb * wc);
+                        const bool to_b = (evf[i] & 1u) && gb != g0, to_c = (evf[i] & 2u) != 0u;
+                        double* vb = a.ev_val + (2 * rg) * (2 * a.n_T);
+                        double* vc = vb + 2 * a.n_T;
 #pragma unroll
                         for (int it = 0; it < MAXT; ++it) {
-                            if (it < a.n_T && evf[i] != 0u) {
+                            if (it < a.n_T) {
                                 const double* n = occ + (int64_t)it * a.n_modes;
                                 const double na = n[g0], nb_ = n[gb], nc = n[gc];
-                                const int64_t o = (int64_t)it * a.n_modes;
                                 if (evf[i] & 1u) {
                                     const double xa = pr[i].base * (nb_ - nc);
                                     accw[it] += xa;
                                     accg[it] += xa * V2;
-                                    if (gb != g0) {
-                                        const double xb = pr[i].base * (na - nc);
-                                        if (a.gamma_out) atomicAdd(a.gamma_out + o + gb, a.pref * xb * V2);
-                                        if (a.wp_out) atomicAdd(a.wp_out + o + gb, a.wpref * xb);
-                                    }
                                 }
-                                if (evf[i] & 2u) {
-                                    const double xc = bm * (1.0 + na + nb_);
-                                    if (a.gamma_out) atomicAdd(a.gamma_out + o + gc, a.pref * xc * V2);
-                                    if (a.wp_out) atomicAdd(a.wp_out + o + gc, a.wpref * xc);
-                                }
+                                const double xb = pr[i].base * (na - nc);
+                                const double xc = bm * (1.0 + na + nb_);
+                                vb[it] = to_b ? a.pref * xb * V2 : 0.0;
+                                vb[a.n_T + it] = to_b ? a.wpref * xb : 0.0;
+                                vc[it] = to_c ? a.pref * xc * V2 : 0.0;
+                                vc[a.n_T + it] = to_c ? a.wpref * xc : 0.0;
                             }
                         }
+                        a.ev_key[2 * rg] = to_b ? gb : 0x7FFFFFFF;
+                        a.ev_key[2 * rg + 1] = to_c ? gc : 0x7FFFFFFF;
                     }
                     continue;
                 }
@@ -815,6 +823,45 @@ __global__ void k_finalize(const double* __restrict__ partial, const int64_t* __
             }
         }
         __syncthreads();
+    }
+}
+
+// k_fill for int32
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_iota_i32(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+// Event contributions to the partner modes, added per mode in the order of the
+// stably sorted (mode, entry) pairs: deterministic, whatever the timing of the
+// rate kernel.  keys are sorted, idx the entries (2 rec + slot) in that order.
+__global__ void k_event_reduce(const int32_t* __restrict__ keys, const int32_t* __restrict__ idx, int64_t n,
+                               const double* __restrict__ val, int32_t n_T, double* __restrict__ gamma_out,
+                               double* __restrict__ wp_out, int64_t n_modes) {
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < n_modes;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = n;  // first key >= m
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < m) lo = mid + 1; else hi = mid;
+        }
+        for (int it = 0; it < n_T; ++it) {
+            double sg = 0.0, sw = 0.0;
+            for (int64_t k = lo; k < n && keys[k] == m; ++k) {
+                const double* v = val + (int64_t)idx[k] * (2 * n_T);
+                sg += v[it];
+                sw += v[n_T + it];
+            }
+            if (lo < n && keys[lo] == m) {
+                if (gamma_out) gamma_out[(int64_t)it * n_modes + m] += sg;
+                if (wp_out) wp_out[(int64_t)it * n_modes + m] += sw;
+            }
+        }
     }
 }
 

@@ -1,6 +1,7 @@
 // libfp host runtime: context, loaders, launches of the rate kernels.
 // Every entry point of include/fp.h except the host enumerator lives here.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <array>
@@ -194,6 +195,9 @@ struct fp_ctx {
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
     DevBuf<double2> fold;     // fused FP64 path: one folded force-constant table per wave
+    DevBuf<double> ev_val;    // three-phonon events: partner contributions per record
+    DevBuf<int32_t> ev_key[2], ev_idx[2];  // their target modes and entries, unsorted and sorted
+    DevBuf<unsigned char> ev_tmp;          // radix-sort workspace
     DevBuf<int64_t> unit_kept;  // fused enumeration: kept records per unit
     DevBuf<int64_t> unit_tup;   // fused enumeration: tuples with a kept record per unit
     DevBuf<int64_t> fused_cnt;  // last fused call: processes, tuples
@@ -327,7 +331,9 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
     c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release();
-    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release(); c->unit_kept.release();
+    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release();
+    c->ev_val.release(); c->ev_key[0].release(); c->ev_key[1].release(); c->ev_idx[0].release();
+    c->ev_idx[1].release(); c->ev_tmp.release(); c->unit_kept.release();
     c->unit_tup.release(); c->fused_cnt.release();
     c->slot[0].release(); c->slot[1].release();
     if (c->flag) (void)hipFree(c->flag);
@@ -1020,8 +1026,27 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     a.br = make_broad(c, sigma);
     a.pref = rate_prefactor(c, m);
     a.wpref = m == 3 ? 1.0 / (double)c->nq : 1.0 / ((double)c->nq * (double)c->nq);
-    a.gamma_out = gamma_out;
-    a.wp_out = wp_out;
+    a.ev_val = nullptr;
+    a.ev_key = nullptr;
+    // three-phonon event lists: per-record partner contributions, reduced per mode
+    // in a fixed order after the row sums (k_event_reduce)
+    bool events = false;
+    int64_t n_all = 0;  // records of the call
+    for (int l : sel) {
+        events = events || lists[l].type == FP_3E;
+        n_all += lists[l].n_rec;
+    }
+    if (events) {
+        HIP_TRY(c, c->ev_val.ensure((size_t)std::max<int64_t>(2 * n_all * 2 * n_T, 1)));
+        for (int i = 0; i < 2; ++i) {
+            HIP_TRY(c, c->ev_key[i].ensure((size_t)std::max<int64_t>(2 * n_all, 1)));
+            HIP_TRY(c, c->ev_idx[i].ensure((size_t)std::max<int64_t>(2 * n_all, 1)));
+        }
+        hipLaunchKernelGGL(fpk::k_fill_i32, dim3(grid_for(2 * n_all)), dim3(256), 0, st, c->ev_key[0].p, 2 * n_all,
+                           (int32_t)0x7FFFFFFF);
+        a.ev_val = c->ev_val.p;
+        a.ev_key = c->ev_key[0].p;
+    }
     const int tsel = n_T == 1 ? 1 : (n_T <= 4 ? 4 : 8);
     if (mixed) {
         const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
@@ -1055,6 +1080,20 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
         hipLaunchKernelGGL(fpk::k_finalize, dim3((unsigned)pp.la.l[k].n_rows), dim3(fpk::kBlock), 0, st,
                            c->partial.p, c->unit_off.p, c->rows.p, pp.la.l[k].row_base, n_T, pref, wpref, gamma_out,
                            wp_out, nm);
+    }
+    if (events && n_all > 0) {
+        // stable sort of (target mode, entry) pairs, then one ordered sum per mode
+        const int n = (int)(2 * n_all);
+        if (2 * n_all > INT32_MAX) return fail(c, FP_ERR_UNSUPPORTED, "too many event records");
+        hipLaunchKernelGGL(fpk::k_iota_i32, dim3(grid_for(n)), dim3(256), 0, st, c->ev_idx[0].p, (int64_t)n);
+        size_t bytes = 0;
+        HIP_TRY(c, hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, c->ev_key[0].p, c->ev_key[1].p, c->ev_idx[0].p,
+                                                      c->ev_idx[1].p, n, 0, 32, st));
+        HIP_TRY(c, c->ev_tmp.ensure(std::max<size_t>(bytes, 1)));
+        HIP_TRY(c, hipcub::DeviceRadixSort::SortPairs(c->ev_tmp.p, bytes, c->ev_key[0].p, c->ev_key[1].p,
+                                                      c->ev_idx[0].p, c->ev_idx[1].p, n, 0, 32, st));
+        hipLaunchKernelGGL(fpk::k_event_reduce, dim3(grid_for(nm)), dim3(256), 0, st, c->ev_key[1].p, c->ev_idx[1].p,
+                           (int64_t)n, c->ev_val.p, n_T, gamma_out, wp_out, nm);
     }
     HIP_TRY(c, hipGetLastError());
     if (c->validate) return fp_check(c, stream);

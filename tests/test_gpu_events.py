@@ -5,7 +5,8 @@ Parity: with every mode of a small mesh as a row, the rates and WP equal the
 oracle's list-mode sums over its own FP_3P and FP_3M enumerations per mode
 within 1e-10 (one and five temperatures); on the 4^3 all-modes workload and a
 12^3 all-modes mesh they equal the per-mode list path within 1e-12 while
-evaluating about a third of the matrix elements.
+evaluating about a third of the matrix elements; repeated calls agree bit for
+bit (the partners' contributions are reduced per mode in a fixed order).
 """
 import sys
 import time
@@ -96,6 +97,36 @@ def test_events_match_per_mode_path(ctx, name):
     say(f"{name}: per-mode {n_pm} processes ({t0 * 1e3:.2f} ms), events {n_ev} ({t1 * 1e3:.2f} ms)")
     assert_parity(g1, g0, f"{name} Gamma3 events vs per-mode", rtol=1e-12)
     assert_parity(w1, w0, f"{name} WP3 events vs per-mode", rtol=1e-12)
+
+
+def test_events_deterministic(ctx):
+    """The partners' contributions are summed per mode in a fixed order: repeated
+    calls give the same bits (a 12^3 all-modes mesh, 3 temperatures, events
+    split over several lists so that modes receive contributions from many
+    units and lists)."""
+    from paper_2510_00518_amd.driver import RatePath
+    cfg = small_config(12)
+    rows = row_modes(cfg)
+    T = [300.0, 600.0, 900.0]
+    parts = np.array_split(rows, 3)
+    lists = [fp.enumerate_list(fp.FP_3E, cfg, row_mode=r) for r in parts]
+    import torch
+    dev = torch.device("cuda", 0)
+    pls = [fp.PList.from_host(fp.FP_3E, rm, off, rec, dev) for rm, off, rec in lists]
+    p = RatePath(cfg, ctx=ctx)
+    p.load_ifc(phi3=p.phi3)
+    out = []
+    for rep in range(3):
+        gam, wp = p.outputs(len(T))
+        fp.fp_rates3(ctx, pls, T, cfg["sigma"], fp.FP_FP64, gam, wp)
+        fp.fp_check(ctx)
+        torch.cuda.synchronize()
+        out.append((gam.cpu().numpy(), wp.cpu().numpy()))
+    say(f"events 12^3 in {len(pls)} lists, {sum(pl.n_rec for pl in pls)} records: three calls")
+    assert np.abs(out[0][0]).max() > 0
+    for g, w in out[1:]:
+        np.testing.assert_array_equal(g, out[0][0])
+        np.testing.assert_array_equal(w, out[0][1])
 
 
 def test_events_unsupported_paths(ctx):
