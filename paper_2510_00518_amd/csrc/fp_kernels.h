@@ -59,6 +59,7 @@ struct ListArg {
     int32_t type;
     int32_t pad;
     int64_t n_rows, row_base, n_rec, rec_base;
+    int64_t rec_shift;  // subtracted from row_off (a row range of a longer list; rec already shifted)
     const int32_t* row_mode;
     const int64_t* row_off;
     const uint64_t* rec;
@@ -144,7 +145,7 @@ __global__ void k_rows(ListsArg la, int64_t n_modes, int64_t unit, RowInfo* __re
         while (l + 1 < la.n_lists && gr >= la.l[l + 1].row_base) ++l;
         const ListArg& L = la.l[l];
         const int64_t r = gr - L.row_base;
-        int64_t beg = L.row_off[r], end = L.row_off[r + 1];
+        int64_t beg = L.row_off[r] - L.rec_shift, end = L.row_off[r + 1] - L.rec_shift;
         int32_t mode = L.row_mode[r];
         bool ok = beg >= 0 && end >= beg && end <= L.n_rec && mode >= 0 && mode < n_modes;
         if (!ok) {

@@ -208,6 +208,7 @@ struct fp_ctx {
     int32_t blocks_per_cu = 0;  // 0: as many resident blocks as the kernel's occupancy allows
     int32_t variant = 6;        // order-4 contraction form: 0-3 per-process (k_rates), 4-7 tuple-batched
     int32_t grad_chunk = 8192;  // records per adjoint chunk (a multiple of 256)
+    int64_t grad_records = int64_t(1) << 24;  // records per order-4 adjoint pass (bounds the h buffer)
     int32_t fused_form = 2;     // FP64 form of fp_rates4_fused: 0 B-keys, 2 first partner folded
     // kernel timing
     bool profile = false;
@@ -361,6 +362,9 @@ extern "C" fp_status fp_set_knob(fp_ctx* c, const char* name, int64_t value) {
     } else if (!strcmp(name, "variant")) {
         if (value < 0 || value > 7) return fail(c, FP_ERR_ARG, "variant must be in [0, 7]");
         c->variant = (int32_t)value;
+    } else if (!strcmp(name, "grad_records")) {
+        if (value < 1024 || value > (int64_t(1) << 34)) return fail(c, FP_ERR_ARG, "grad_records: 1024..2^34");
+        c->grad_records = value;
     } else if (!strcmp(name, "fused_form")) {
         if (value != 0 && value != 2) return fail(c, FP_ERR_ARG, "fused_form must be 0 or 2");
         c->fused_form = (int32_t)value;
@@ -382,6 +386,8 @@ extern "C" fp_status fp_get_knob(fp_ctx* c, const char* name, int64_t* value) {
         *value = c->variant;
     else if (!strcmp(name, "fused_form"))
         *value = c->fused_form;
+    else if (!strcmp(name, "grad_records"))
+        *value = c->grad_records;
     else
         return fail(c, FP_ERR_ARG, "unknown knob %s", name);
     return FP_OK;
@@ -894,7 +900,8 @@ struct Prepared {
 // table, row table, work units of `unit` records, and the pre-contracted
 // force constants of every row.
 fp_status prepare(fp_ctx* c, int m, const fp_plist* lists, const std::vector<int>& sel, int32_t n_T,
-                  const double* T_K, int64_t unit, hipStream_t st, Prepared* pp) {
+                  const double* T_K, int64_t unit, hipStream_t st, Prepared* pp,
+                  const std::vector<int64_t>* rec_shift = nullptr) {
     IfcState& S = c->ifc[m - 3];
     fpk::ListsArg& la = pp->la;
     memset(&la, 0, sizeof la);
@@ -911,6 +918,7 @@ fp_status prepare(fp_ctx* c, int m, const fp_plist* lists, const std::vector<int
         la.l[k].row_mode = P.row_mode;
         la.l[k].row_off = P.row_off;
         la.l[k].rec = P.rec;
+        la.l[k].rec_shift = rec_shift ? (*rec_shift)[k] : 0;
         total_rows += P.n_rows;
         n_units += (P.n_rec + unit - 1) / unit + P.n_rows;
     }
@@ -1562,60 +1570,116 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
         if (ts != FP_OK) return ts;
         Prepared pp;
         fp_status ps;
-        if (m == 4 && n_rec > 0) {
-            // first half: h_p = c_p conj(V_p) for every record (tuple-batched, units of
-            // 128 records, FP64 or mixed precision)
-            ps = prepare(c, m, lists, sel, n_T, T_K, fpk::kBR * fpk::kWave, st, &pp);
-            if (ps != FP_OK) return ps;
-            HIP_TRY(c, c->hbuf.ensure((size_t)n_rec));
-            fpk::RatesArgs ra;
-            memset(&ra, 0, sizeof ra);
-            ra.n_units = pp.n_units;
-            ra.n_modes = c->n_modes;
-            ra.n_keys = (int32_t)S.n_keys;
-            ra.n_groups = S.n_groups;
-            ra.n_T = n_T;
-            ra.ppl = fpk::kBR;
-            ra.geo = pp.geo;
-            ra.br = make_broad(c, sigma);
-            const double pref4 = rate_prefactor(c, m);
-            if (mixed) {
-                const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
-                HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
-                hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, pp.total_rows, c->phit.p,
-                                   S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_keys, c->fsp.p);
-                ps = tsel == 1 ? launch_mixed_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
-                               : (tsel == 4 ? launch_mixed_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
-                                            : launch_mixed_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
-            } else {
-                ps = tsel == 1 ? launch_batched_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
-                               : (tsel == 4 ? launch_batched_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
-                                            : launch_batched_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
-            }
-            if (ps != FP_OK) return ps;
-        }
-        ps = prepare(c, m, lists, sel, n_T, T_K, c->grad_chunk, st, &pp);
-        if (ps != FP_OK) return ps;
         fpk::GradArgs a;
         memset(&a, 0, sizeof a);
-        a.n_units = pp.n_units;
         a.n_modes = c->n_modes;
         a.n_terms = (int32_t)S.n_terms;
         a.n_keys = (int32_t)S.n_keys;
         a.n_groups = S.n_groups;
         a.n_pairs = S.n_pairs;
         a.n_T = n_T;
-        a.geo = pp.geo;
         a.br = make_broad(c, sigma);
         a.pref = rate_prefactor(c, m);
-        fp_status ls;
-        if (m == 3)
-            ls = tsel == 1 ? launch_grad_p<3, 1>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
-                           : (tsel == 4 ? launch_grad_p<3, 4>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
-                                        : launch_grad_p<3, 8>(c, st, pp, a, S, dL_dgamma, dphi, accumulate));
-        else
-            ls = launch_grad4t(c, st, pp, a, S, dphi, accumulate);
-        if (ls != FP_OK) return ls;
+        if (m == 4 && n_rec > 0) {
+            // Row ranges of at most grad_records records (a longer row alone) are
+            // taken one after another, so the h buffer of the first pass holds one
+            // range, not the whole call: pass 1 writes h_p = c_p conj(V_p) per record
+            // of the range (tuple-batched, units of 128 records, FP64 or mixed), pass
+            // 2 turns it into dL/dPhi, added over the ranges in order.
+            std::vector<std::vector<int64_t>> offs(sel.size());
+            for (size_t k = 0; k < sel.size(); ++k) {
+                const fp_plist& P = lists[sel[k]];
+                offs[k].resize((size_t)P.n_rows + 1);
+                HIP_TRY(c, hipMemcpyAsync(offs[k].data(), P.row_off, offs[k].size() * 8, hipMemcpyDeviceToHost, st));
+            }
+            HIP_TRY(c, hipStreamSynchronize(st));
+            struct Piece { size_t k; int64_t r0, r1; };
+            std::vector<std::vector<Piece>> ranges(1);
+            int64_t cur = 0;
+            for (size_t k = 0; k < sel.size(); ++k)
+                for (int64_t r = 0; r < lists[sel[k]].n_rows; ++r) {
+                    const int64_t nr = offs[k][(size_t)r + 1] - offs[k][(size_t)r];
+                    if (nr < 0 || offs[k][(size_t)r] < 0 || offs[k][(size_t)r + 1] > lists[sel[k]].n_rec)
+                        return fail(c, FP_ERR_ARG, "list %d: bad row offsets", sel[k]);
+                    if (cur > 0 && cur + nr > c->grad_records) {
+                        ranges.emplace_back();
+                        cur = 0;
+                    }
+                    auto& rg = ranges.back();
+                    if (!rg.empty() && rg.back().k == k && rg.back().r1 == r)
+                        rg.back().r1 = r + 1;
+                    else
+                        rg.push_back({k, r, r + 1});
+                    cur += nr;
+                }
+            const double pref4 = rate_prefactor(c, m);
+            for (size_t ri = 0; ri < ranges.size(); ++ri) {
+                std::vector<fp_plist> sub;
+                std::vector<int64_t> shift;
+                std::vector<int> all;
+                int64_t n_sub = 0;
+                for (const Piece& pc : ranges[ri]) {
+                    const fp_plist& P = lists[sel[pc.k]];
+                    const int64_t b0 = offs[pc.k][(size_t)pc.r0], b1 = offs[pc.k][(size_t)pc.r1];
+                    fp_plist q = P;
+                    q.n_rows = pc.r1 - pc.r0;
+                    q.n_rec = b1 - b0;
+                    q.row_mode = P.row_mode + pc.r0;
+                    q.row_off = P.row_off + pc.r0;
+                    q.rec = P.rec + b0;
+                    all.push_back((int)sub.size());
+                    sub.push_back(q);
+                    shift.push_back(b0);
+                    n_sub += b1 - b0;
+                }
+                ps = prepare(c, m, sub.data(), all, n_T, T_K, fpk::kBR * fpk::kWave, st, &pp, &shift);
+                if (ps != FP_OK) return ps;
+                HIP_TRY(c, c->hbuf.ensure((size_t)std::max<int64_t>(n_sub, 1)));
+                fpk::RatesArgs ra;
+                memset(&ra, 0, sizeof ra);
+                ra.n_units = pp.n_units;
+                ra.n_modes = c->n_modes;
+                ra.n_keys = (int32_t)S.n_keys;
+                ra.n_groups = S.n_groups;
+                ra.n_T = n_T;
+                ra.ppl = fpk::kBR;
+                ra.geo = pp.geo;
+                ra.br = make_broad(c, sigma);
+                if (mixed) {
+                    const int64_t nf = pp.total_rows * S.n_kblk * 4 * fpk::kWave;
+                    HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
+                    hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, pp.total_rows,
+                                       c->phit.p, S.groups.p, S.kblk.p, S.n_kblk, (int32_t)S.n_keys, c->fsp.p);
+                    ps = tsel == 1 ? launch_mixed_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                                   : (tsel == 4 ? launch_mixed_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                                                : launch_mixed_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
+                } else {
+                    ps = tsel == 1 ? launch_batched_h<1>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                                   : (tsel == 4 ? launch_batched_h<4>(c, st, pp.n_units, ra, S, dL_dgamma, pref4)
+                                                : launch_batched_h<8>(c, st, pp.n_units, ra, S, dL_dgamma, pref4));
+                }
+                if (ps != FP_OK) return ps;
+                ps = prepare(c, m, sub.data(), all, n_T, T_K, c->grad_chunk, st, &pp, &shift);
+                if (ps != FP_OK) return ps;
+                a.n_units = pp.n_units;
+                a.geo = pp.geo;
+                fp_status ls = launch_grad4t(c, st, pp, a, S, dphi, accumulate || ri > 0);
+                if (ls != FP_OK) return ls;
+            }
+        } else {
+            ps = prepare(c, m, lists, sel, n_T, T_K, c->grad_chunk, st, &pp);
+            if (ps != FP_OK) return ps;
+            a.n_units = pp.n_units;
+            a.geo = pp.geo;
+            fp_status ls;
+            if (m == 3)
+                ls = tsel == 1 ? launch_grad_p<3, 1>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
+                               : (tsel == 4 ? launch_grad_p<3, 4>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
+                                            : launch_grad_p<3, 8>(c, st, pp, a, S, dL_dgamma, dphi, accumulate));
+            else
+                ls = launch_grad4t(c, st, pp, a, S, dphi, accumulate);
+            if (ls != FP_OK) return ls;
+        }
         ts = timer_stop(c, st, 10 + m, ev0, ev1);
         if (ts != FP_OK) return ts;
     }

@@ -121,6 +121,27 @@ def test_backward_mixed_precision(ctx, cell):
     assert_grad(g4, o4, f"mixed-precision dPhi4 ({cell})", rtol=1e-4, floor_rel=1e-3)
 
 
+def test_backward_record_ranges(ctx):
+    """The order-4 adjoint takes the lists in row ranges of at most grad_records
+    records (the h buffer holds one range): many small ranges give the oracle's
+    gradient and the single-range result up to the grouping of the sums."""
+    cfg = dict(small_config(3), sigma=2.0)
+    rows = row_modes(cfg)[::2]
+    lists = oracle_lists(cfg, (fp.FP_4PP, fp.FP_4PM, fp.FP_4MM), rows, 2.0)
+    n = sum(int(v[1][-1]) for v in lists.values())
+    T = [300.0, 900.0]
+    dLdG = np.random.default_rng(6).uniform(0.5, 1.5, size=(len(T), cfg["omega"].size))
+    _, one = gpu_grad(ctx, cfg, lists, T, dLdG)
+    with knob_util.knobs(ctx, grad_records=1024):
+        _, many = gpu_grad(ctx, cfg, lists, T, dLdG)
+    _, o = oracle_grad(cfg, lists, T, dLdG)
+    say(f"  {n} records in ranges of <= 1024 records (longer rows alone)")
+    assert n > 8 * 1024
+    assert_grad(many, o, "dPhi4 in small ranges")
+    scale = np.abs(one).max()
+    np.testing.assert_allclose(many, one, rtol=1e-12, atol=1e-13 * scale)
+
+
 def test_backward_chunking_and_passes(ctx):
     """Chunk sizes change only the summation grouping; the 8-atom cell has more
     adjoint tiles than one pass holds."""
