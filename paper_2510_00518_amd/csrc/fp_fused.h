@@ -43,6 +43,8 @@ struct FusedArgs {
     // sigma); a candidate with cut < |Delta| <= cut_max has its width evaluated
     // exactly as the host enumerator does
     const double* vel;
+    const double* proj;      // the per-mode table (proj_0, proj_1, proj_2, omega)
+    const double* proj_max;  // per q-point: the largest |proj_d| over its branches
     double recip[9];
     double factor, sigma, nsigma, cut_max;
     // bound on |norm of the nine pair projections from the per-mode table P
@@ -69,21 +71,6 @@ __device__ inline double fused_pair_sq(double s2, const double* __restrict__ vel
         s2 = s2 + p * p;
     }
     return s2;
-}
-
-// max over the branches of one q-point of |v . b_d| / N_d, d = 0, 1, 2: bounds
-// the pair projections of the adaptive width from above
-__device__ inline void fused_proj_max(const double* __restrict__ vel, int32_t iq, const FusedArgs& f,
-                                      const ModeGeom& geo, double (&pm)[3]) {
-    const double n[3] = {(double)geo.N0, (double)geo.N1, (double)geo.N2};
-    pm[0] = pm[1] = pm[2] = 0.0;
-#pragma unroll
-    for (int j = 0; j < kFusedNb; ++j) {
-        const double* v = vel + ((int64_t)iq * kFusedNb + j) * 3;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            pm[d] = fmax(pm[d], fabs(v[0] * f.recip[d * 3] + v[1] * f.recip[d * 3 + 1] + v[2] * f.recip[d * 3 + 2]) / n[d]);
-    }
 }
 
 // Largest nsigma * sigma_p any branch triple of the q-points with projection
@@ -160,6 +147,73 @@ __device__ inline void tbx_fold(double2* sF, int32_t n_pkeys, const double2* __r
     }
 }
 
+// One record of the form-2 batch: the three partner modes and the branch of the
+// first partner (g1 = g0 for a slot without a record).
+struct XProc {
+    int32_t g1, g2, gl, jp;
+};
+
+// Form-2 records, written by the fused filter: j1 | j2 << 3 | j3 << 6 |
+// iq2 << 9 | iq3 << 33, with q' the unit's (iq1) and the last partner's q-point
+// iq3 already closed by momentum, so no index division is left here.
+__device__ inline XProc tbx_decode(bool have, uint64_t rec, int32_t g0, int32_t iq1) {
+    XProc p;
+    p.g1 = p.g2 = p.gl = g0;
+    p.jp = 0;
+    if (!have) return p;
+    const int j1 = (int)(rec & 7u), j2 = (int)((rec >> 3) & 7u), j3 = (int)((rec >> 6) & 7u);
+    const int32_t iq2 = (int32_t)((rec >> 9) & 0xFFFFFFu), iq3 = (int32_t)((rec >> 33) & 0xFFFFFFu);
+    p.g1 = iq1 * kFusedNb + j1;
+    p.g2 = iq2 * kFusedNb + j2;
+    p.gl = iq3 * kFusedNb + j3;
+    p.jp = j1;
+    return p;
+}
+
+// The weight factor w G(Delta) / prod(omega) of a decoded record (w the
+// triangle weight, G the Gaussian of the call's or the adaptive width), formed
+// after the contraction so that it holds no registers there; the mismatch, the
+// product of frequencies and the width follow setup_proc's operation order.
+__device__ inline double tbx_weight(const XProc& p, int type, int s1, int s2, int s3, double w0,
+                                    const double* __restrict__ omega, const Broad& br) {
+    Proj4 P1, P2, Pl;
+    double w1, w2, wl;
+    if (br.proj) {  // the adaptive width's table rows carry the frequencies too
+        P1 = ld_proj4(br.proj, p.g1);
+        P2 = ld_proj4(br.proj, p.g2);
+        Pl = ld_proj4(br.proj, p.gl);
+        w1 = P1.b.y;
+        w2 = P2.b.y;
+        wl = Pl.b.y;
+    } else {
+        w1 = omega[p.g1];
+        w2 = omega[p.g2];
+        wl = omega[p.gl];
+    }
+    double delta = s1 > 0 ? w0 + w1 : w0 - w1;
+    delta = s2 > 0 ? delta + w2 : delta - w2;
+    delta = s3 > 0 ? delta + wl : delta - wl;
+    double wprod = w0 * w1 * w2;
+    wprod *= wl;
+    double wt = 1.0;
+    if (type == 2) {
+        if (p.g1 == p.g2) wt = 0.5;
+    } else if (type == 3) {
+        if (p.g2 == p.gl) wt = 0.5;
+    } else {
+        const int eq = (p.g1 == p.g2) + (p.g2 == p.gl) + (p.g1 == p.gl);
+        wt = eq == 3 ? (1.0 / 6.0) : (eq >= 1 ? 0.5 : 1.0);
+    }
+    double inv_sigma2 = br.inv_sigma2, gnorm = br.gnorm;
+    if (br.proj) {
+        const double s2q = proj_sq4(P1, P2) + proj_sq4(P1, Pl) + proj_sq4(P2, Pl);
+        const double sig = fmax(br.factor * sqrt(s2q * (1.0 / 9.0)), br.floor_);
+        inv_sigma2 = 1.0 / (sig * sig);
+        gnorm = 0.56418958354775628695 / sig;  // 1/(sigma sqrt(pi))
+    }
+    return wt * exp(-(delta * delta) * inv_sigma2) * gnorm / wprod;
+}
+
 // One batch of up to 128 records of one unit (record k * 64 + lane in rec[k];
 // `count` valid), all with the unit's q': decode, find the tuples (a change of
 // q'' between consecutive records), build A_p per pair group and 16-tuple tile
@@ -167,12 +221,14 @@ __device__ inline void tbx_fold(double2* sF, int32_t n_pkeys, const double2* __r
 // weight in FP64.  ptab is the pkey table (B at [4..6]); A and Qs are this
 // wave's LDS staging.
 template <int MAXT>
-__device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t g0, int type,
-                                 const double2* sF, const double* __restrict__ omega,
-                                 const double2* __restrict__ evec, const double* __restrict__ occ,
-                                 const int32_t* __restrict__ ptab, const int32_t* __restrict__ pgroups,
-                                 int n_pgroups, int* __restrict__ flag, const RatesArgs& a, const double2* sroots,
-                                 double2 (*A)[kXM], int32_t* Qs, double (&accg)[MAXT], double (&accw)[MAXT]) {
+__device__ inline void tbx_batch(const uint64_t (&rec)[kBR], const int32_t (&qpk)[kBR], int count, int32_t g0,
+                                 int type, int32_t iq1, const double2* sF,
+                                 const double* __restrict__ omega, const double2* __restrict__ evec,
+                                 const double* __restrict__ occt, const int32_t* __restrict__ ptab,
+                                 const int32_t* __restrict__ pgroups, int n_pgroups, const RatesArgs& a,
+                                 const double2* sroots, double2 (*A)[kXM], int32_t* Qs, double (&accg)[MAXT],
+                                 double (&accw)[MAXT]) {
+    constexpr int MT = (MAXT + 1) & ~1;  // occupations per mode in occt (temperature-fastest)
     const int lane = threadIdx.x & (kWave - 1);
     const int li = lane & 15, lk = lane >> 4;
     const ModeGeom& geo = a.geo;
@@ -181,24 +237,20 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t 
     type_signs(type, s1, s2, s3);
     const double c2 = s2 > 0 ? 1.0 : -1.0;
     const double c3 = s3 > 0 ? 1.0 : -1.0;
-    const int32_t iq0 = g0 / nb;
-    const int32_t c00 = iq0 / (geo.N1 * geo.N2), c01 = (iq0 / geo.N2) % geo.N1, c02 = iq0 % geo.N2;
     const double w0 = omega[g0];
 
     // ---- records, tuple boundaries (q'' changes) and slots
-    Proc pr[kBR];
+    XProc pr[kBR];
     bool have[kBR], first[kBR];
-    int slot[kBR], jp[kBR];
+    int slot[kBR];
     int32_t prev_last = -1;
     int base = 0;
 #pragma unroll
     for (int k = 0; k < kBR; ++k) {
         const int idx = k * kWave + lane;
         have[k] = idx < count;
-        pr[k] = setup_proc<4>(have[k], rec[k], type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
-                              flag, a.br);
-        jp[k] = pr[k].g1 % nb;
-        const int32_t key = have[k] ? pr[k].g2 / nb : -2;
+        pr[k] = tbx_decode(have[k], rec[k], g0, iq1);
+        const int32_t key = have[k] ? (int32_t)((rec[k] >> 9) & 0xFFFFFFu) : -2;
         int32_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
         if (lane == 0) up = prev_last;
         first[k] = have[k] && key != up;
@@ -222,7 +274,7 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t 
 #pragma unroll
             for (int k = 0; k < kBR; ++k) {
                 const int s = slot[k] - tb;
-                if (first[k] && s >= 0 && s < kXTB) Qs[s] = pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20);
+                if (first[k] && s >= 0 && s < kXTB) Qs[s] = qpk[k];
             }
             lds_fence();
             // A_p for this tile: two passes of two M-tiles (Karatsuba, three real
@@ -283,7 +335,7 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t 
                         y[q] = ld_eps(e2 + q, c2);
                         z[q] = ld_eps(e3 + q, c3);
                     }
-                    const double2* Ar = A[s] + jp[k] * 9;
+                    const double2* Ar = A[s] + pr[k].jp * 9;
                     double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -301,23 +353,33 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], int count, int32_t 
         }
     }
 
-    // ---- weights and occupations (FP64)
+    // ---- weights and occupations (FP64); the three partners' occupations at every
+    // temperature come in 16-byte loads from the temperature-fastest table
 #pragma unroll
     for (int k = 0; k < kBR; ++k) {
         const double V2 = V[k].x * V[k].x + V[k].y * V[k].y;
+        const double base = have[k] ? tbx_weight(pr[k], type, s1, s2, s3, w0, omega, a.br) : 0.0;
+        double n1[MT], n2[MT], nl[MT];
+#pragma unroll
+        for (int it = 0; it < MT; it += 2) {
+            const double2 x1 = *reinterpret_cast<const double2*>(occt + (int64_t)pr[k].g1 * MT + it);
+            const double2 x2 = *reinterpret_cast<const double2*>(occt + (int64_t)pr[k].g2 * MT + it);
+            const double2 xl = *reinterpret_cast<const double2*>(occt + (int64_t)pr[k].gl * MT + it);
+            n1[it] = x1.x; n1[it + 1] = x1.y;
+            n2[it] = x2.x; n2[it + 1] = x2.y;
+            nl[it] = xl.x; nl[it + 1] = xl.y;
+        }
 #pragma unroll
         for (int it = 0; it < MAXT; ++it) {
             if (it < a.n_T) {
-                const double* n = occ + (int64_t)it * a.n_modes;
-                const double n1 = n[pr[k].g1], n2 = n[pr[k].g2], nl = n[pr[k].gl];
                 double oc;
                 if (type == 2)
-                    oc = n1 * n2 * (1.0 + nl) - (1.0 + n1) * (1.0 + n2) * nl;
+                    oc = n1[it] * n2[it] * (1.0 + nl[it]) - (1.0 + n1[it]) * (1.0 + n2[it]) * nl[it];
                 else if (type == 3)
-                    oc = n1 * (1.0 + n2) * (1.0 + nl) - (1.0 + n1) * n2 * nl;
+                    oc = n1[it] * (1.0 + n2[it]) * (1.0 + nl[it]) - (1.0 + n1[it]) * n2[it] * nl[it];
                 else
-                    oc = (1.0 + n1) * (1.0 + n2) * (1.0 + nl) - n1 * n2 * nl;
-                const double xw = pr[k].base * oc;
+                    oc = (1.0 + n1[it]) * (1.0 + n2[it]) * (1.0 + nl[it]) - n1[it] * n2[it] * nl[it];
+                const double xw = base * oc;
                 accw[it] += xw;
                 accg[it] += xw * V2;
             }
@@ -375,8 +437,20 @@ struct FusedTabs {
     const int32_t* plist;
     const int32_t* pgroups;
     double2* fold;
+    const double* occt;  // form 2: occupations [mode][temperature], rows padded to an even count
     int32_t n_bkeys, n_pkeys, n_pgroups, n_fold_ks;
 };
+
+// occt[g * mt + it] = occ[it * n_modes + g], zero in the padding columns it >= n_T
+__global__ void k_occ_t(const double* __restrict__ occ, int64_t n_modes, int32_t n_T, int32_t mt,
+                        double* __restrict__ occt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_modes * mt;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = i / mt;
+        const int it = (int)(i % mt);
+        occt[i] = it < n_T ? occ[(int64_t)it * n_modes + g] : 0.0;
+    }
+}
 
 // FORM 0: FP64, B-keys (tb_batch, 24-tuple batches, three blocks per CU);
 // FORM 1: mixed precision (tbm_batch: split bf16 MFMA build, FP32 contraction,
@@ -477,7 +551,8 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
 #pragma unroll
             for (int j = 1; j < NB; ++j) w1max = fmax(w1max, w1[j]);
             double pm1[3] = {0.0, 0.0, 0.0};
-            if (ADAPT) fused_proj_max(f.vel, iq1, f, geo, pm1);
+            if (ADAPT)
+                for (int d = 0; d < 3; ++d) pm1[d] = f.proj_max[(int64_t)iq1 * 4 + d];
             // The folded table of the FP64 forms is built at the unit's first
             // batch: most units of the ++ and -- types keep no process at all.
             bool folded = false;
@@ -529,8 +604,12 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
             // them) until 128 have gathered, across chunks of q''; one pass past
             // the last chunk (no candidates) evaluates the remainder
             uint64_t buf[kBR];
+            int32_t qbuf[kBR];  // form 2: each record's packed signed q'' coordinates
 #pragma unroll
-            for (int k = 0; k < kBR; ++k) buf[k] = 0;
+            for (int k = 0; k < kBR; ++k) {
+                buf[k] = 0;
+                qbuf[k] = 0;
+            }
             int pend = 0;
             int ptup = 0;  // tuples in buf (FORM 2 flushes at kXTB of them)
             // FORM 2: wave w of the block takes the chunks w, w + 4, ... of q''
@@ -542,12 +621,18 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                 const int32_t iq2 = start + lane;
                 const bool qv = iq2 < nq;
                 uint64_t m[4] = {0, 0, 0, 0};
+                int32_t iq3_l = 0, qpk_l = 0;  // this lane's last q-point and packed signed q'' (form 2)
                 if (qv) {
                     const int32_t q20 = iq2 / (N1 * N2), q21 = (iq2 / N2) % N1, q22 = iq2 % N2;
                     // s3 q''' = -(q + s1 q' + s2 q'')
                     const int32_t iq3 = (wrapn(s3 * -(q00 + s1 * q10 + s2 * q20), N0) * N1 +
                                          wrapn(s3 * -(q01 + s1 * q11 + s2 * q21), N1)) * N2 +
                                         wrapn(s3 * -(q02 + s1 * q12 + s2 * q22), N2);
+                    if (FORM == 2) {
+                        iq3_l = iq3;
+                        qpk_l = (s2 > 0 ? q20 : wrapn(-q20, N0)) | ((s2 > 0 ? q21 : wrapn(-q21, N1)) << 10) |
+                                ((s2 > 0 ? q22 : wrapn(-q22, N2)) << 20);
+                    }
                     double w2[NB], w3[NB];
 #pragma unroll
                     for (int j = 0; j < NB; ++j) {
@@ -559,9 +644,10 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                     double cut_q = f.cut;
                     uint64_t xm[4] = {0, 0, 0, 0};  // candidates that need the exact width
                     if (ADAPT) {
-                        double pm2[3], pm3[3];
-                        fused_proj_max(f.vel, iq2, f, geo, pm2);
-                        fused_proj_max(f.vel, iq3, f, geo, pm3);
+                        const double2 a2 = *reinterpret_cast<const double2*>(f.proj_max + (int64_t)iq2 * 4);
+                        const double2 a3 = *reinterpret_cast<const double2*>(f.proj_max + (int64_t)iq3 * 4);
+                        const double pm2[3] = {a2.x, a2.y, f.proj_max[(int64_t)iq2 * 4 + 2]};
+                        const double pm3[3] = {a3.x, a3.y, f.proj_max[(int64_t)iq3 * 4 + 2]};
                         cut_q = fused_cut_bound(pm1, pm2, pm3, f);
                     }
                     // Frequency bounds: every mismatch of this lane with branch j1 lies in
@@ -619,58 +705,57 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                     // formed again with the same operations in the same order, so the
                     // decision is the one the host makes.
                     if (ADAPT) {
+                        uint64_t x0 = xm[0], x1 = xm[1], x2 = xm[2], x3 = xm[3];
+                        while (x0 | x1 | x2 | x3) {
+                            int cc[2];
+                            bool cv[2];
 #pragma unroll
-                        for (int wd = 0; wd < 4; ++wd) {
-                            uint64_t xb = xm[wd];
-                            const int bit0 = xb ? __builtin_ctzll(xb) : 0;  // a real candidate, for idle slots
-                            while (xb) {
-                                int bit[2];
-                                bool cv[2];
+                            for (int k = 0; k < 2; ++k) {
+                                // lowest pending candidate over the four words (an idle
+                                // second slot repeats the first, its result unused)
+                                cv[k] = (x0 | x1 | x2 | x3) != 0;
+                                const int wd = x0 ? 0 : (x1 ? 1 : (x2 ? 2 : 3));
+                                const uint64_t cur = x0 ? x0 : (x1 ? x1 : (x2 ? x2 : x3));
+                                cc[k] = cv[k] ? wd * 64 + __builtin_ctzll(cur) : cc[0];
+                                const uint64_t nxt = cur & (cur - 1);
+                                x0 = wd == 0 ? nxt : x0;
+                                x1 = wd == 1 ? nxt : x1;
+                                x2 = wd == 2 ? nxt : x2;
+                                x3 = wd == 3 ? nxt : x3;
+                            }
+                            double ad[2], nrm[2];
+                            int32_t ga[2], gb[2], gc[2];
 #pragma unroll
-                                for (int k = 0; k < 2; ++k) {
-                                    cv[k] = xb != 0;
-                                    bit[k] = cv[k] ? __builtin_ctzll(xb) : bit0;
-                                    xb &= xb - 1;
-                                }
-                                double ad[2], nrm[2];
-                                int32_t ga[2], gb[2], gc[2];
+                            for (int k = 0; k < 2; ++k) {
+                                const int c = cc[k];
+                                const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
+                                ga[k] = iq1 * NB + j1;
+                                gb[k] = iq2 * NB + j2;
+                                gc[k] = iq3 * NB + j3;
+                                const Proj4 P1 = ld_proj4(f.proj, ga[k]), P2 = ld_proj4(f.proj, gb[k]),
+                                            P3 = ld_proj4(f.proj, gc[k]);
+                                const double d1 = s1 > 0 ? w0 + P1.b.y : w0 - P1.b.y;
+                                const double d2 = s2 > 0 ? d1 + P2.b.y : d1 - P2.b.y;
+                                const double delta = s3 > 0 ? d2 + P3.b.y : d2 - P3.b.y;
+                                ad[k] = fabs(delta);
+                                nrm[k] = __builtin_sqrt(proj_sq4(P1, P2) + proj_sq4(P1, P3) + proj_sq4(P2, P3));
+                            }
 #pragma unroll
-                                for (int k = 0; k < 2; ++k) {
-                                    const int c = wd * 64 + bit[k];
-                                    const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
-                                    ga[k] = iq1 * NB + j1;
-                                    gb[k] = iq2 * NB + j2;
-                                    gc[k] = iq3 * NB + j3;
-                                    double o1 = w1[0], o2 = w2[0], o3 = w3[0];
+                            for (int k = 0; k < 2; ++k) {
+                                // the width from the per-mode projection table brackets the
+                                // enumerator's; only a candidate inside the bracket needs
+                                // the enumerator's own arithmetic
+                                constexpr double rel = 1e-13;
+                                const double sp_lo = f.factor / 3.0 * (nrm[k] * (1.0 - rel) - f.perr) * (1.0 - rel);
+                                const double sp_hi = f.factor / 3.0 * (nrm[k] * (1.0 + rel) + f.perr) * (1.0 + rel);
+                                const double thr_lo = f.nsigma * fmax(sp_lo, f.sigma) * (1.0 - rel);
+                                const double thr_hi = f.nsigma * fmax(sp_hi, f.sigma) * (1.0 + rel);
+                                bool keep = ad[k] <= thr_lo;
+                                if (cv[k] && !keep && ad[k] <= thr_hi)
+                                    keep = fused_adaptive_pass(ad[k], ga[k], gb[k], gc[k], f, geo);
+                                const uint64_t b = cv[k] && keep ? 1ull << (cc[k] & 63) : 0ull;
 #pragma unroll
-                                    for (int j = 1; j < NB; ++j) {
-                                        o1 = j1 == j ? w1[j] : o1;
-                                        o2 = j2 == j ? w2[j] : o2;
-                                        o3 = j3 == j ? w3[j] : o3;
-                                    }
-                                    const double d1 = s1 > 0 ? w0 + o1 : w0 - o1;
-                                    const double d2 = s2 > 0 ? d1 + o2 : d1 - o2;
-                                    const double delta = s3 > 0 ? d2 + o3 : d2 - o3;
-                                    ad[k] = fabs(delta);
-                                    nrm[k] = __builtin_sqrt(proj_sq(a.br.proj, ga[k], gb[k]) +
-                                                            proj_sq(a.br.proj, ga[k], gc[k]) +
-                                                            proj_sq(a.br.proj, gb[k], gc[k]));
-                                }
-#pragma unroll
-                                for (int k = 0; k < 2; ++k) {
-                                    // the width from the per-mode projection table brackets the
-                                    // enumerator's; only a candidate inside the bracket needs
-                                    // the enumerator's own arithmetic
-                                    constexpr double rel = 1e-13;
-                                    const double sp_lo = f.factor / 3.0 * (nrm[k] * (1.0 - rel) - f.perr) * (1.0 - rel);
-                                    const double sp_hi = f.factor / 3.0 * (nrm[k] * (1.0 + rel) + f.perr) * (1.0 + rel);
-                                    const double thr_lo = f.nsigma * fmax(sp_lo, f.sigma) * (1.0 - rel);
-                                    const double thr_hi = f.nsigma * fmax(sp_hi, f.sigma) * (1.0 + rel);
-                                    bool keep = ad[k] <= thr_lo;
-                                    if (cv[k] && !keep && ad[k] <= thr_hi)
-                                        keep = fused_adaptive_pass(ad[k], ga[k], gb[k], gc[k], f, geo);
-                                    if (cv[k] && keep) m[wd] |= 1ull << bit[k];
-                                }
+                                for (int x = 0; x < 4; ++x) m[x] |= (cc[k] >> 6) == x ? b : 0ull;
                             }
                         }
                     }
@@ -740,9 +825,18 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                             }
                             const int c = word * 64 + select_bit(ww, n);
                             const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
-                            const uint64_t g1 = (uint64_t)(iq1 * NB + j1);
-                            const uint64_t g2 = (uint64_t)((start + lo) * NB + j2);
-                            if (pos >= pend && pos < pend + take) buf[k] = g1 | (g2 << 24) | ((uint64_t)j3 << 48);
+                            if constexpr (FORM == 2) {
+                                const int32_t i3 = __shfl(iq3_l, lo, kWave), qp = __shfl(qpk_l, lo, kWave);
+                                if (pos >= pend && pos < pend + take) {
+                                    buf[k] = (uint64_t)j1 | ((uint64_t)j2 << 3) | ((uint64_t)j3 << 6) |
+                                             ((uint64_t)(start + lo) << 9) | ((uint64_t)i3 << 33);
+                                    qbuf[k] = qp;
+                                }
+                            } else {
+                                const uint64_t g1 = (uint64_t)(iq1 * NB + j1);
+                                const uint64_t g2 = (uint64_t)((start + lo) * NB + j2);
+                                if (pos >= pend && pos < pend + take) buf[k] = g1 | (g2 << 24) | ((uint64_t)j3 << 48);
+                            }
                         }
                     }
                     pend += take;
@@ -759,8 +853,9 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                                                                        ft.fgroups, flag, a, sroots, sA[wave],
                                                                        sQ[wave], accg, accw, dl, 0.0, nullptr);
                         else
-                            tbx_batch<MAXT>(buf, pend, g0, type, sF, omega, evec, occ, bt, ft.pgroups, ft.n_pgroups,
-                                            flag, a, sroots, sA[wave], &sQ[wave][0][0], accg, accw);
+                            tbx_batch<MAXT>(buf, qbuf, pend, g0, type, iq1, sF, omega, evec, ft.occt, bt,
+                                            ft.pgroups, ft.n_pgroups, a, sroots, sA[wave], &sQ[wave][0][0], accg,
+                                            accw);
                         pend = 0;
                         ptup = 0;
                     }

@@ -104,7 +104,11 @@ struct RecipN {
     double inv_n[3];
 };
 
-__global__ void k_proj(const double* __restrict__ vel, int64_t n_modes, RecipN r, double* __restrict__ proj) {
+// proj[g] = (v_g . b_0 / N_0, v_g . b_1 / N_1, v_g . b_2 / N_2, omega_g): the
+// frequency rides in the fourth slot so that one 32-byte row holds all a
+// width evaluation needs of a mode
+__global__ void k_proj(const double* __restrict__ vel, const double* __restrict__ omega, int64_t n_modes, RecipN r,
+                       double* __restrict__ proj) {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_modes;
          g += (int64_t)gridDim.x * blockDim.x) {
         const double v0 = vel[g * 3], v1 = vel[g * 3 + 1], v2 = vel[g * 3 + 2];
@@ -112,7 +116,7 @@ __global__ void k_proj(const double* __restrict__ vel, int64_t n_modes, RecipN r
         p.x = (v0 * r.b[0] + v1 * r.b[1] + v2 * r.b[2]) * r.inv_n[0];
         p.y = (v0 * r.b[3] + v1 * r.b[4] + v2 * r.b[5]) * r.inv_n[1];
         p.z = (v0 * r.b[6] + v1 * r.b[7] + v2 * r.b[8]) * r.inv_n[2];
-        p.w = 0.0;
+        p.w = omega[g];
         reinterpret_cast<double2*>(proj)[g * 2] = make_double2(p.x, p.y);
         reinterpret_cast<double2*>(proj)[g * 2 + 1] = make_double2(p.z, p.w);
     }
@@ -409,6 +413,33 @@ __device__ inline Proc decode4(bool have, uint64_t rec, int s1, int s2, int s3, 
 }
 
 // squared distance of two projection rows (three directions)
+// pm[iq] = (max over the branches j of |proj[iq nb + j][d]|, d = 0, 1, 2; 0)
+__global__ void k_proj_max(const double* __restrict__ proj, int64_t nq, int nb, double* __restrict__ pm) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+        double m[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < nb; ++j)
+            for (int d = 0; d < 3; ++d) m[d] = fmax(m[d], fabs(proj[(q * nb + j) * 4 + d]));
+        for (int d = 0; d < 3; ++d) pm[q * 4 + d] = m[d];
+        pm[q * 4 + 3] = 0.0;
+    }
+}
+
+// one mode's row of the projection table: (proj_0, proj_1, proj_2, omega)
+struct Proj4 {
+    double2 a, b;
+};
+__device__ inline Proj4 ld_proj4(const double* __restrict__ proj, int32_t g) {
+    Proj4 p;
+    p.a = *reinterpret_cast<const double2*>(proj + (size_t)g * 4);
+    p.b = *reinterpret_cast<const double2*>(proj + (size_t)g * 4 + 2);
+    return p;
+}
+// the same squared distance as proj_sq, from rows already loaded
+__device__ inline double proj_sq4(const Proj4& x, const Proj4& y) {
+    const double d0 = x.a.x - y.a.x, d1 = x.a.y - y.a.y, d2 = x.b.x - y.b.x;
+    return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
 __device__ inline double proj_sq(const double* __restrict__ proj, int32_t gi, int32_t gj) {
     const double2 a01 = *reinterpret_cast<const double2*>(proj + (size_t)gi * 4);
     const double2 b01 = *reinterpret_cast<const double2*>(proj + (size_t)gj * 4);

@@ -176,7 +176,8 @@ struct fp_ctx {
     bool adaptive = false;      // per-process broadening (fp_set_broadening)
     double bfactor = 0.0;
     fp_broadening bro{};        // the setting behind proj, for the host enumerator
-    DevBuf<double> proj;        // [n_modes][4] projections v . b_d / N_d
+    DevBuf<double> proj;        // [n_modes][4] projections v . b_d / N_d and the frequency
+    DevBuf<double> proj_max;    // [nq][4] largest |projection| over the branches of each q-point
     std::vector<double> masses;
     std::vector<double> h_omega, h_vel;  // host copies for the streaming executor's enumerator
     StreamSlot slot[2];
@@ -195,6 +196,7 @@ struct fp_ctx {
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
     DevBuf<double2> fold;     // fused FP64 path: one folded force-constant table per wave
+    DevBuf<double> occt;      // fused form 2: occupations, temperature-fastest
     DevBuf<double> ev_val;    // three-phonon events: partner contributions per record
     DevBuf<int32_t> ev_key[2], ev_idx[2];  // their target modes and entries, unsorted and sorted
     DevBuf<unsigned char> ev_tmp;          // radix-sort workspace
@@ -328,11 +330,11 @@ extern "C" void fp_destroy(fp_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->omega.release(); c->vel.release(); c->evec.release(); c->roots.release(); c->evec32.release();
-    c->proj.release();
+    c->proj.release(); c->proj_max.release();
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
     c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release();
-    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release();
+    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release(); c->occt.release();
     c->ev_val.release(); c->ev_key[0].release(); c->ev_key[1].release(); c->ev_idx[0].release();
     c->ev_idx[1].release(); c->ev_tmp.release(); c->unit_kept.release();
     c->unit_tup.release(); c->fused_cnt.release();
@@ -482,8 +484,11 @@ extern "C" fp_status fp_set_broadening(fp_ctx* c, const fp_broadening* b) {
     for (int d = 0; d < 3; ++d) r.inv_n[d] = 1.0 / (double)c->mesh[d];
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, c->proj.ensure((size_t)c->n_modes * 4));
-    hipLaunchKernelGGL(fpk::k_proj, dim3(grid_for(c->n_modes)), dim3(256), 0, nullptr, c->vel.p, c->n_modes, r,
-                       c->proj.p);
+    HIP_TRY(c, c->proj_max.ensure((size_t)c->nq * 4));
+    hipLaunchKernelGGL(fpk::k_proj, dim3(grid_for(c->n_modes)), dim3(256), 0, nullptr, c->vel.p, c->omega.p,
+                       c->n_modes, r, c->proj.p);
+    hipLaunchKernelGGL(fpk::k_proj_max, dim3(grid_for(c->nq)), dim3(256), 0, nullptr, c->proj.p, (int64_t)c->nq,
+                       (int)c->nb, c->proj_max.p);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipDeviceSynchronize());
     c->bfactor = b->factor;
@@ -1293,6 +1298,15 @@ fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const
     const int64_t nfold = form != 0 ? 1 : nblk * fpk::kWavesPerBlock * (int64_t)ft.n_fold_ks * 2 * fpk::kWave;
     HIP_TRY(c, c->fold.ensure((size_t)nfold));
     ft.fold = c->fold.p;
+    ft.occt = nullptr;
+    if (form == 2) {  // occupations transposed so that one record's temperatures load together
+        const int mt = (T + 1) & ~1;
+        const int64_t nocc = c->n_modes * mt;
+        HIP_TRY(c, c->occt.ensure((size_t)nocc));
+        hipLaunchKernelGGL(fpk::k_occ_t, dim3(grid_for(nocc)), dim3(256), 0, st, c->occ.p, c->n_modes, a.n_T, mt,
+                           c->occt.p);
+        ft.occt = c->occt.p;
+    }
     fpk::RatesArgs af = a;
     if (form == 0) af.n_groups = S.n_fgroups;
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
@@ -1351,6 +1365,8 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     if (c->adaptive) {
         // the enumerator's rule; cut_max bounds nsigma * sigma_p over every process
         f.vel = c->vel.p;
+        f.proj = c->proj.p;
+        f.proj_max = c->proj_max.p;
         for (int i = 0; i < 9; ++i) f.recip[i] = c->bro.recip[i];
         f.factor = c->bro.factor;
         f.sigma = sigma;
