@@ -468,6 +468,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
     }
 }
 
+// First level of the partial-gradient reduction: out[s][i] = sum of
+// gpart[b][i] over the parts b of slab s (kSlab consecutive parts, in order).
+constexpr int kSlab = 32;
+__global__ void k_grad_slab(const double* __restrict__ gpart, int64_t n_parts, int64_t n, double* __restrict__ out) {
+    const int64_t n_slabs = (n_parts + kSlab - 1) / kSlab;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_slabs * n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sl = j / n, i = j % n;
+        const int64_t b1 = (sl + 1) * kSlab < n_parts ? (sl + 1) * kSlab : n_parts;
+        double s = 0.0;
+        for (int64_t b = sl * kSlab; b < b1; ++b) s += gpart[b * n + i];
+        out[j] = s;
+    }
+}
+
 // dphi[perm[t]][k] (+)= sum_b gpart[b][t][k], summed in block order.
 __global__ void k_grad_reduce(const double* __restrict__ gpart, int64_t n_blocks, int64_t n_terms, int32_t ncomp,
                               const int32_t* __restrict__ perm, int accumulate, double* __restrict__ dphi) {

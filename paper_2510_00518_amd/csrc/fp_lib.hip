@@ -193,6 +193,7 @@ struct fp_ctx {
     DevBuf<double2> phit;
     DevBuf<uint4> fsp;  // bf16 split planes of phit (mixed precision)
     DevBuf<double> gpart;
+    DevBuf<double> gslab;       // first level of the partial-gradient reduction
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
     DevBuf<double2> fold;     // fused FP64 path: one folded force-constant table per wave
@@ -333,7 +334,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->proj.release(); c->proj_max.release();
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
-    c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release();
+    c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release(); c->gslab.release();
     c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release(); c->occt.release();
     c->ev_val.release(); c->ev_key[0].release(); c->ev_key[1].release(); c->ev_idx[0].release();
     c->ev_idx[1].release(); c->ev_tmp.release(); c->unit_kept.release();
@@ -1113,6 +1114,27 @@ fp_status run_rates(fp_ctx* c, int m, const fp_plist* lists, int32_t n_lists, in
     return FP_OK;
 }
 
+// dphi (+)= the sum of n_parts partial gradients in gpart, in part order; above
+// two slabs, slabs of kSlab parts are summed first (deterministic either way).
+fp_status reduce_partials(fp_ctx* c, hipStream_t st, int64_t n_parts, const IfcState& S, int32_t ncomp,
+                          bool accumulate, double* dphi) {
+    const int64_t per = (int64_t)S.n_terms * ncomp;
+    const double* src = c->gpart.p;
+    int64_t n = n_parts;
+    if (n_parts > 2 * fpk::kSlab) {
+        const int64_t n_slabs = (n_parts + fpk::kSlab - 1) / fpk::kSlab;
+        HIP_TRY(c, c->gslab.ensure((size_t)(n_slabs * per)));
+        hipLaunchKernelGGL(fpk::k_grad_slab, dim3(grid_for(n_slabs * per)), dim3(256), 0, st, c->gpart.p, n_parts, per,
+                           c->gslab.p);
+        src = c->gslab.p;
+        n = n_slabs;
+    }
+    hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, src, n, S.n_terms, ncomp,
+                       S.perm.p, accumulate ? 1 : 0, dphi);
+    HIP_TRY(c, hipGetLastError());
+    return FP_OK;
+}
+
 template <int M, int T, int MAXP>
 fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
                       const double* dldg, double* dphi, bool accumulate) {
@@ -1128,31 +1150,43 @@ fp_status launch_grad(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.tc.p, S.groups.p, S.pairs.p, S.scale.p, c->rows.p,
                        c->units.p, dldg, c->gpart.p, c->flag, a);
-    hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, nblk, S.n_terms, ncomp,
-                       S.perm.p, accumulate ? 1 : 0, dphi);
+    HIP_TRY(c, hipGetLastError());
+    return reduce_partials(c, st, nblk, S, ncomp, accumulate, dphi);
+}
+
+// Second pass of the order-4 adjoint, tuple form: one partial dPhi per wave of
+// the largest grid the kernel can keep resident, zeroed once per call
+// (grad4t_begin), added to by every row range (launch_grad4t, whose grid never
+// exceeds that one) and summed once at the end (reduce_partials).
+int64_t grad4t_waves(fp_ctx* c, int* occ_out) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fpk::k_grad4t, fpk::kBlock,
+                                                     (size_t)c->L * sizeof(double2)) != hipSuccess || occ < 1)
+        occ = 1;
+    *occ_out = occ;
+    return (int64_t)c->n_cu * occ * fpk::kWavesPerBlock;
+}
+
+fp_status grad4t_begin(fp_ctx* c, hipStream_t st, const IfcState& S, int64_t* n_waves) {
+    int occ = 0;
+    *n_waves = grad4t_waves(c, &occ);
+    const int64_t n = *n_waves * (int64_t)S.n_terms * 81;
+    HIP_TRY(c, c->gpart.ensure((size_t)n));
+    hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n)), dim3(256), 0, st, c->gpart.p, n, 0.0);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
 
-// Second pass of the order-4 adjoint, tuple form: one partial dPhi per wave.
-fp_status launch_grad4t(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S,
-                        double* dphi, bool accumulate) {
+fp_status launch_grad4t(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk::GradArgs& a, const IfcState& S) {
     auto kern = fpk::k_grad4t;
     const size_t shm = (size_t)c->L * sizeof(double2);  // the root table
     int occ = 0;
-    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
-    if (occ < 1) occ = 1;
+    const int64_t cap = grad4t_waves(c, &occ) / fpk::kWavesPerBlock;
     const int64_t n_items = pp.n_units * (int64_t)S.n_groups;
     const int64_t want = (n_items + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
-    const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * occ, want));
-    const int64_t n_waves = nblk * fpk::kWavesPerBlock;
-    const int64_t per = (int64_t)S.n_terms * 81;
-    HIP_TRY(c, c->gpart.ensure((size_t)(n_waves * per)));
-    hipLaunchKernelGGL(fpk::k_fill, dim3(grid_for(n_waves * per)), dim3(256), 0, st, c->gpart.p, n_waves * per, 0.0);
+    const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(cap, want));
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->evec.p, c->roots.p, S.tmeta.p, S.tc.p,
                        S.groups.p, S.scale.p, c->rows.p, c->units.p, c->hbuf.p, c->gpart.p, c->flag, a);
-    hipLaunchKernelGGL(fpk::k_grad_reduce, dim3(grid_for(per)), dim3(256), 0, st, c->gpart.p, n_waves, S.n_terms, 81,
-                       S.perm.p, accumulate ? 1 : 0, dphi);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -1628,7 +1662,19 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
                         rg.push_back({k, r, r + 1});
                     cur += nr;
                 }
+            // the h buffer at the largest range's size up front (no reallocation,
+            // hence no device-wide wait, between ranges)
+            int64_t max_range = 1;
+            for (const auto& rg : ranges) {
+                int64_t nr = 0;
+                for (const Piece& pc : rg) nr += offs[pc.k][(size_t)pc.r1] - offs[pc.k][(size_t)pc.r0];
+                max_range = std::max(max_range, nr);
+            }
+            HIP_TRY(c, c->hbuf.ensure((size_t)max_range));
             const double pref4 = rate_prefactor(c, m);
+            int64_t n_waves = 0;
+            ps = grad4t_begin(c, st, S, &n_waves);
+            if (ps != FP_OK) return ps;
             for (size_t ri = 0; ri < ranges.size(); ++ri) {
                 std::vector<fp_plist> sub;
                 std::vector<int64_t> shift;
@@ -1679,9 +1725,11 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
                 if (ps != FP_OK) return ps;
                 a.n_units = pp.n_units;
                 a.geo = pp.geo;
-                fp_status ls = launch_grad4t(c, st, pp, a, S, dphi, accumulate || ri > 0);
+                fp_status ls = launch_grad4t(c, st, pp, a, S);
                 if (ls != FP_OK) return ls;
             }
+            ps = reduce_partials(c, st, n_waves, S, 81, accumulate, dphi);
+            if (ps != FP_OK) return ps;
         } else {
             ps = prepare(c, m, lists, sel, n_T, T_K, c->grad_chunk, st, &pp);
             if (ps != FP_OK) return ps;
@@ -1693,7 +1741,12 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
                                : (tsel == 4 ? launch_grad_p<3, 4>(c, st, pp, a, S, dL_dgamma, dphi, accumulate)
                                             : launch_grad_p<3, 8>(c, st, pp, a, S, dL_dgamma, dphi, accumulate));
             else
-                ls = launch_grad4t(c, st, pp, a, S, dphi, accumulate);
+            {
+                int64_t n_waves = 0;
+                ls = grad4t_begin(c, st, S, &n_waves);
+                if (ls == FP_OK) ls = launch_grad4t(c, st, pp, a, S);
+                if (ls == FP_OK) ls = reduce_partials(c, st, n_waves, S, 81, accumulate, dphi);
+            }
             if (ls != FP_OK) return ls;
         }
         ts = timer_stop(c, st, 10 + m, ev0, ev1);
