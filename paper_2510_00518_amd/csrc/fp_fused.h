@@ -119,9 +119,11 @@ constexpr int kXMT = 4;   // M-tiles of 16
 constexpr int kXTB = 16;  // tuples per batch tile (the MFMA N)
 
 // H of this unit for every pkey, written to the block's LDS table sF[pk][54]
-// (component j' * 9 + gamma delta) by all threads of the block together.  c1 =
-// +1 or -1 conjugates the eigenvectors of an emitted lambda'.
-__device__ inline void tbx_fold(double2* sF, int32_t n_pkeys, const double2* __restrict__ phit_row,
+// (component j' * 9 + gamma delta) by all threads of the block together, in
+// FP64 and stored as TF (double2, or float2 for the mixed form).  c1 = +1 or -1
+// conjugates the eigenvectors of an emitted lambda'.
+template <class TF>
+__device__ inline void tbx_fold(TF* sF, int32_t n_pkeys, const double2* __restrict__ phit_row,
                                 const double2* __restrict__ evec, int32_t iq1, double c1, int32_t Q10, int32_t Q11,
                                 int32_t Q12, const int32_t* __restrict__ tm, const int32_t* __restrict__ ptab,
                                 const int32_t* __restrict__ plist, const double2* sroots, const ModeGeom& geo) {
@@ -143,7 +145,10 @@ __device__ inline void tbx_fold(double2* sF, int32_t n_pkeys, const double2* __r
             for (int bb = 0; bb < 3; ++bb) hx = cfma(hx, h[bb * 9], ld_eps(x + bb, c1));
             F = cfma(F, sroots[mod_l(kq, geo.L, geo.magic)], hx);
         }
-        sF[i] = F;
+        if constexpr (sizeof(TF) == sizeof(float2))
+            sF[i] = make_float2((float)F.x, (float)F.y);
+        else
+            sF[i] = F;
     }
 }
 
@@ -220,14 +225,15 @@ __device__ inline double tbx_weight(const XProc& p, int type, int s1, int s2, in
 // on FP64 MFMA from the block's folded table sF, contract per process on the VALU,
 // weight in FP64.  ptab is the pkey table (B at [4..6]); A and Qs are this
 // wave's LDS staging.
-template <int MAXT>
+template <int MAXT, bool F32>
 __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], const int32_t (&qpk)[kBR], int count, int32_t g0,
-                                 int type, int32_t iq1, const double2* sF,
+                                 int type, int32_t iq1, const std::conditional_t<F32, float2, double2>* sF,
                                  const double* __restrict__ omega, const double2* __restrict__ evec,
+                                 const float2* __restrict__ evec32,
                                  const double* __restrict__ occt, const int32_t* __restrict__ ptab,
                                  const int32_t* __restrict__ pgroups, int n_pgroups, const RatesArgs& a,
-                                 const double2* sroots, double2 (*A)[kXM], int32_t* Qs, double (&accg)[MAXT],
-                                 double (&accw)[MAXT]) {
+                                 const double2* sroots, std::conditional_t<F32, float2, double2> (*A)[kXM],
+                                 int32_t* Qs, double (&accg)[MAXT], double (&accw)[MAXT]) {
     constexpr int MT = (MAXT + 1) & ~1;  // occupations per mode in occt (temperature-fastest)
     const int lane = threadIdx.x & (kWave - 1);
     const int li = lane & 15, lk = lane >> 4;
@@ -284,6 +290,45 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], const int32_t (&qpk
             const bool tval = li < nbt;
             const int32_t qa = Qs[tval ? li : 0];
             const int32_t qb0 = qa & 1023, qb1 = (qa >> 10) & 1023, qb2 = (qa >> 20) & 1023;
+if constexpr (F32) {
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                f4v k1[2], k2[2], k3[2];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) k1[mt] = k2[mt] = k3[mt] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < kMaxKs; ++ks) {
+                    if (ks >= n_ks) break;
+                    const int32_t pk = p0 + 4 * ks + lk;
+                    float2 ph = make_float2(0.0f, 0.0f);
+                    if (pk < p1 && tval) {
+                        const int32_t* b = ptab + pk * 8;
+                        const uint32_t kq = (uint32_t)(qb0 * b[4] + qb1 * b[5] + qb2 * b[6]);
+                        const double2 r = sroots[mod_l(kq, geo.L, geo.magic)];
+                        ph = make_float2((float)r.x, (float)r.y);
+                    }
+                    const float pd = ph.y - ph.x, ps = ph.x + ph.y;
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        const int mc = (2 * half + mt) * 16 + li;
+                        const float2 F = pk < p1 && mc < kXM ? sF[pk * kXM + mc] : make_float2(0.0f, 0.0f);
+                        k1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(F.x + F.y, ph.x, k1[mt], 0, 0, 0);
+                        k2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(F.x, pd, k2[mt], 0, 0, 0);
+                        k3[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(F.y, ps, k3[mt], 0, 0, 0);
+                    }
+                }
+                // FP32 result layout: D[i = 4 lk + r][j = li]
+                if (tval) {
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int mc = (2 * half + mt) * 16 + 4 * lk + r;
+                            if (mc < kXM) A[li][mc] = make_float2(k1[mt][r] - k3[mt][r], k1[mt][r] + k2[mt][r]);
+                        }
+                }
+            }
+            } else {
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 d4 k1[2], k2[2], k3[2];
@@ -320,6 +365,7 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], const int32_t (&qpk
                         }
                 }
             }
+            }
             lds_fence();
             __builtin_amdgcn_s_setprio(3);
             // per process: 9 + 3 complex MACs with the partners of slots 2 and 3
@@ -327,25 +373,47 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], const int32_t (&qpk
             for (int k = 0; k < kBR; ++k) {
                 const int s = slot[k] - tb;
                 if (have[k] && s >= 0 && s < nbt) {
-                    const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
-                    const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
-                    double2 y[3], z[3];
+                    if constexpr (F32) {
+                        const float2* e2 = evec32 + (int64_t)pr[k].g2 * nb + 3 * ac;
+                        const float2* e3 = evec32 + (int64_t)pr[k].gl * nb + 3 * ad;
+                        float2 y[3], z[3];
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        y[q] = ld_eps(e2 + q, c2);
-                        z[q] = ld_eps(e3 + q, c3);
+                        for (int q = 0; q < 3; ++q) {
+                            y[q] = ld_eps32(e2 + q, (float)c2);
+                            z[q] = ld_eps32(e3 + q, (float)c3);
+                        }
+                        const float2* Ar = A[s] + pr[k].jp * 9;
+                        float2 acc = make_float2(0.0f, 0.0f);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            float2 vc = make_float2(0.0f, 0.0f);
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) vc = cfmaf(vc, Ar[c * 3 + d], z[d]);
+                            acc = cfmaf(acc, vc, y[c]);
+                        }
+                        V[k].x += (double)acc.x;
+                        V[k].y += (double)acc.y;
+                    } else {
+                        const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
+                        const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
+                        double2 y[3], z[3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            y[q] = ld_eps(e2 + q, c2);
+                            z[q] = ld_eps(e3 + q, c3);
+                        }
+                        const double2* Ar = A[s] + pr[k].jp * 9;
+                        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double2 vc = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) vc = cfma(vc, Ar[c * 3 + d], z[d]);
+                            acc = cfma(acc, vc, y[c]);
+                        }
+                        V[k].x += acc.x;
+                        V[k].y += acc.y;
                     }
-                    const double2* Ar = A[s] + pr[k].jp * 9;
-                    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        double2 vc = make_double2(0.0, 0.0);
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) vc = cfma(vc, Ar[c * 3 + d], z[d]);
-                        acc = cfma(acc, vc, y[c]);
-                    }
-                    V[k].x += acc.x;
-                    V[k].y += acc.y;
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -455,9 +523,11 @@ __global__ void k_occ_t(const double* __restrict__ occ, int64_t n_modes, int32_t
 // FORM 0: FP64, B-keys (tb_batch, 24-tuple batches, three blocks per CU);
 // FORM 1: mixed precision (tbm_batch: split bf16 MFMA build, FP32 contraction,
 // FP64 weights); FORM 2: FP64 with the first partner folded (tbx_batch,
-// batches of at most 16 tuples, two blocks per CU).
+// batches of at most 16 tuples, two blocks per CU); FORM 3: form 2 in mixed
+// precision (folded table, staging and contraction in FP32, the build on FP32
+// matrix cores, the filter and weights in FP64).
 template <int MAXT, bool ADAPT, int FORM>
-__global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
+__global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fused4(const double* __restrict__ omega, const double2* __restrict__ evec,
                                                      const double* __restrict__ occ, const double2* __restrict__ roots,
                                                      const double2* __restrict__ phit,
                                                      const int32_t* __restrict__ tmeta,
@@ -468,30 +538,33 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                                                      const uint4* __restrict__ fsp, int32_t n_kblk, FusedTabs ft) {
     constexpr int NB = kFusedNb;
     constexpr bool MIXED = FORM == 1;
+    constexpr bool XF = FORM >= 2;   // first partner folded per unit (FP64: 2, mixed: 3)
+    constexpr bool X32 = FORM == 3;  // FP32 folded table, staging and contraction
+    using XT = std::conditional_t<X32, float2, double2>;
     constexpr int STB = FORM == 1 ? kTB : (FORM == 0 ? kFusedTB : kXTB);  // tuples staged per wave
-    constexpr int SNC = FORM == 2 ? kXM : 27;                             // components staged per tuple
+    constexpr int SNC = XF ? kXM : 27;                                    // components staged per tuple
     // dynamic LDS: the root table (FP64, or its bf16 splits: 16 bytes an entry
     // either way), then the key table, then (FP64) the B-key or pkey table
     extern __shared__ double2 sroots[];
-    __shared__ std::conditional_t<MIXED, float2, double2> sA[kWavesPerBlock][STB][SNC];
+    __shared__ std::conditional_t<MIXED || X32, float2, double2> sA[kWavesPerBlock][STB][SNC];
     __shared__ int32_t sQ[kWavesPerBlock][STB][2];
     // FORM 2: the unit's folded table, shared by the block's four waves (after
     // the staged tables, 16-byte aligned), and the per-wave unit sums
-    __shared__ double sRed[FORM == 2 ? kWavesPerBlock : 1][2 * MAXT];
-    __shared__ int64_t sCnt[FORM == 2 ? kWavesPerBlock : 1][2];
+    __shared__ double sRed[XF ? kWavesPerBlock : 1][2 * MAXT];
+    __shared__ int64_t sCnt[XF ? kWavesPerBlock : 1][2];
     const int32_t* tm;
-    const int32_t* bt = FORM == 2 ? ft.ptab : ft.btab;
-    double2* sF = nullptr;
+    const int32_t* bt = XF ? ft.ptab : ft.btab;
+    XT* sF = nullptr;
     if constexpr (MIXED) {
         tbm_roots(reinterpret_cast<uint4*>(sroots), roots, a.geo.L);
         tm = tb_stage_terms(sroots + a.geo.L, tmeta, a.n_keys);
     } else {
         tm = tb_stage(sroots, roots, a.geo.L, tmeta, a.n_keys);
-        const int32_t n_tab = FORM == 2 ? ft.n_pkeys : ft.n_bkeys;
+        const int32_t n_tab = XF ? ft.n_pkeys : ft.n_bkeys;
         const bool staged = a.n_keys <= kStageTerms && n_tab <= kStageTerms;
         if (staged) bt = tb_stage_terms(reinterpret_cast<int32_t*>(sroots + a.geo.L) + a.n_keys * 8, bt, n_tab);
-        if (FORM == 2)
-            sF = sroots + a.geo.L + ((staged ? (a.n_keys + n_tab) * 8 : 0) + 3) / 4;
+        if (XF)
+            sF = reinterpret_cast<XT*>(sroots + a.geo.L + ((staged ? (a.n_keys + n_tab) * 8 : 0) + 3) / 4);
     }
     __syncthreads();
 
@@ -501,7 +574,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
     const int64_t wstride = (int64_t)(gridDim.x / kXcd) * kWavesPerBlock;
     const ModeGeom geo = a.geo;
     // this wave's folded force-constant table (FP64 forms), rewritten per unit
-    constexpr int FMT = FORM == 2 ? kXMT : 2;  // M-tiles per K-step of the folded table
+    constexpr int FMT = XF ? kXMT : 2;  // M-tiles per K-step of the folded table
     double2* __restrict__ fw = ft.fold + ((int64_t)blockIdx.x * kWavesPerBlock + wave) * ft.n_fold_ks * FMT * kWave;
     const int32_t N0 = geo.N0, N1 = geo.N1, N2 = geo.N2;
     const int32_t nq = N0 * N1 * N2;
@@ -521,8 +594,8 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
     for (int it = 0; it < MAXT; ++it) dl[it] = 0.0;
 
     // FORM 2: a unit per block (the four waves split its q'' range); else a unit per wave
-    const int64_t w_first = FORM == 2 ? (int64_t)(blockIdx.x / kXcd) : (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave;
-    const int64_t w_step = FORM == 2 ? (int64_t)(gridDim.x / kXcd) : wstride;
+    const int64_t w_first = XF ? (int64_t)(blockIdx.x / kXcd) : (int64_t)(blockIdx.x / kXcd) * kWavesPerBlock + wave;
+    const int64_t w_step = XF ? (int64_t)(gridDim.x / kXcd) : wstride;
     for (int64_t w = w_first; w < w_end; w += w_step) {
         const int64_t fr = w / q_cnt;
         const int32_t iq1 = q_beg + (int32_t)(w % q_cnt);
@@ -590,7 +663,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                 folded = true;
             };
 
-            if constexpr (FORM == 2) {
+            if constexpr (XF) {
                 // the block folds the unit's table together (it is read by all
                 // four waves); the barrier before keeps the previous unit's
                 // readers, the one after every writer
@@ -613,8 +686,8 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
             int pend = 0;
             int ptup = 0;  // tuples in buf (FORM 2 flushes at kXTB of them)
             // FORM 2: wave w of the block takes the chunks w, w + 4, ... of q''
-            const int32_t c_first = (tri12 ? iq1 : 0) + (FORM == 2 ? wave * kWave : 0);
-            const int32_t c_step = FORM == 2 ? kBlock : kWave;
+            const int32_t c_first = (tri12 ? iq1 : 0) + (XF ? wave * kWave : 0);
+            const int32_t c_step = XF ? kBlock : kWave;
             for (int32_t start = c_first;; start += c_step) {
                 const bool last = start >= nq;
                 // ---- candidate masks: lane = q''
@@ -628,7 +701,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                     const int32_t iq3 = (wrapn(s3 * -(q00 + s1 * q10 + s2 * q20), N0) * N1 +
                                          wrapn(s3 * -(q01 + s1 * q11 + s2 * q21), N1)) * N2 +
                                         wrapn(s3 * -(q02 + s1 * q12 + s2 * q22), N2);
-                    if (FORM == 2) {
+                    if (XF) {
                         iq3_l = iq3;
                         qpk_l = (s2 > 0 ? q20 : wrapn(-q20, N0)) | ((s2 > 0 ? q21 : wrapn(-q21, N1)) << 10) |
                                 ((s2 > 0 ? q22 : wrapn(-q22, N2)) << 20);
@@ -777,7 +850,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                 const uint64_t nz = __ballot(cnt > 0);  // lanes (tuples) with kept records
                 do {
                     int take = kBU - pend < total - used ? kBU - pend : total - used;
-                    if (FORM == 2 && take > 0) {
+                    if (XF && take > 0) {
                         // at most kXTB - ptup more tuples: every lane the take touches is
                         // one new tuple of the buffer (a take starts at a lane boundary,
                         // or mid-lane right after a flush)
@@ -825,7 +898,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                             }
                             const int c = word * 64 + select_bit(ww, n);
                             const int j1 = c / (NB * NB), j2 = (c / NB) % NB, j3 = c % NB;
-                            if constexpr (FORM == 2) {
+                            if constexpr (XF) {
                                 const int32_t i3 = __shfl(iq3_l, lo, kWave), qp = __shfl(qpk_l, lo, kWave);
                                 if (pos >= pend && pos < pend + take) {
                                     buf[k] = (uint64_t)j1 | ((uint64_t)j2 << 3) | ((uint64_t)j3 << 6) |
@@ -841,7 +914,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                     }
                     pend += take;
                     used += take;
-                    if (pend == kBU || (FORM == 2 && ptup == kXTB) || (last && pend > 0)) {
+                    if (pend == kBU || (XF && ptup == kXTB) || (last && pend > 0)) {
                         if (FORM == 0 && !folded) fold_unit();
                         if constexpr (FORM == 1)
                             tbm_batch<MAXT, false>(buf, pend, g0, type, fsp + fr * n_kblk * 4 * kWave * 3, omega,
@@ -853,7 +926,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
                                                                        ft.fgroups, flag, a, sroots, sA[wave],
                                                                        sQ[wave], accg, accw, dl, 0.0, nullptr);
                         else
-                            tbx_batch<MAXT>(buf, qbuf, pend, g0, type, iq1, sF, omega, evec, ft.occt, bt,
+                            tbx_batch<MAXT, X32>(buf, qbuf, pend, g0, type, iq1, sF, omega, evec, evec32, ft.occt, bt,
                                             ft.pgroups, ft.n_pgroups, a, sroots, sA[wave], &sQ[wave][0][0], accg,
                                             accw);
                         pend = 0;
@@ -864,7 +937,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 ? 3 : 2) void k_fused4(const doub
             }
         }
         double* out = partial + u * (2 * a.n_T);
-        if constexpr (FORM == 2) {
+        if constexpr (XF) {
             // the unit's sums: each wave's, then the four in wave order
 #pragma unroll
             for (int it = 0; it < MAXT; ++it) {

@@ -1292,30 +1292,38 @@ extern "C" fp_status fp_rates4_noalloc(fp_ctx* c, const fp_plist* lists, int32_t
 
 namespace {
 
+// Form of the fused kernel: FP64 0 (B-keys) or 2 (first partner folded), the
+// fused_form knob; mixed 1 (split bf16 build) or 3 (the folded form in FP32).
+// The folded forms keep the unit's table in LDS (n_pkeys x 54 complex), so
+// tables beyond 48 KB (FP64) take the unfolded form.
+int fused_form_of(const fp_ctx* c, const IfcState& S, bool mixed) {
+    const bool fits = (size_t)S.n_pkeys * fpk::kXM * 16 <= (48u << 10);
+    if (mixed) return c->fused_form == 2 && fits ? 3 : 1;
+    return c->fused_form == 2 && fits ? 2 : 0;
+}
+
 template <int T>
 fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const fpk::FusedArgs& f,
                        const IfcState& S, bool mixed) {
-    // form: 1 mixed; FP64 0 (B-keys) or 2 (first partner folded), the fused_form
-    // knob; form 2 keeps the unit's folded table in LDS (n_pkeys x 54 complex),
-    // so tables beyond 48 KB take form 0
-    const int form = mixed ? 1 : (c->fused_form == 2 && (size_t)S.n_pkeys * fpk::kXM * 16 > (48u << 10) ? 0
-                                                                                                       : c->fused_form);
-    auto kern = form == 1 ? (f.vel ? fpk::k_fused4<T, true, 1> : fpk::k_fused4<T, false, 1>)
+    const int form = fused_form_of(c, S, mixed);
+    auto kern = form == 1   ? (f.vel ? fpk::k_fused4<T, true, 1> : fpk::k_fused4<T, false, 1>)
                 : form == 0 ? (f.vel ? fpk::k_fused4<T, true, 0> : fpk::k_fused4<T, false, 0>)
-                            : (f.vel ? fpk::k_fused4<T, true, 2> : fpk::k_fused4<T, false, 2>);
+                : form == 2 ? (f.vel ? fpk::k_fused4<T, true, 2> : fpk::k_fused4<T, false, 2>)
+                            : (f.vel ? fpk::k_fused4<T, true, 3> : fpk::k_fused4<T, false, 3>);
     // the FP64 forms also stage the B-key or pkey table when the key table is staged
-    const int32_t n_tab = form == 2 ? S.n_pkeys : S.n_bkeys;
+    const bool xf = form >= 2;
+    const int32_t n_tab = xf ? S.n_pkeys : S.n_bkeys;
     const bool staged = S.n_keys <= fpk::kStageTerms && n_tab <= fpk::kStageTerms;
     size_t shm = fpk::tb_dyn_lds(c->L, S.n_keys) + (form != 1 && staged ? (size_t)n_tab * 8 * sizeof(int32_t) : 0);
-    if (form == 2)  // the folded table, 16-byte aligned after the staged tables
+    if (xf)  // the folded table (complex FP64, or FP32 in form 3), 16-byte aligned after the staged tables
         shm = (size_t)c->L * sizeof(double2) + (staged ? ((size_t)(S.n_keys + n_tab) * 8 + 3) / 4 * 16 : 0) +
-              (size_t)S.n_pkeys * fpk::kXM * sizeof(double2);
+              (size_t)S.n_pkeys * fpk::kXM * (form == 3 ? sizeof(float2) : sizeof(double2));
     int occ = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, fpk::kBlock, shm));
     if (occ < 1) occ = 1;
     const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, occ) : occ;
     // a unit per wave (form 2: per block)
-    const int64_t want = form == 2 ? f.n_units : (f.n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
+    const int64_t want = xf ? f.n_units : (f.n_units + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
     int64_t nblk = std::min<int64_t>((int64_t)c->n_cu * bpc, want);
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     // one folded table per wave (FP64 forms)
@@ -1328,12 +1336,12 @@ fp_status launch_fused(fp_ctx* c, hipStream_t st, const fpk::RatesArgs& a, const
     ft.n_bkeys = S.n_bkeys;
     ft.n_pkeys = S.n_pkeys;
     ft.n_pgroups = S.n_pgroups;
-    ft.n_fold_ks = form == 2 ? S.n_pks : S.n_fks;
+    ft.n_fold_ks = xf ? S.n_pks : S.n_fks;
     const int64_t nfold = form != 0 ? 1 : nblk * fpk::kWavesPerBlock * (int64_t)ft.n_fold_ks * 2 * fpk::kWave;
     HIP_TRY(c, c->fold.ensure((size_t)nfold));
     ft.fold = c->fold.p;
     ft.occt = nullptr;
-    if (form == 2) {  // occupations transposed so that one record's temperatures load together
+    if (xf) {  // occupations transposed so that one record's temperatures load together
         const int mt = (T + 1) & ~1;
         const int64_t nocc = c->n_modes * mt;
         HIP_TRY(c, c->occt.ensure((size_t)nocc));
@@ -1444,7 +1452,7 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     const fpk::ModeGeom geo = geometry(c);
     hipLaunchKernelGGL(fpk::k_precontract<4>, dim3(grid_for(n_frows * S.n_keys * 27)), dim3(256), 0, st, c->rows.p,
                        n_frows, c->evec.p, c->roots.p, geo, S.phi_s.p, S.tmeta.p, S.tc.p, S.n_keys, c->phit.p);
-    if (mixed) {
+    if (fused_form_of(c, S, mixed) == 1) {  // the split bf16 force constants of form 1
         const int64_t nf = n_frows * S.n_kblk * 4 * fpk::kWave;
         HIP_TRY(c, c->fsp.ensure((size_t)std::max<int64_t>(nf * 3, 1)));
         hipLaunchKernelGGL(fpk::k_split_phit, dim3(grid_for(nf)), dim3(256), 0, st, n_frows, c->phit.p, S.groups.p,

@@ -191,16 +191,19 @@ def test_fused_adaptive_fcc8_against_lists(ctx):
     assert_modes(gam2.cpu().numpy(), g_list, "fused adaptive vs lists", rtol=1e-12)
 
 
+@pytest.mark.parametrize("form", [0, 2])
 @pytest.mark.parametrize("mesh,sigma,stride", [(4, None, 5), (3, 4.0, 2)])
-def test_fused_mixed_precision_matches_oracle(ctx, mesh, sigma, stride):
-    """FP_MIXED in the fused launch: the same kept set, rates within the mixed
-    bar (2e-5 per mode relative; modes below 1e-6 of the largest within that
-    absolute floor) of the oracle's FP64 sums."""
+def test_fused_mixed_precision_matches_oracle(ctx, mesh, sigma, stride, form):
+    """FP_MIXED in the fused launch, both mixed forms (split bf16 build; the
+    folded form in FP32, the default): the same kept set, rates within the
+    mixed bar (2e-5 per mode relative; modes below 1e-6 of the largest within
+    that absolute floor) of the oracle's FP64 sums."""
     cfg = small_config(mesh)
     sig = cfg["sigma"] if sigma is None else sigma
     rows = np.asarray(row_modes(cfg)[::stride], np.int32)
     T = [300.0, 1200.0]
-    g, w, kept = fused_rates(ctx, cfg, rows, T, sigma=sig, precision=fp.FP_MIXED)
+    with knob_util.knobs(ctx, fused_form=form):
+        g, w, kept = fused_rates(ctx, cfg, rows, T, sigma=sig, precision=fp.FP_MIXED)
     go, wo, ko, to = oracle_rows(cfg, TYPES4, rows, T, sig)
     assert kept == ko
     assert fp.fp_fused_counts(ctx) == (ko, to)
@@ -214,14 +217,18 @@ def test_fused_mixed_precision_matches_oracle(ctx, mesh, sigma, stride):
 
 
 @pytest.mark.slow
-def test_fused_mixed_fcc8_against_mixed_lists(ctx):
-    """8^3 workload: the fused mixed launch against the list-driven mixed path
-    (the same per-process arithmetic, sums grouped differently)."""
+@pytest.mark.parametrize("form", [0, 2])
+def test_fused_mixed_fcc8_against_mixed_lists(ctx, form):
+    """8^3 workload, the fused mixed launch against the list-driven paths: the
+    split-bf16 form (fused_form 0) does the list path's mixed per-process
+    arithmetic with sums grouped differently, so it matches the mixed lists to
+    rounding; the folded FP32 form (fused_form 2, the default) holds the mixed
+    bar of 2e-5 per mode against the FP64 lists."""
     import torch
     from paper_2510_00518_amd.driver import RatePath, host_lists
     cfg = make_config("fcc8_4ph")
     lists = host_lists(cfg, TYPES4)
-    p = RatePath(cfg, ctx=ctx, precision=fp.FP_MIXED)
+    p = RatePath(cfg, ctx=ctx, precision=fp.FP_MIXED if form == 0 else fp.FP_FP64)
     p.set_lists(lists)
     gam, _ = p.outputs(1)
     p.load_ifc()
@@ -229,11 +236,14 @@ def test_fused_mixed_fcc8_against_mixed_lists(ctx):
     torch.cuda.synchronize()
     g_list = gam.cpu().numpy()
     del lists
-    g, _, kept = fused_rates(ctx, cfg, row_modes(cfg), [300.0], precision=fp.FP_MIXED)
+    with knob_util.knobs(ctx, fused_form=form):
+        g, _, kept = fused_rates(ctx, cfg, row_modes(cfg), [300.0], precision=fp.FP_MIXED)
     scale = np.abs(g_list).max()
     err = np.abs(g - g_list) / np.maximum(np.abs(g_list), 1e-6 * scale)
-    say(f"fcc8 fused mixed vs mixed lists: max rel err {err.max():.2e} (modes below 1e-6 of the largest: absolute)")
-    assert err.max() <= 1e-12
+    what = "mixed lists" if form == 0 else "FP64 lists"
+    say(f"fcc8 fused mixed (fused_form {form}) vs {what}: max rel err {err.max():.2e} "
+        "(modes below 1e-6 of the largest: absolute)")
+    assert err.max() <= (1e-12 if form == 0 else 2e-5)
 
 
 def test_fused_type_mask(ctx):
