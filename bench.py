@@ -153,14 +153,20 @@ def form_work(fp, ctx, n_proc, n_tup, folded):
     return build, contract, per_process_form, desc
 
 
-def roofline(fp, ctx, n_proc, n_tup, kernel_s, kernel, mixed=False, folded=False):
+def roofline(fp, ctx, n_proc, n_tup, kernel_s, kernel, mixed=None, folded=False):
+    """mixed: None (FP64), "bf16" (split-bf16 build, FP32 contraction) or
+    "fp32" (FP32 matrix-core build and FP32 contraction)."""
     build, contract, f4, desc = form_work(fp, ctx, n_proc, n_tup, folded)
     total = build + contract
     r = {"bound": "mfma", "unit": "TFLOP/s", "kernel": kernel, "work": desc, "kernel_ms": kernel_s * 1e3}
-    if mixed:
+    if mixed == "bf16":
         r["achieved"] = (6 * build + contract) / kernel_s / 1e12
         r["peak"] = PEAK_BF16_TFLOPS
         r["work"] += "; 6 bf16 products per FP32-accurate product in the build"
+    elif mixed == "fp32":
+        r["achieved"] = total / kernel_s / 1e12
+        r["peak"] = PEAK_FP32_TFLOPS
+        r["work"] += "; build on FP32 matrix cores, contraction in FP32"
     else:
         r["achieved"] = total / kernel_s / 1e12
         r["peak"] = PEAK_FP64_TFLOPS
@@ -325,7 +331,7 @@ def leg_lists_8(torch, fp, args, lists, n_tup):
     out["mixed"] = {"value": n4 / (np.median(per_m) * 1e-3), "ms_per_step_median": float(np.median(per_m)),
                     "kappa_rel_err_vs_fp64": float(np.max(np.abs(km - k0) / np.abs(k0))),
                     "roofline": roofline(fp, path.ctx, n4, n_tup, km_ms * 1e-3, "k_rates4m (list-driven, mixed)",
-                                         mixed=True)}
+                                         mixed="bf16")}
     path.close()
     log(f"bench: 8^3 lists FP64 {np.median(per):.3f} ms/step (kernel {k_ms:.3f} ms), mixed {np.median(per_m):.3f}")
     return out
@@ -464,9 +470,10 @@ def main():
     log(f"bench: FP64 {args.steps} steps, {per.mean():.1f} ms/step, {value:.3e} 4ph processes/s, "
         f"fused kernel {k4_ms:.1f} ms total")
     form = fp.fp_get_knob(ctx, "fused_form")
+    folded = form == 2  # FP64 form 2 and, in mixed precision, form 3
     roof = roofline(fp, ctx, n4_timed, tup, k4_ms * 1e-3,
                     f"k_fused4 form {form} (GPU enumeration + tuple-batched FP64: matrix-core build, VALU "
-                    "contraction)", folded=form == 2)
+                    "contraction)", folded=folded)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
@@ -519,8 +526,11 @@ def main():
             "kappa_rel_err": float(np.max(np.abs(k_m - k_ref) / np.abs(k_ref))),
             "gamma_rel_err_max": float(rel.max()), "gamma_rel_err_median": float(np.median(rel)),
             "error_reference": "the FP64 pass of this run (held to the oracle at 1e-10 per mode by the tests)",
-            "roofline": roofline(fp, ctx, n4m, tupm, km_ms * 1e-3, "k_fused4 mixed (bf16 split MFMA + FP32 VALU)",
-                                 mixed=True)}
+            "roofline": (roofline(fp, ctx, n4m, tupm, km_ms * 1e-3,
+                                  "k_fused4 form 3 (folded, FP32 matrix-core build + FP32 VALU, FP64 weights)",
+                                  mixed="fp32", folded=True) if folded else
+                         roofline(fp, ctx, n4m, tupm, km_ms * 1e-3, "k_fused4 form 1 (bf16 split MFMA + FP32 VALU)",
+                                  mixed="bf16"))}
         log(f"bench: mixed {per_m.mean():.1f} ms/step, kappa rel err {out['mixed']['kappa_rel_err']:.2e}")
     if args.paper_scale_adaptive:
         b = adaptive_broadening(cfg)

@@ -366,16 +366,19 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *                    one (5), or two with 24-tuple batches and three resident
  *                    blocks per CU (6, the default), or three records per
  *                    lane (7)
- *   "grad_chunk"     records per adjoint work chunk, a multiple of 256
+ *   "grad_chunk"     records per adjoint work chunk, a multiple of 256 (default 4096)
  *   "grad_records"   records per order-4 adjoint pass, 1024..2^34 (default
- *                    2^24): rows are taken in ranges of at most this many
+ *                    2^25, 512 MiB of buffer): rows are taken in ranges of at most this many
  *                    records (a longer row alone), so the per-record adjoint
  *                    buffer holds one range (16 bytes per record), not the
  *                    whole call; the gradient is summed over the ranges in order
  *   "fused_form"     FP64 form of fp_rates4_fused: 0 = phase keys folded over
  *                    A per (lambda, q') unit, 2 (the default) = keys and the
  *                    first partner's eigenvector folded per unit, pair groups
- *                    over the atoms of slots 2 and 3
+ *                    over the atoms of slots 2 and 3.  With FP_MIXED, 0 takes
+ *                    the split-bf16 build and 2 the folded form in FP32
+ *                    (folded table, build on FP32 matrix cores, contraction;
+ *                    filter and weights stay FP64)
  * FP_ERR_ARG for an unknown name or a value out of range. */
 fp_status fp_set_knob(fp_ctx* ctx, const char* name, int64_t value);
 
