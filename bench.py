@@ -416,6 +416,7 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="the 16^3 FP64 steps only (for profiling)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-8", action="store_true", help="skip the 8^3 legs (lists, adjoint, adaptive)")
+    ap.add_argument("--no-16", action="store_true", help="skip the 16^3 headline (for profiling the 8^3 legs)")
     ap.add_argument("--paper-scale-adaptive", action="store_true",
                     help="also run one pass of the 16^3 cell with the adaptive width")
     ap.add_argument("--variant", type=int, default=None, help="order-4 contraction form of the list kernel")
@@ -446,105 +447,107 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- headline: the 16^3 cell, FP64, batched by q1
-    cfg = make_config("fcc16_34ph")
-    ctx = fp.fp_create(0)
-    if args.fused_form is not None:
-        fp.fp_set_knob(ctx, "fused_form", args.fused_form)
-    t0 = time.perf_counter()
-    W = Batched16(torch, fp, cfg, ctx)
-    log(f"bench: 16^3 set-up ({N_BATCH} q1 batches, 3ph host lists) {time.perf_counter() - t0:.1f} s")
-    t0 = time.perf_counter()
-    counts, g_ref, k_ref = W.reference_pass(fp.FP_FP64)
-    t_ref = time.perf_counter() - t0
-    n4_all, tup_all = int(counts[:, 0].sum()), int(counts[:, 1].sum())
-    n3_all = sum(B["n3"] for B in W.batches)
-    log(f"bench: reference pass {t_ref:.2f} s: {n4_all} 4ph processes in {tup_all} tuples, {n3_all} 3ph; "
-        f"kappa {k_ref}")
-    per, done, k4_ms, k3_ms = W.timed(args.steps, args.warmup, fp.FP_FP64, first=0)
-    proc = np.array([counts[b, 0] for b in done], np.float64)
-    tup = int(sum(counts[b, 1] for b in done))
-    n4_timed = int(proc.sum())
-    t_total = per.sum() * 1e-3
-    value = n4_timed / t_total
-    log(f"bench: FP64 {args.steps} steps, {per.mean():.1f} ms/step, {value:.3e} 4ph processes/s, "
-        f"fused kernel {k4_ms:.1f} ms total")
-    form = fp.fp_get_knob(ctx, "fused_form")
-    folded = form == 2  # FP64 form 2 and, in mixed precision, form 3
-    roof = roofline(fp, ctx, n4_timed, tup, k4_ms * 1e-3,
-                    f"k_fused4 form {form} (GPU enumeration + tuple-batched FP64: matrix-core build, VALU "
-                    "contraction)", folded=folded)
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_source_hash") == kernel_source_hash():
-            # measured bytes per process, scaled to this run's launches
-            traffic = tr["hbm_bytes_per_process"] * n4_timed / max(1, len(done))
-    roof["traffic"] = traffic
-    out = {
-        "metric": "4ph processes/sec at 1 GPU, FP64 vs mixed (rel err vs oracle); bwd/fwd time ratio",
-        "value": value,
-        "unit": "processes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": float(per.mean()),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "3ph+4ph FP64, 2-atom diamond cell, 16x16x16 mesh, Oh-irreducible q1 (145), "
-                        f"{int(cfg['ifc3']['n_terms'])} cubic + {int(cfg['ifc4']['n_terms'])} quartic terms, "
-                        "sigma 0.1 THz, |Delta| <= 3 sigma, T = 300/600/900 K; 4ph lists generated on the GPU, "
-                        "3ph host lists",
-            "step": f"one of {N_BATCH} q1 batches: load_ifc(3,4) + rates3 + fused rates4 (Gamma3+Gamma4) + "
-                    "kappa_RTA share",
-            "batches": N_BATCH,
-            "processes_4ph_cell": n4_all, "tuples_4ph_cell": tup_all, "processes_3ph_cell": n3_all,
-            "processes_4ph_timed": n4_timed,
-            "full_cell_pass_s": t_ref,
-        },
-        "per_step_processes_per_s_median": float(np.median(proc / (per * 1e-3))),
-        "kernel_only_processes_per_s": n4_timed / (k4_ms * 1e-3),
-        "call_level_ms_per_step": float(per.mean()),
-        "kernel_only_ms_per_step": (k4_ms + k3_ms) / len(done),
-        "kappa_rta_W_per_mK": [float(x) for x in k_ref],
-        "roofline": roof,
-    }
-    if not args.no_mixed:
-        per_m, done_m, km_ms, _ = W.timed(N_BATCH, 1, fp.FP_MIXED, first=0)
-        g_m, k_m = W.gamma(), W.kappa()
-        big = np.abs(g_ref) > 1e-6 * np.abs(g_ref).max()
-        rel = np.abs(g_m[big] - g_ref[big]) / np.abs(g_ref[big])
-        n4m = int(sum(counts[b, 0] for b in done_m))
-        tupm = int(sum(counts[b, 1] for b in done_m))
-        out["mixed"] = {
-            "value": n4m / (per_m.sum() * 1e-3), "unit": "processes/s", "ms_per_step": float(per_m.mean()),
-            "steps": len(done_m), "speedup_vs_fp64": float(per.mean() / per_m.mean()),
-            "kappa_rel_err": float(np.max(np.abs(k_m - k_ref) / np.abs(k_ref))),
-            "gamma_rel_err_max": float(rel.max()), "gamma_rel_err_median": float(np.median(rel)),
-            "error_reference": "the FP64 pass of this run (held to the oracle at 1e-10 per mode by the tests)",
-            "roofline": (roofline(fp, ctx, n4m, tupm, km_ms * 1e-3,
-                                  "k_fused4 form 3 (folded, FP32 matrix-core build + FP32 VALU, FP64 weights)",
-                                  mixed="fp32", folded=True) if folded else
-                         roofline(fp, ctx, n4m, tupm, km_ms * 1e-3, "k_fused4 form 1 (bf16 split MFMA + FP32 VALU)",
-                                  mixed="bf16"))}
-        log(f"bench: mixed {per_m.mean():.1f} ms/step, kappa rel err {out['mixed']['kappa_rel_err']:.2e}")
-    if args.paper_scale_adaptive:
-        b = adaptive_broadening(cfg)
-        ctx_a = fp.fp_create(0)
-        Wa = Batched16(torch, fp, dict(cfg, sigma=SIGMA_FLOOR), ctx_a, broadening=b)
-        per_a, done_a, ka_ms, _ = Wa.timed(N_BATCH, 1, fp.FP_FP64, first=0)
-        ca, _, _ = Wa.reference_pass(fp.FP_FP64)
-        n4a = int(ca[:, 0].sum())
-        out["paper_scale_adaptive"] = {"value": n4a / (per_a.sum() * 1e-3), "unit": "processes/s",
-                                       "processes_4ph": n4a, "seconds": float(per_a.sum() * 1e-3),
-                                       "kernel_ms": ka_ms}
-        fp.fp_destroy(ctx_a)
-    fp.fp_destroy(ctx)
-    del W
+    out = {}
+    if not args.no_16:
+        # ---- headline: the 16^3 cell, FP64, batched by q1
+        cfg = make_config("fcc16_34ph")
+        ctx = fp.fp_create(0)
+        if args.fused_form is not None:
+            fp.fp_set_knob(ctx, "fused_form", args.fused_form)
+        t0 = time.perf_counter()
+        W = Batched16(torch, fp, cfg, ctx)
+        log(f"bench: 16^3 set-up ({N_BATCH} q1 batches, 3ph host lists) {time.perf_counter() - t0:.1f} s")
+        t0 = time.perf_counter()
+        counts, g_ref, k_ref = W.reference_pass(fp.FP_FP64)
+        t_ref = time.perf_counter() - t0
+        n4_all, tup_all = int(counts[:, 0].sum()), int(counts[:, 1].sum())
+        n3_all = sum(B["n3"] for B in W.batches)
+        log(f"bench: reference pass {t_ref:.2f} s: {n4_all} 4ph processes in {tup_all} tuples, {n3_all} 3ph; "
+            f"kappa {k_ref}")
+        per, done, k4_ms, k3_ms = W.timed(args.steps, args.warmup, fp.FP_FP64, first=0)
+        proc = np.array([counts[b, 0] for b in done], np.float64)
+        tup = int(sum(counts[b, 1] for b in done))
+        n4_timed = int(proc.sum())
+        t_total = per.sum() * 1e-3
+        value = n4_timed / t_total
+        log(f"bench: FP64 {args.steps} steps, {per.mean():.1f} ms/step, {value:.3e} 4ph processes/s, "
+            f"fused kernel {k4_ms:.1f} ms total")
+        form = fp.fp_get_knob(ctx, "fused_form")
+        folded = form == 2  # FP64 form 2 and, in mixed precision, form 3
+        roof = roofline(fp, ctx, n4_timed, tup, k4_ms * 1e-3,
+                        f"k_fused4 form {form} (GPU enumeration + tuple-batched FP64: matrix-core build, VALU "
+                        "contraction)", folded=folded)
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("kernel_source_hash") == kernel_source_hash():
+                # measured bytes per process, scaled to this run's launches
+                traffic = tr["hbm_bytes_per_process"] * n4_timed / max(1, len(done))
+        roof["traffic"] = traffic
+        out = {
+            "metric": "4ph processes/sec at 1 GPU, FP64 vs mixed (rel err vs oracle); bwd/fwd time ratio",
+            "value": value,
+            "unit": "processes/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": float(per.mean()),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {
+                "workload": "3ph+4ph FP64, 2-atom diamond cell, 16x16x16 mesh, Oh-irreducible q1 (145), "
+                            f"{int(cfg['ifc3']['n_terms'])} cubic + {int(cfg['ifc4']['n_terms'])} quartic terms, "
+                            "sigma 0.1 THz, |Delta| <= 3 sigma, T = 300/600/900 K; 4ph lists generated on the GPU, "
+                            "3ph host lists",
+                "step": f"one of {N_BATCH} q1 batches: load_ifc(3,4) + rates3 + fused rates4 (Gamma3+Gamma4) + "
+                        "kappa_RTA share",
+                "batches": N_BATCH,
+                "processes_4ph_cell": n4_all, "tuples_4ph_cell": tup_all, "processes_3ph_cell": n3_all,
+                "processes_4ph_timed": n4_timed,
+                "full_cell_pass_s": t_ref,
+            },
+            "per_step_processes_per_s_median": float(np.median(proc / (per * 1e-3))),
+            "kernel_only_processes_per_s": n4_timed / (k4_ms * 1e-3),
+            "call_level_ms_per_step": float(per.mean()),
+            "kernel_only_ms_per_step": (k4_ms + k3_ms) / len(done),
+            "kappa_rta_W_per_mK": [float(x) for x in k_ref],
+            "roofline": roof,
+        }
+        if not args.no_mixed:
+            per_m, done_m, km_ms, _ = W.timed(N_BATCH, 1, fp.FP_MIXED, first=0)
+            g_m, k_m = W.gamma(), W.kappa()
+            big = np.abs(g_ref) > 1e-6 * np.abs(g_ref).max()
+            rel = np.abs(g_m[big] - g_ref[big]) / np.abs(g_ref[big])
+            n4m = int(sum(counts[b, 0] for b in done_m))
+            tupm = int(sum(counts[b, 1] for b in done_m))
+            out["mixed"] = {
+                "value": n4m / (per_m.sum() * 1e-3), "unit": "processes/s", "ms_per_step": float(per_m.mean()),
+                "steps": len(done_m), "speedup_vs_fp64": float(per.mean() / per_m.mean()),
+                "kappa_rel_err": float(np.max(np.abs(k_m - k_ref) / np.abs(k_ref))),
+                "gamma_rel_err_max": float(rel.max()), "gamma_rel_err_median": float(np.median(rel)),
+                "error_reference": "the FP64 pass of this run (held to the oracle at 1e-10 per mode by the tests)",
+                "roofline": (roofline(fp, ctx, n4m, tupm, km_ms * 1e-3,
+                                      "k_fused4 form 3 (folded, FP32 matrix-core build + FP32 VALU, FP64 weights)",
+                                      mixed="fp32", folded=True) if folded else
+                             roofline(fp, ctx, n4m, tupm, km_ms * 1e-3, "k_fused4 form 1 (bf16 split MFMA + FP32 VALU)",
+                                      mixed="bf16"))}
+            log(f"bench: mixed {per_m.mean():.1f} ms/step, kappa rel err {out['mixed']['kappa_rel_err']:.2e}")
+        if args.paper_scale_adaptive:
+            b = adaptive_broadening(cfg)
+            ctx_a = fp.fp_create(0)
+            Wa = Batched16(torch, fp, dict(cfg, sigma=SIGMA_FLOOR), ctx_a, broadening=b)
+            per_a, done_a, ka_ms, _ = Wa.timed(N_BATCH, 1, fp.FP_FP64, first=0)
+            ca, _, _ = Wa.reference_pass(fp.FP_FP64)
+            n4a = int(ca[:, 0].sum())
+            out["paper_scale_adaptive"] = {"value": n4a / (per_a.sum() * 1e-3), "unit": "processes/s",
+                                           "processes_4ph": n4a, "seconds": float(per_a.sum() * 1e-3),
+                                           "kernel_ms": ka_ms}
+            fp.fp_destroy(ctx_a)
+        fp.fp_destroy(ctx)
+        del W
 
     if not args.no_8:
         from paper_2510_00518_amd.driver import TYPES3, TYPES4, host_lists
@@ -560,7 +563,7 @@ def main():
         out["adaptive_8"] = leg_adaptive_8(torch, fp, args)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, args.cpu_seconds_single)
+        out["cpu_baseline"] = cpu_baseline(make_config("fcc16_34ph"), args.cpu_seconds, args.cpu_seconds_single)
     print(json.dumps(out), flush=True)
 
 
