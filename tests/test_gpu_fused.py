@@ -115,11 +115,14 @@ def test_fused_matches_oracle_brute_force(ctx, mesh, sigma, stride, form):
     assert_modes(w, wo, "WP4")
 
 
+@pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("form", [0, 2])
 @pytest.mark.parametrize("mesh,factor,floor,stride", [(4, 0.5, 0.3, 13), ((2, 3, 4), 0.7, 0.2, 5), (3, 2.0, 0.5, 4)])
-def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride, form):
-    """Adaptive width in the on-GPU filter: the kept count equals the oracle's
-    adaptive enumeration exactly, and the rates its list-mode sums."""
+def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride, form, mixed):
+    """Adaptive width in the on-GPU filter, every fused form (FP64 0 and 2;
+    mixed 1 and 3): the kept count equals the oracle's adaptive enumeration
+    exactly, and the rates its list-mode sums (FP64: 1e-10 per mode; mixed: the
+    mixed bar, with WP in FP64 in both)."""
     import torch
     from paper_2510_00518_amd.driver import RatePath
     cfg = small_config(mesh)
@@ -127,7 +130,7 @@ def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride, f
     b = {"factor": factor, "recip": cfg["recip"] + rng.uniform(-0.3, 0.3, size=(3, 3))}
     rows = np.asarray(row_modes(cfg)[::stride], np.int32)
     T = [300.0, 900.0]
-    p = RatePath(dict(cfg, sigma=floor), ctx=ctx)
+    p = RatePath(dict(cfg, sigma=floor), ctx=ctx, precision=fp.FP_MIXED if mixed else fp.FP_FP64)
     p.set_broadening(b)
     p.set_fused(rows, 7)
     gam, wp = p.outputs(len(T))
@@ -151,7 +154,16 @@ def test_fused_adaptive_width_matches_oracle(ctx, mesh, factor, floor, stride, f
             wo[:, rows] += w.T
     say(f"fused adaptive {mesh}: {kept} processes (oracle {ko})")
     assert kept == ko
-    assert_modes(gam.cpu().numpy(), go, "Gamma4 adaptive")
+    g = gam.cpu().numpy()
+    if mixed:
+        scale = np.abs(go).max()
+        big = np.abs(go) > 1e-6 * scale
+        rel = np.abs(g[big] - go[big]) / np.abs(go[big])
+        say(f"  mixed: Gamma rel err max {rel.max():.2e}")
+        assert rel.max() <= 2e-5
+        assert np.abs(g[~big] - go[~big]).max() <= 1e-6 * scale
+    else:
+        assert_modes(g, go, "Gamma4 adaptive")
     assert_modes(wp.cpu().numpy(), wo, "WP4 adaptive")
 
 
