@@ -177,6 +177,11 @@ def roofline(fp, ctx, n_proc, n_tup, kernel_s, kernel, mixed=None, folded=False)
     r["mfma_part_tflops"] = build / kernel_s / 1e12
     r["valu_part_tflops"] = contract / kernel_s / 1e12
     r["per_process_form_equivalent_tflops"] = f4 / kernel_s / 1e12
+    if folded:
+        # the same processes in the list form's FLOP (keys per tuple, partner groups per process)
+        lb, lc, _, _ = form_work(fp, ctx, n_proc, n_tup, False)
+        r["list_form_equivalent_tflops"] = (lb + lc) / kernel_s / 1e12
+        r["list_form_equivalent_frac_fp64"] = r["list_form_equivalent_tflops"] / PEAK_FP64_TFLOPS
     return r
 
 
