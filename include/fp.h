@@ -290,6 +290,17 @@ fp_status fp_rates4_fused(fp_ctx* ctx, int64_t n_rows, const int32_t* row_mode, 
  * FP_ERR_ARG for NULL out, FP_ERR_STATE before any fp_rates4_fused call. */
 fp_status fp_fused_counts(fp_ctx* ctx, int64_t out[2], void* hip_stream);
 
+/* Peak probes of the device, measured beside the published peaks that rooflines
+ * divide by.  kind 0: FP64 vector FMA; 1: FP64 matrix cores (v_mfma_f64_16x16x4f64);
+ * 2: FP32 matrix cores (v_mfma_f32_16x16x4f32); 3: bf16 matrix cores
+ * (v_mfma_f32_16x16x32_bf16, dense) -- all in TFLOP/s; 4: device copy of 1 GiB,
+ * bytes read plus written, in GB/s.  Each kernel keeps one pipe busy with
+ * independent chains on every CU.  One untimed launch, then `reps` (1..100)
+ * timed with HIP events on `hip_stream`; *achieved is the best.  Waits for the
+ * stream; kind 4 allocates (and frees) 2 GiB of device memory.  FP_ERR_ARG for
+ * an unknown kind or reps out of range. */
+fp_status fp_peak_probe(fp_ctx* ctx, int32_t kind, int32_t reps, double* achieved, void* hip_stream);
+
 /* Figures of one fp_rates_streamed call (host wall-clock milliseconds). */
 typedef struct {
     int64_t n_records;  /* records evaluated, all selected types */

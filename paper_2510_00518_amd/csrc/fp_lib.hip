@@ -23,6 +23,7 @@
 #include "fp_batched.h"
 #include "fp_mixed.h"
 #include "fp_fused.h"
+#include "fp_probe.h"
 #include "fp_enum_impl.h"
 
 namespace {
@@ -194,6 +195,7 @@ struct fp_ctx {
     DevBuf<uint4> fsp;  // bf16 split planes of phit (mixed precision)
     DevBuf<double> gpart;
     DevBuf<double> gslab;       // first level of the partial-gradient reduction
+    DevBuf<double> probe_out;   // results of the peak probes (one per thread)
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
     DevBuf<double2> fold;     // fused FP64 path: one folded force-constant table per wave
@@ -334,7 +336,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->proj.release(); c->proj_max.release();
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
-    c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release(); c->gslab.release();
+    c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release(); c->gslab.release(); c->probe_out.release();
     c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release(); c->occt.release();
     c->ev_val.release(); c->ev_key[0].release(); c->ev_key[1].release(); c->ev_idx[0].release();
     c->ev_idx[1].release(); c->ev_tmp.release(); c->unit_kept.release();
@@ -1492,6 +1494,73 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
                            c->unit_off.p, c->rows.p, (int64_t)ti * n_rows, n_T, pref, wpref, gamma_out, wp_out, nm);
     HIP_TRY(c, hipGetLastError());
     if (c->validate) return fp_check(c, stream);
+    return FP_OK;
+}
+
+extern "C" fp_status fp_peak_probe(fp_ctx* c, int32_t kind, int32_t reps, double* achieved, void* stream) {
+    if (!c || !achieved) return FP_ERR_ARG;
+    if (kind < 0 || kind > 4) return fail(c, FP_ERR_ARG, "probe kind must be in [0, 4]");
+    if (reps < 1 || reps > 100) return fail(c, FP_ERR_ARG, "reps must be in [1, 100]");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    // FLOP (or bytes) of one launch and the launch itself
+    const int64_t blocks = (int64_t)c->n_cu * (kind == 0 ? 8 : 4);
+    const int iters = kind == 0 ? 16384 : (kind == 3 ? 16384 : 4096);
+    const int64_t n_copy = int64_t(1) << 26;  // 16-byte elements: 1 GiB each way
+    DevBuf<uint4> src, dst;
+    if (kind == 4) {
+        HIP_TRY(c, src.ensure((size_t)n_copy));
+        HIP_TRY(c, dst.ensure((size_t)n_copy));
+    } else {
+        HIP_TRY(c, c->probe_out.ensure((size_t)(blocks * fpk::kBlock)));
+    }
+    double work = 0.0;
+    auto launch = [&]() {
+        switch (kind) {
+            case 0:
+                hipLaunchKernelGGL(fpk::k_probe_fma64, dim3((unsigned)blocks), dim3(fpk::kBlock), 0, st, c->probe_out.p,
+                                   iters);
+                work = 2.0 * fpk::kProbeChains * (double)iters * (double)(blocks * fpk::kBlock);
+                break;
+            case 1:
+            case 2:
+            case 3: {
+                auto k = kind == 1 ? fpk::k_probe_mfma<0> : (kind == 2 ? fpk::k_probe_mfma<1> : fpk::k_probe_mfma<2>);
+                hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(fpk::kBlock), 0, st, c->probe_out.p, iters);
+                const double per = kind == 3 ? 16.0 * 16 * 32 * 2 : 16.0 * 16 * 4 * 2;
+                work = per * fpk::kProbeAcc * (double)iters * (double)(blocks * fpk::kWavesPerBlock);
+                break;
+            }
+            default:
+                hipLaunchKernelGGL(fpk::k_probe_copy, dim3((unsigned)(c->n_cu * 8)), dim3(fpk::kBlock), 0, st, src.p,
+                                   dst.p, n_copy);
+                work = 2.0 * (double)n_copy * sizeof(uint4);
+        }
+    };
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, FP_ERR_HIP, "hipEventCreate failed");
+    }
+    launch();  // untimed
+    double best = 0.0;
+    hipError_t err = hipGetLastError();
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        err = hipEventRecord(e0, st);
+        if (err == hipSuccess) launch();
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess && ms > 0.0f) best = std::max(best, work / (ms * 1e-3));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    src.release();
+    dst.release();
+    if (err != hipSuccess) return fail(c, FP_ERR_HIP, "peak probe: %s", hipGetErrorString(err));
+    *achieved = kind == 4 ? best / 1e9 : best / 1e12;  // GB/s or TFLOP/s
     return FP_OK;
 }
 

@@ -26,7 +26,7 @@ FP_NOALLOC_BYTES = 128 << 20
 EXPORTS = ["fp_create", "fp_destroy", "fp_last_error", "fp_load_modes", "fp_load_ifc", "fp_rates3", "fp_rates4",
            "fp_rates4_fused", "fp_rates_backward", "fp_kappa_rta", "fp_check", "fp_set_knob", "fp_get_knob", "fp_autotune", "fp_profile", "fp_profile_read",
            "fp_enumerate_count", "fp_enumerate_fill", "fp_set_broadening", "fp_rates_streamed", "fp_fused_counts",
-           "fp_ifc_info", "fp_rates4_noalloc"]
+           "fp_ifc_info", "fp_rates4_noalloc", "fp_peak_probe"]
 
 
 class FpError(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
             f.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp]
         L.fp_rates4_fused.argtypes = [vp, i64, vp, i32, i32, vp, dbl, dbl, i32, vp, vp, vp, vp]
         L.fp_fused_counts.argtypes = [vp, vp, vp]
+        L.fp_peak_probe.argtypes = [vp, i32, i32, vp, vp]
         L.fp_ifc_info.argtypes = [vp, i32, vp]
         L.fp_rates_backward.argtypes = [vp, ctypes.POINTER(fp_plist), i32, i32, vp, dbl, i32, vp, vp, vp, vp]
         L.fp_kappa_rta.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, vp]
@@ -259,6 +260,17 @@ def fp_ifc_info(ctx, order):
     _check(ctx, lib().fp_ifc_info(ctx, int(order), _hp(out)))
     return {"n_terms": int(out[0]), "n_keys": int(out[1]), "n_groups": int(out[2]), "n_pkeys": int(out[3]),
             "n_pgroups": int(out[4])}
+
+
+PROBES = {"fp64_vector_tflops": 0, "fp64_matrix_tflops": 1, "fp32_matrix_tflops": 2, "bf16_matrix_tflops": 3,
+          "hbm_copy_gbs": 4}
+
+
+def fp_peak_probe(ctx, kind, reps=3, stream=None):
+    """The device's measured peak for probe `kind` (0-3: TFLOP/s, 4: GB/s)."""
+    out = np.zeros(1, np.float64)
+    _check(ctx, lib().fp_peak_probe(ctx, int(kind), int(reps), _hp(out), _stream(stream)))
+    return float(out[0])
 
 
 def fp_fused_counts(ctx, stream=None):
