@@ -87,9 +87,10 @@ __device__ inline double fused_cut_bound(const double (&p1)[3], const double (&p
     return fmin(f.nsigma * sp * (1.0 + 1e-9), f.cut_max);
 }
 
-// not inlined: the exact width is needed only for the few candidates between
-// the two cuts, which each lane walks after its unrolled filter loop
-__device__ __noinline__ bool fused_adaptive_pass(double ad, int32_t g1, int32_t g2, int32_t g3, const FusedArgs& f,
+// The enumerator's own width test, for the candidates inside the bracket of
+// the table width (rare).  Inlined: as a call it cost the kernel a call frame
+// and register saves around the walk (8.60 s against 7.55 s for the 16^3 cell).
+__device__ inline bool fused_adaptive_pass(double ad, int32_t g1, int32_t g2, int32_t g3, const FusedArgs& f,
                                            const ModeGeom& geo) {
 #pragma clang fp contract(off)
     double s2 = fused_pair_sq(0.0, f.vel, g1, g2, f, geo);
