@@ -697,7 +697,8 @@ __global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fuse
                 uint64_t m[4] = {0, 0, 0, 0};
                 int32_t iq3_l = 0, qpk_l = 0;  // this lane's last q-point and packed signed q'' (form 2)
                 if (qv) {
-                    const int32_t q20 = iq2 / (N1 * N2), q21 = (iq2 / N2) % N1, q22 = iq2 % N2;
+                    int32_t q20, q21, q22;
+                    q_coords(iq2, geo, q20, q21, q22);
                     // s3 q''' = -(q + s1 q' + s2 q'')
                     const int32_t iq3 = (wrapn(s3 * -(q00 + s1 * q10 + s2 * q20), N0) * N1 +
                                          wrapn(s3 * -(q01 + s1 * q11 + s2 * q21), N1)) * N2 +

@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
             const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
             // decode: partners, signed wavevectors (as the forward does)
             const Proc pr = decode4(have, rec, s1, s2, s3, g0, c00, c01, c02, geo, a.n_modes, flag);
-            const uint64_t key = have ? (((uint64_t)(pr.g1 / nb) << 32) | (uint64_t)(pr.g2 / nb)) : ~0ull;
+            const uint64_t key = have ? (((uint64_t)mode_q(pr.g1, geo) << 32) | (uint64_t)mode_q(pr.g2, geo)) : ~0ull;
             const uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
             const bool first = have && (lane == 0 || key != up);
             const uint64_t mask = __ballot(first);

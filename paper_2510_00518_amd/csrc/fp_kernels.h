@@ -251,8 +251,33 @@ struct ModeGeom {
     int32_t N0, N1, N2, nb;
     int32_t L;
     uint32_t magic;
-    int32_t s0, s1, s2;  // L / N_d
+    int32_t s0, s1, s2;        // L / N_d
+    uint32_t m_nb, m_n2, m_n12;  // floor((2^32 - 1) / d) for d = nb, N2, N1 N2 (udivm)
 };
+
+// x / d for any x < 2^32, with m = floor((2^32 - 1) / d): x m / 2^32 falls short
+// of x / d by x (1 + e) / (d 2^32) < 1 (m d = 2^32 - 1 - e, e < d), so the high
+// product is the quotient or one less, and one remainder test fixes it.
+__device__ inline uint32_t udivm(uint32_t x, uint32_t d, uint32_t m) {
+    const uint32_t q = __umulhi(x, m);
+    return x - q * d >= d ? q + 1 : q;
+}
+
+// q-point index -> mesh coordinates (n0, n1, n2), iq = (n0 N1 + n1) N2 + n2
+__device__ inline void q_coords(int32_t iq, const ModeGeom& geo, int32_t& n0, int32_t& n1, int32_t& n2) {
+    const uint32_t n12 = (uint32_t)(geo.N1 * geo.N2);
+    const uint32_t a = udivm((uint32_t)iq, n12, geo.m_n12);
+    const uint32_t r = (uint32_t)iq - a * n12;
+    const uint32_t b = udivm(r, (uint32_t)geo.N2, geo.m_n2);
+    n0 = (int32_t)a;
+    n1 = (int32_t)b;
+    n2 = (int32_t)(r - b * (uint32_t)geo.N2);
+}
+
+// q-point of global mode g
+__device__ inline int32_t mode_q(int32_t g, const ModeGeom& geo) {
+    return (int32_t)udivm((uint32_t)g, (uint32_t)geo.nb, geo.m_nb);
+}
 
 // phit[row][k][c] = sum_{t in key k} exp(2 pi i q.C_t / L) sum_alpha phi_s[t][alpha][c] e_lambda(a0_t)_alpha
 template <int M>
@@ -355,9 +380,12 @@ __device__ inline void type_signs(int type, int& s1, int& s2, int& s3) {
 }
 
 __device__ inline int wrapn(int x, int n) {
-    // x in (-2n, 2n)
-    x = x % n;
-    return x < 0 ? x + n : x;
+    // x mod n for x in (-4n, 4n) (every caller passes a sum of at most three
+    // mesh coordinates, signed): two folds by 2n, then one by n
+    x = x < 0 ? x + 2 * n : x;
+    x = x < 0 ? x + 2 * n : x;
+    x = x >= 2 * n ? x - 2 * n : x;
+    return x >= n ? x - n : x;
 }
 
 // One listed process as seen by one lane: partner modes, signed partner
@@ -389,9 +417,9 @@ __device__ inline Proc decode4(bool have, uint64_t rec, int s1, int s2, int s3, 
         raise_flag(flag);
         return p;
     }
-    const int32_t iq1 = g1 / nb, iq2 = g2 / nb;
-    const int32_t c10 = iq1 / (geo.N1 * geo.N2), c11 = (iq1 / geo.N2) % geo.N1, c12 = iq1 % geo.N2;
-    const int32_t c20 = iq2 / (geo.N1 * geo.N2), c21 = (iq2 / geo.N2) % geo.N1, c22 = iq2 % geo.N2;
+    int32_t c10, c11, c12, c20, c21, c22;
+    q_coords(mode_q(g1, geo), geo, c10, c11, c12);
+    q_coords(mode_q(g2, geo), geo, c20, c21, c22);
     p.Q10 = s1 > 0 ? c10 : wrapn(-c10, geo.N0);
     p.Q11 = s1 > 0 ? c11 : wrapn(-c11, geo.N1);
     p.Q12 = s1 > 0 ? c12 : wrapn(-c12, geo.N2);
@@ -412,7 +440,6 @@ __device__ inline Proc decode4(bool have, uint64_t rec, int s1, int s2, int s3, 
     return p;
 }
 
-// squared distance of two projection rows (three directions)
 // pm[iq] = (max over the branches j of |proj[iq nb + j][d]|, d = 0, 1, 2; 0)
 __global__ void k_proj_max(const double* __restrict__ proj, int64_t nq, int nb, double* __restrict__ pm) {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
@@ -440,6 +467,7 @@ __device__ inline double proj_sq4(const Proj4& x, const Proj4& y) {
     return d0 * d0 + d1 * d1 + d2 * d2;
 }
 
+// squared distance of two projection rows (three directions)
 __device__ inline double proj_sq(const double* __restrict__ proj, int32_t gi, int32_t gj) {
     const double2 a01 = *reinterpret_cast<const double2*>(proj + (size_t)gi * 4);
     const double2 b01 = *reinterpret_cast<const double2*>(proj + (size_t)gj * 4);
@@ -473,14 +501,14 @@ __device__ inline Proc setup_proc(bool have, uint64_t rec, int type, int s1, int
         return p;
     }
     // signed wavevectors of the listed partners; the last partner follows from momentum
-    const int32_t iq1 = g1 / nb;
-    const int32_t c10 = iq1 / (geo.N1 * geo.N2), c11 = (iq1 / geo.N2) % geo.N1, c12 = iq1 % geo.N2;
+    int32_t c10, c11, c12;
+    q_coords(mode_q(g1, geo), geo, c10, c11, c12);
     p.Q10 = s1 > 0 ? c10 : wrapn(-c10, geo.N0);
     p.Q11 = s1 > 0 ? c11 : wrapn(-c11, geo.N1);
     p.Q12 = s1 > 0 ? c12 : wrapn(-c12, geo.N2);
     if (M == 4) {
-        const int32_t iq2 = g2 / nb;
-        const int32_t c20 = iq2 / (geo.N1 * geo.N2), c21 = (iq2 / geo.N2) % geo.N1, c22 = iq2 % geo.N2;
+        int32_t c20, c21, c22;
+        q_coords(mode_q(g2, geo), geo, c20, c21, c22);
         p.Q20 = s2 > 0 ? c20 : wrapn(-c20, geo.N0);
         p.Q21 = s2 > 0 ? c21 : wrapn(-c21, geo.N1);
         p.Q22 = s2 > 0 ? c22 : wrapn(-c22, geo.N2);

@@ -265,6 +265,9 @@ fpk::ModeGeom geometry(const fp_ctx* c) {
     g.s0 = c->L / c->mesh[0];
     g.s1 = c->L / c->mesh[1];
     g.s2 = c->L / c->mesh[2];
+    g.m_nb = 0xFFFFFFFFu / (uint32_t)c->nb;
+    g.m_n2 = 0xFFFFFFFFu / (uint32_t)c->mesh[2];
+    g.m_n12 = 0xFFFFFFFFu / (uint32_t)(c->mesh[1] * c->mesh[2]);
     return g;
 }
 

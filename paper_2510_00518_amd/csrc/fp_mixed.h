@@ -151,7 +151,7 @@ __device__ inline void tbm_batch(const uint64_t (&rec)[kBR], int count, int32_t 
         have[k] = idx < count;
         pr[k] = setup_proc<4>(have[k], rec[k], type, s1, s2, s3, g0, c00, c01, c02, w0, geo, omega, a.n_modes,
                               flag, a.br);
-        const uint64_t key = have[k] ? (((uint64_t)(pr[k].g1 / nb) << 32) | (uint64_t)(pr[k].g2 / nb))
+        const uint64_t key = have[k] ? (((uint64_t)mode_q(pr[k].g1, geo) << 32) | (uint64_t)mode_q(pr[k].g2, geo))
                                      : ~0ull;
         uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
         if (lane == 0) up = prev_last;
