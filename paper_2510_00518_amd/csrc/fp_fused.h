@@ -47,6 +47,7 @@ struct FusedArgs {
     const double* proj_max;  // per q-point: the largest |proj_d| over its branches
     double recip[9];
     double factor, sigma, nsigma, cut_max;
+    double wmin, wmax;  // smallest active and largest frequency of the mesh (unit bound)
     // bound on |norm of the nine pair projections from the per-mode table P
     // minus the same norm in the enumerator's arithmetic| (3e-12 max_g,d
     // sum_k |v_gk b_dk| / N_d: several hundred times the rounding of either)
@@ -621,9 +622,26 @@ __global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fuse
             double w1[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) w1[j] = omega[iq1 * NB + j];
-            double w1max = w1[0];
+            double w1max = w1[0], w1min = w1[0];
 #pragma unroll
-            for (int j = 1; j < NB; ++j) w1max = fmax(w1max, w1[j]);
+            for (int j = 1; j < NB; ++j) {
+                w1max = fmax(w1max, w1[j]);
+                w1min = fmin(w1min, w1[j]);
+            }
+            // Unit bound: every mismatch of the unit lies in [lo, hi] (the first
+            // partner from the branches of q', the other two from the mesh's extreme
+            // frequencies, summed in the filter's order; rounding is monotone).  A
+            // unit whose interval misses the widest cut keeps nothing, so it skips
+            // the fold and the q'' loop (most ++ and many -- units).
+            const double cut_u = (ADAPT ? f.cut_max : f.cut) + 1e-9 * (w0 + w1max + 2.0 * f.wmax);
+            double lo = s1 > 0 ? w0 + w1min : w0 - w1max;
+            lo = s2 > 0 ? lo + f.wmin : lo - f.wmax;
+            lo = s3 > 0 ? lo + f.wmin : lo - f.wmax;
+            double hi = s1 > 0 ? w0 + w1max : w0 - w1min;
+            hi = s2 > 0 ? hi + f.wmax : hi - f.wmin;
+            hi = s3 > 0 ? hi + f.wmax : hi - f.wmin;
+            const bool live = lo <= cut_u && hi >= -cut_u;
+            if (live) {
             double pm1[3] = {0.0, 0.0, 0.0};
             if (ADAPT)
                 for (int d = 0; d < 3; ++d) pm1[d] = f.proj_max[(int64_t)iq1 * 4 + d];
@@ -937,6 +955,7 @@ __global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fuse
                 } while (used < total);
                 if (last) break;
             }
+            }  // live
         }
         double* out = partial + u * (2 * a.n_T);
         if constexpr (XF) {

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -1408,6 +1409,13 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     f.n_rows = n_rows;
     f.n_units = (int64_t)f.n_types * n_rows * c->nq;
     f.floor_ = c->floor_;
+    // extreme frequencies of the mesh for the kernel's unit bound (active modes for the minimum)
+    f.wmin = std::numeric_limits<double>::infinity();
+    f.wmax = 0.0;
+    for (double w : c->h_omega) {
+        if (w >= c->floor_) f.wmin = std::min(f.wmin, w);
+        f.wmax = std::max(f.wmax, w);
+    }
     f.cut = nsigma * sigma;
     if (c->adaptive) {
         // the enumerator's rule; cut_max bounds nsigma * sigma_p over every process
