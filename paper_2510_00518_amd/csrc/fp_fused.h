@@ -1014,6 +1014,25 @@ __global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fuse
     }
 }
 
+// parts[b] = sum of block b's slice of v[0..n) (slices of ceil(n / blocks)); a
+// second k_sum_i64 over the parts gives the total (integer sums are exact in any
+// order).
+__global__ void k_sum_i64_parts(const int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ parts) {
+    __shared__ int64_t red[kBlock];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    int64_t s = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+}
+
 // out[0] = sum of v[0..n), one block, fixed order.
 __global__ void k_sum_i64(const int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ out) {
     __shared__ int64_t red[kBlock];

@@ -197,6 +197,7 @@ struct fp_ctx {
     DevBuf<double> gpart;
     DevBuf<double> gslab;       // first level of the partial-gradient reduction
     DevBuf<double> probe_out;   // results of the peak probes (one per thread)
+    DevBuf<int64_t> sum_parts;  // per-block parts of the fused call's kept and tuple counts
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
     DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
     DevBuf<double2> fold;     // fused FP64 path: one folded force-constant table per wave
@@ -340,7 +341,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->proj.release(); c->proj_max.release();
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
-    c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release(); c->gslab.release(); c->probe_out.release();
+    c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release(); c->gslab.release(); c->probe_out.release(); c->sum_parts.release();
     c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release(); c->occt.release();
     c->ev_val.release(); c->ev_key[0].release(); c->ev_key[1].release(); c->ev_idx[0].release();
     c->ev_idx[1].release(); c->ev_tmp.release(); c->unit_kept.release();
@@ -1493,10 +1494,18 @@ extern "C" fp_status fp_rates4_fused(fp_ctx* c, int64_t n_rows, const int32_t* r
     if (ts != FP_OK) return ts;
     const double pref = rate_prefactor(c, 4);
     const double wpref = 1.0 / ((double)c->nq * (double)c->nq);
+    // kept processes and tuples of the call: per-block parts, then one block over the parts
+    constexpr int kParts = 256;
+    HIP_TRY(c, c->sum_parts.ensure(2 * kParts));
+    hipLaunchKernelGGL(fpk::k_sum_i64_parts, dim3(kParts), dim3(fpk::kBlock), 0, st, c->unit_kept.p, f.n_units,
+                       c->sum_parts.p);
+    hipLaunchKernelGGL(fpk::k_sum_i64_parts, dim3(kParts), dim3(fpk::kBlock), 0, st, c->unit_tup.p, f.n_units,
+                       c->sum_parts.p + kParts);
     if (n_kept)
-        hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->unit_kept.p, f.n_units, n_kept);
-    hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->unit_kept.p, f.n_units, c->fused_cnt.p);
-    hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->unit_tup.p, f.n_units,
+        hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->sum_parts.p, (int64_t)kParts, n_kept);
+    hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->sum_parts.p, (int64_t)kParts,
+                       c->fused_cnt.p);
+    hipLaunchKernelGGL(fpk::k_sum_i64, dim3(1), dim3(fpk::kBlock), 0, st, c->sum_parts.p + kParts, (int64_t)kParts,
                        c->fused_cnt.p + 1);
     c->fused_done = true;
     // one finalize launch per type: rows of one mode in different types add into the same outputs
