@@ -55,6 +55,7 @@ __device__ inline const int32_t* tb_stage(double2* sroots, const double2* __rest
 // build A_g per tuple and partner group on FP64 MFMA, contract per process on
 // the VALU, weight in FP64.  Adds this lane's Gamma and WP terms into
 // accg/accw; with GRAD it also writes h_p = c_p conj(V_p) to hout[k * 64 + lane]
+// and the record's decoding (last partner, packed signed wavevectors) to dout
 // for the valid records, c_p = 2 pref w G / prod(omega) sum_T dl[T] occ_T.
 // g0, type and count are wave-uniform; A and Qs are this wave's LDS staging.
 // FOLD (the fused path, where every record of the batch shares q'): `groups`
@@ -69,7 +70,7 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
                                 const int32_t* __restrict__ tmeta, const int32_t* __restrict__ groups,
                                 int* __restrict__ flag, const RatesArgs& a, const double2* sroots, double2 (*A)[27],
                                 int32_t (*Qs)[2], double (&accg)[MAXT], double (&accw)[MAXT], const double (&dl)[MAXT],
-                                double pref, double2* __restrict__ hout) {
+                                double pref, double2* __restrict__ hout, uint4* __restrict__ dout = nullptr) {
     const int lane = threadIdx.x & (kWave - 1);
     const int li = lane & 15, lk = lane >> 4;
     const ModeGeom& geo = a.geo;
@@ -298,6 +299,9 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
         if (GRAD && have[k]) {
             cw *= 2.0 * pref * pr[k].base;
             hout[k * kWave + lane] = make_double2(cw * V[k].x, -cw * V[k].y);
+            dout[k * kWave + lane] = make_uint4((uint32_t)pr[k].gl,
+                                                (uint32_t)(pr[k].Q10 | (pr[k].Q11 << 10) | (pr[k].Q12 << 20)),
+                                                (uint32_t)(pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20)), 0u);
         }
     }
 }
@@ -309,7 +313,8 @@ __device__ inline void tb_batch(const uint64_t (&rec)[BR], int count, int32_t g0
 // OCC resident blocks per CU.  The root table is dynamic LDS of L entries.
 template <int MAXT, bool GRAD, int BR = kBR, int TB = kTB, int OCC = 2>
 __global__ __launch_bounds__(kBlock, OCC) void k_rates4b(FP_RATES_PARAMS, const double* __restrict__ dldg,
-                                                                      double pref, double2* __restrict__ hbuf) {
+                                                                      double pref, double2* __restrict__ hbuf,
+                                                                      uint4* __restrict__ hdec) {
     extern __shared__ double2 sroots[];
     __shared__ double2 sA[kWavesPerBlock][TB][27];
     __shared__ int32_t sQ[kWavesPerBlock][TB][2];
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_rates4b(FP_RATES_PARAMS, const 
             for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
             tb_batch<MAXT, GRAD, BR, TB>(rec, count, g0, type, phit + (int64_t)row * a.n_keys * 27, omega, evec, occ, tm,
                                  groups, flag, a, sroots, sA[wave], sQ[wave], accg, accw, dl, pref,
-                                 GRAD ? hbuf + ri.hbase + ud.start : nullptr);
+                                 GRAD ? hbuf + ri.hbase + ud.start : nullptr, GRAD ? hdec + ri.hbase + ud.start : nullptr);
         }
         if (GRAD) continue;
         double* out = partial + u * (2 * a.n_T);

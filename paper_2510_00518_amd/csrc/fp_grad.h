@@ -302,7 +302,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
                                                      const double* __restrict__ tscale,
                                                      const RowInfo* __restrict__ rows,
                                                      const UnitDesc* __restrict__ units,
-                                                     const double2* __restrict__ hbuf, double* __restrict__ gpart,
+                                                     const double2* __restrict__ hbuf,
+                                                     const uint4* __restrict__ hdec, double* __restrict__ gpart,
                                                      int* __restrict__ flag, GradArgs a) {
     extern __shared__ double2 sroots[];  // L roots of unity (dynamic: sized by the launch)
     __shared__ double2 sU[kWavesPerBlock][kWave][3];  // h x_b per record
@@ -364,8 +365,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
             const int idx = sub + lane;
             const bool have = lane < n_here;
             const uint64_t rec = have ? ri.rec[ud.start + idx] : 0;
-            // decode: partners, signed wavevectors (as the forward does)
-            const Proc pr = decode4(have, rec, s1, s2, s3, g0, c00, c01, c02, geo, a.n_modes, flag);
+            // the first pass decoded the record (last partner closed by momentum,
+            // signed wavevectors packed as the phase index needs them); a record it
+            // found out of range has h = 0 and is read with the row's mode
+            Proc pr;
+            {
+                const uint4 dv = have ? hdec[ri.hbase + ud.start + idx] : make_uint4((uint32_t)g0, 0u, 0u, 0u);
+                pr.g1 = (int32_t)(rec & 0xFFFFFFu);
+                pr.g2 = (int32_t)((rec >> 24) & 0xFFFFFFu);
+                if (!have || pr.g1 >= a.n_modes || pr.g2 >= a.n_modes) pr.g1 = pr.g2 = g0;
+                pr.gl = (int32_t)dv.x;
+                pr.Q10 = (int32_t)dv.y;  // packed Q1 (10 bits per axis)
+                pr.Q20 = (int32_t)dv.z;  // packed Q2
+            }
             const uint64_t key = have ? (((uint64_t)mode_q(pr.g1, geo) << 32) | (uint64_t)mode_q(pr.g2, geo)) : ~0ull;
             const uint64_t up = __shfl(key, (lane + kWave - 1) & (kWave - 1), kWave);
             const bool first = have && (lane == 0 || key != up);
@@ -375,8 +387,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_grad4t(const double2* __restrict_
             const int n_tup = __builtin_amdgcn_readfirstlane(__popcll(mask));
             if (first) {
                 T[slot] = lane;
-                Qs[slot][0] = pr.Q10 | (pr.Q11 << 10) | (pr.Q12 << 20);
-                Qs[slot][1] = pr.Q20 | (pr.Q21 << 10) | (pr.Q22 << 20);
+                Qs[slot][0] = pr.Q10;
+                Qs[slot][1] = pr.Q20;
             }
             if (lane == 0) T[n_tup] = n_here;
             // this lane's record: h_p x_b and y_g z_d for the group's partner atoms

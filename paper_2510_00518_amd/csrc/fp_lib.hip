@@ -199,7 +199,8 @@ struct fp_ctx {
     DevBuf<double> probe_out;   // results of the peak probes (one per thread)
     DevBuf<int64_t> sum_parts;  // per-block parts of the fused call's kept and tuple counts
     DevBuf<double> tune_out;  // scratch output of the autotuner's trial launches
-    DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of the call
+    DevBuf<double2> hbuf;     // adjoint: c_p conj(V_p) per record of a range
+    DevBuf<uint4> hdec;       // adjoint: each record's last partner and packed signed wavevectors
     DevBuf<double2> fold;     // fused FP64 path: one folded force-constant table per wave
     DevBuf<double> occt;      // fused form 2: occupations, temperature-fastest
     DevBuf<double> ev_val;    // three-phonon events: partner contributions per record
@@ -342,7 +343,7 @@ extern "C" void fp_destroy(fp_ctx* c) {
     c->ifc[0].release(); c->ifc[1].release();
     c->occ.release(); c->partial.release(); c->rows.release(); c->row_units.release();
     c->unit_off.release(); c->units.release(); c->phit.release(); c->gpart.release(); c->gslab.release(); c->probe_out.release(); c->sum_parts.release();
-    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->fold.release(); c->occt.release();
+    c->fsp.release(); c->tune_out.release(); c->hbuf.release(); c->hdec.release(); c->fold.release(); c->occt.release();
     c->ev_val.release(); c->ev_key[0].release(); c->ev_key[1].release(); c->ev_idx[0].release();
     c->ev_idx[1].release(); c->ev_tmp.release(); c->unit_kept.release();
     c->unit_tup.release(); c->fused_cnt.release();
@@ -802,7 +803,7 @@ fp_status launch_mixed(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::Ra
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec32.p, c->occ.p,
                        c->roots.p, c->fsp.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
-                       S.n_kblk, (const double*)nullptr, 0.0, (double2*)nullptr);
+                       S.n_kblk, (const double*)nullptr, 0.0, (double2*)nullptr, (uint4*)nullptr);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -820,7 +821,7 @@ fp_status launch_mixed_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), 0, st, c->omega.p, c->evec32.p, c->occ.p,
                        c->roots.p, c->fsp.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
-                       S.n_kblk, dldg, pref, c->hbuf.p);
+                       S.n_kblk, dldg, pref, c->hbuf.p, c->hdec.p);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -838,7 +839,7 @@ fp_status launch_batched(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk::
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
-                       (const double*)nullptr, 0.0, (double2*)nullptr);
+                       (const double*)nullptr, 0.0, (double2*)nullptr, (uint4*)nullptr);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -859,7 +860,7 @@ fp_status launch_batched_h(fp_ctx* c, hipStream_t st, int64_t n_units, const fpk
     nblk = std::max<int64_t>(fpk::kXcd, (nblk + fpk::kXcd - 1) / fpk::kXcd * fpk::kXcd);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->omega.p, c->evec.p, c->occ.p,
                        c->roots.p, c->phit.p, S.tmeta.p, S.groups.p, c->rows.p, c->units.p, c->partial.p, c->flag, a,
-                       dldg, pref, c->hbuf.p);
+                       dldg, pref, c->hbuf.p, c->hdec.p);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -1193,7 +1194,7 @@ fp_status launch_grad4t(fp_ctx* c, hipStream_t st, const Prepared& pp, const fpk
     const int64_t want = (n_items + fpk::kWavesPerBlock - 1) / fpk::kWavesPerBlock;
     const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(cap, want));
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(fpk::kBlock), shm, st, c->evec.p, c->roots.p, S.tmeta.p, S.tc.p,
-                       S.groups.p, S.scale.p, c->rows.p, c->units.p, c->hbuf.p, c->gpart.p, c->flag, a);
+                       S.groups.p, S.scale.p, c->rows.p, c->units.p, c->hbuf.p, c->hdec.p, c->gpart.p, c->flag, a);
     HIP_TRY(c, hipGetLastError());
     return FP_OK;
 }
@@ -1768,6 +1769,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
                 max_range = std::max(max_range, nr);
             }
             HIP_TRY(c, c->hbuf.ensure((size_t)max_range));
+            HIP_TRY(c, c->hdec.ensure((size_t)max_range));
             const double pref4 = rate_prefactor(c, m);
             int64_t n_waves = 0;
             ps = grad4t_begin(c, st, S, &n_waves);
@@ -1794,6 +1796,7 @@ extern "C" fp_status fp_rates_backward(fp_ctx* c, const fp_plist* lists, int32_t
                 ps = prepare(c, m, sub.data(), all, n_T, T_K, fpk::kBR * fpk::kWave, st, &pp, &shift);
                 if (ps != FP_OK) return ps;
                 HIP_TRY(c, c->hbuf.ensure((size_t)std::max<int64_t>(n_sub, 1)));
+                HIP_TRY(c, c->hdec.ensure((size_t)std::max<int64_t>(n_sub, 1)));
                 fpk::RatesArgs ra;
                 memset(&ra, 0, sizeof ra);
                 ra.n_units = pp.n_units;

@@ -125,7 +125,8 @@ __device__ inline void tbm_batch(const uint64_t (&rec)[kBR], int count, int32_t 
                                  const int32_t* __restrict__ tmeta, const int32_t* __restrict__ groups,
                                  int* __restrict__ flag, const RatesArgs& a, const uint4* sroot, float2 (*A)[27],
                                  int32_t (*Qs)[2], double (&accg)[MAXT], double (&accw)[MAXT],
-                                 const double (&dl)[MAXT], double pref, double2* __restrict__ hout) {
+                                 const double (&dl)[MAXT], double pref, double2* __restrict__ hout,
+                                 uint4* __restrict__ dout = nullptr) {
     const int lane = threadIdx.x & (kWave - 1);
     const int li = lane & 15, lk = lane >> 4;
     const ModeGeom& geo = a.geo;
@@ -328,6 +329,9 @@ __device__ inline void tbm_batch(const uint64_t (&rec)[kBR], int count, int32_t 
         if (GRAD && have[k]) {
             cw *= 2.0 * pref * pr[k].base;
             hout[k * kWave + lane] = make_double2(cw * vx, -cw * vy);
+            dout[k * kWave + lane] = make_uint4((uint32_t)pr[k].gl,
+                                                (uint32_t)(pr[k].Q10 | (pr[k].Q11 << 10) | (pr[k].Q12 << 20)),
+                                                (uint32_t)(pr[k].Q20 | (pr[k].Q21 << 10) | (pr[k].Q22 << 20)), 0u);
         }
     }
 }
@@ -348,7 +352,8 @@ __device__ inline void tbm_roots(uint4* sroot, const double2* __restrict__ roots
 // mixed-precision contraction), as the FP64 tuple-batched kernel does.
 template <int MAXT, bool GRAD>
 __global__ __launch_bounds__(kBlock, 2) void k_rates4m(FP_RATES_MIXED_PARAMS, const double* __restrict__ dldg,
-                                                      double pref, double2* __restrict__ hbuf) {
+                                                      double pref, double2* __restrict__ hbuf,
+                                                      uint4* __restrict__ hdec) {
     __shared__ uint4 sroot[kMaxRoots];  // word s = bf16 split s of (Re, Im) of the root
     __shared__ float2 sA[kWavesPerBlock][kTB][27];
     __shared__ int32_t sQ[kWavesPerBlock][kTB][2];
@@ -387,7 +392,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_rates4m(FP_RATES_MIXED_PARAMS, co
             for (int it = 0; it < MAXT; ++it) dl[it] = (GRAD && it < a.n_T) ? dldg[(int64_t)it * a.n_modes + g0] : 0.0;
             tbm_batch<MAXT, GRAD>(rec, count, g0, type, fsp + (int64_t)row * n_kblk * 4 * kWave * 3, omega, evec32, occ,
                                   tmeta, groups, flag, a, sroot, A, Qs, accg, accw, dl, pref,
-                                  GRAD ? hbuf + ri.hbase + ud.start : nullptr);
+                                  GRAD ? hbuf + ri.hbase + ud.start : nullptr,
+                                  GRAD ? hdec + ri.hbase + ud.start : nullptr);
         }
         if (GRAD) continue;
         double* out = partial + u * (2 * a.n_T);
