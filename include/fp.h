@@ -379,9 +379,9 @@ fp_status fp_kappa_rta(fp_ctx* ctx, int32_t n_q1, const int32_t* q1, const doubl
  *                    lane (7)
  *   "grad_chunk"     records per adjoint work chunk, a multiple of 256 (default 4096)
  *   "grad_records"   records per order-4 adjoint pass, 1024..2^34 (default
- *                    2^25, 512 MiB of buffer): rows are taken in ranges of at most this many
+ *                    2^25, 1 GiB of buffer): rows are taken in ranges of at most this many
  *                    records (a longer row alone), so the per-record adjoint
- *                    buffer holds one range (16 bytes per record), not the
+ *                    buffers hold one range (32 bytes per record), not the
  *                    whole call; the gradient is summed over the ranges in order
  *   "fused_form"     FP64 form of fp_rates4_fused: 0 = phase keys folded over
  *                    A per (lambda, q') unit, 2 (the default) = keys and the

@@ -216,7 +216,7 @@ struct fp_ctx {
     int32_t blocks_per_cu = 0;  // 0: as many resident blocks as the kernel's occupancy allows
     int32_t variant = 6;        // order-4 contraction form: 0-3 per-process (k_rates), 4-7 tuple-batched
     int32_t grad_chunk = 4096;  // records per adjoint chunk (a multiple of 256)
-    int64_t grad_records = int64_t(1) << 25;  // records per order-4 adjoint pass (bounds the h buffer: 512 MiB)
+    int64_t grad_records = int64_t(1) << 25;  // records per order-4 adjoint pass (bounds the h buffers: 1 GiB)
     int32_t fused_form = 2;     // FP64 form of fp_rates4_fused: 0 B-keys, 2 first partner folded
     // kernel timing
     bool profile = false;
