@@ -760,33 +760,42 @@ __global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fuse
                     const double lo3 = s3 > 0 ? mn3 : -mx3, hi3 = s3 > 0 ? mx3 : -mn3;
                     const double marg = 1e-9 * (w0 + w1max + mx2 + mx3);
                     const double cmax = (ADAPT ? cut_q : f.cut) + marg;
+                    // per lane, once: the signed frequencies of slots 2 and 3 (a - b is
+                    // a + (-b), so the mismatch keeps its bits), their floor tests, and
+                    // the triangle order of q'' against q' and of q''' against q''
+                    double sw2[NB], sw3[NB];
+                    bool ok2f[NB], ok3f[NB];
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        sw2[j] = s2 > 0 ? w2[j] : -w2[j];
+                        sw3[j] = s3 > 0 ? w3[j] : -w3[j];
+                        ok2f[j] = w2[j] >= f.floor_;
+                        ok3f[j] = w3[j] >= f.floor_;
+                    }
+                    const bool lt21 = iq2 < iq1, eq21 = iq2 == iq1;
+                    const bool lt32 = iq3 < iq2, eq32 = iq3 == iq2;
 #pragma unroll
                     for (int j1 = 0; j1 < NB; ++j1) {
-                        const int32_t g1 = iq1 * NB + j1;
                         const bool ok1 = w1[j1] >= f.floor_;
                         const double d1 = s1 > 0 ? w0 + w1[j1] : w0 - w1[j1];
                         if (!__ballot(ok1 && d1 + lo2 + lo3 <= cmax && d1 + hi2 + hi3 >= -cmax)) continue;
 #pragma unroll
                         for (int j2 = 0; j2 < NB; ++j2) {
-                            const int32_t g2 = iq2 * NB + j2;
-                            const bool ok2 = ok1 && !(tri12 && g2 < g1) && w2[j2] >= f.floor_;
-                            const double d2 = s2 > 0 ? d1 + w2[j2] : d1 - w2[j2];
+                            // g2 < g1 <=> q'' before q', or the same q-point and j'' < j'
+                            const bool below1 = lt21 || (eq21 && j2 < j1);
+                            const bool ok2 = ok1 && !(tri12 && below1) && ok2f[j2];
+                            const double d2 = d1 + sw2[j2];
                             if (!__ballot(ok2 && d2 + lo3 <= cmax && d2 + hi3 >= -cmax)) continue;
 #pragma unroll
                             for (int j3 = 0; j3 < NB; ++j3) {
-                                const int32_t g3 = iq3 * NB + j3;
-                                const double delta = s3 > 0 ? d2 + w3[j3] : d2 - w3[j3];
-                                bool keep = ok2 && !(tri23 && g3 < g2) && w3[j3] >= f.floor_;
-                                bool exact = false;
-                                if (keep) {
-                                    const double ad = fabs(delta);
-                                    // sigma_p >= sigma, so the fixed cut keeps without the width
-                                    keep = ad <= f.cut;
-                                    if (ADAPT) exact = !keep && ad <= cut_q;
-                                }
+                                const bool below2 = lt32 || (eq32 && j3 < j2);
+                                const double ad = fabs(d2 + sw3[j3]);
+                                const bool ok = ok2 && !(tri23 && below2) && ok3f[j3];
+                                // sigma_p >= sigma, so the fixed cut keeps without the width
+                                const bool keep = ok && ad <= f.cut;
                                 const int c = (j1 * NB + j2) * NB + j3;
                                 if (keep) m[c >> 6] |= 1ull << (c & 63);
-                                if (ADAPT && exact) xm[c >> 6] |= 1ull << (c & 63);
+                                if (ADAPT && ok && !keep && ad <= cut_q) xm[c >> 6] |= 1ull << (c & 63);
                             }
                         }
                     }
