@@ -279,12 +279,14 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], const int32_t (&qpk
         const int n_ks = (p1 - p0 + 3) >> 2;  // <= kMaxKs: groups hold at most 16 pkeys
         for (int tb = 0; tb < n_tup; tb += kXTB) {
             const int nbt = n_tup - tb < kXTB ? n_tup - tb : kXTB;
+            if (gi == 0 || n_tup > kXTB) {  // one tile: the staged q'' of the first group serve all
 #pragma unroll
-            for (int k = 0; k < kBR; ++k) {
-                const int s = slot[k] - tb;
-                if (first[k] && s >= 0 && s < kXTB) Qs[s] = qpk[k];
+                for (int k = 0; k < kBR; ++k) {
+                    const int s = slot[k] - tb;
+                    if (first[k] && s >= 0 && s < kXTB) Qs[s] = qpk[k];
+                }
+                lds_fence();
             }
-            lds_fence();
             // A_p for this tile: two passes of two M-tiles (Karatsuba, three real
             // MFMAs per complex product: k1 = (Fr + Fi) pr, k2 = Fr (pi - pr),
             // k3 = Fi (pr + pi); Re = k1 - k3, Im = k1 + k2)
@@ -773,12 +775,13 @@ __global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fuse
                         ok3f[j] = w3[j] >= f.floor_;
                     }
                     const bool lt21 = iq2 < iq1, eq21 = iq2 == iq1;
+                    const double lo23 = lo2 + lo3, hi23 = hi2 + hi3;  // pruning bounds (the margin covers the regrouping)
                     const bool lt32 = iq3 < iq2, eq32 = iq3 == iq2;
 #pragma unroll
                     for (int j1 = 0; j1 < NB; ++j1) {
                         const bool ok1 = w1[j1] >= f.floor_;
                         const double d1 = s1 > 0 ? w0 + w1[j1] : w0 - w1[j1];
-                        if (!__ballot(ok1 && d1 + lo2 + lo3 <= cmax && d1 + hi2 + hi3 >= -cmax)) continue;
+                        if (!__ballot(ok1 && d1 + lo23 <= cmax && d1 + hi23 >= -cmax)) continue;
 #pragma unroll
                         for (int j2 = 0; j2 < NB; ++j2) {
                             // g2 < g1 <=> q'' before q', or the same q-point and j'' < j'
