@@ -72,6 +72,10 @@ struct Enum {
     bool adaptive;
     const double* vel;
     double recip[9], factor, sigma, nsigma, cut_max;
+    // frequency bounds (order 4): per q-point the smallest and largest branch
+    // frequency, and over the mesh the smallest active and the largest one
+    std::vector<double> wlo, whi;
+    double wmin_act = 0.0, wmax_all = 0.0;
 
     // squared projections of one partner pair, summed over the three directions
     // into s2 in order
@@ -161,8 +165,26 @@ struct Enum {
         }
         const bool tri12 = (s[1] == s[2]);            // ++ and --: g' <= g''
         const bool tri23 = (s[2] == s[3]);            // +- and --: g'' <= g'''
+        // Frequency bounds skip blocks of candidates that cannot pass: with the
+        // partners' frequencies between their q-point's (or the mesh's) extremes,
+        // every mismatch of a block lies in an interval (sums in the filter's
+        // order; rounding is monotone, and a 1e-9 relative margin is added), and
+        // a block whose interval misses the widest cut holds no kept record.  The
+        // decisions and the order of the kept records are the filter's own.
+        const double cut_any = adaptive ? cut_max : cut;
         // q-point pairs outermost, so the records of one (q', q'') tuple are contiguous
         for (int64_t iq1 = 0; iq1 < nq; ++iq1) {
+            {
+                const double w1l = wlo[(size_t)iq1], w1h = whi[(size_t)iq1];
+                double lo = s[1] > 0 ? w0 + w1l : w0 - w1h;
+                lo = s[2] > 0 ? lo + wmin_act : lo - wmax_all;
+                lo = s[3] > 0 ? lo + wmin_act : lo - wmax_all;
+                double hi = s[1] > 0 ? w0 + w1h : w0 - w1l;
+                hi = s[2] > 0 ? hi + wmax_all : hi - wmin_act;
+                hi = s[3] > 0 ? hi + wmax_all : hi - wmin_act;
+                const double cu = cut_any + 1e-9 * (w0 + w1h + 2.0 * wmax_all);
+                if (lo > cu || hi < -cu) continue;
+            }
             int64_t q1[3];
             coords(iq1, q1);
             for (int64_t iq2 = tri12 ? iq1 : 0; iq2 < nq; ++iq2) {
@@ -171,17 +193,24 @@ struct Enum {
                 coords(iq2, q2);
                 for (int d = 0; d < 3; ++d) q3[d] = s[3] * (-(q0[d] + s[1] * q1[d] + s[2] * q2[d]));
                 const int64_t iq3 = index(q3);
+                const double lo2 = s[2] > 0 ? wlo[(size_t)iq2] : -whi[(size_t)iq2];
+                const double hi2 = s[2] > 0 ? whi[(size_t)iq2] : -wlo[(size_t)iq2];
+                const double lo3 = s[3] > 0 ? wlo[(size_t)iq3] : -whi[(size_t)iq3];
+                const double hi3 = s[3] > 0 ? whi[(size_t)iq3] : -wlo[(size_t)iq3];
+                const double cmax = cut_any + 1e-9 * (w0 + whi[(size_t)iq1] + whi[(size_t)iq2] + whi[(size_t)iq3]);
                 for (int32_t j1 = 0; j1 < nb; ++j1) {
                     const int64_t g1 = iq1 * nb + j1;
                     const double w1 = omega[g1];
                     if (!(w1 >= floor_)) continue;
                     const double d1 = s[1] > 0 ? w0 + w1 : w0 - w1;
+                    if (d1 + lo2 + lo3 > cmax || d1 + hi2 + hi3 < -cmax) continue;
                     for (int32_t j2 = 0; j2 < nb; ++j2) {
                         const int64_t g2 = iq2 * nb + j2;
                         if (tri12 && g2 < g1) continue;
                         const double w2 = omega[g2];
                         if (!(w2 >= floor_)) continue;
                         const double d2 = s[2] > 0 ? d1 + w2 : d1 - w2;
+                        if (d2 + lo3 > cmax || d2 + hi3 < -cmax) continue;
                         const double s2_12 = adaptive ? pair_sq(0.0, g1, g2) : 0.0;
                         for (int32_t j3 = 0; j3 < nb; ++j3) {
                             const int64_t g3 = iq3 * nb + j3;
@@ -219,6 +248,24 @@ fp_status setup(Enum* e, int32_t type, const int32_t mesh[3], int32_t nb, const 
     e->omega = omega;
     e->floor_ = omega_floor;
     e->cut = nsigma * sigma;
+    if (e->ti.order == 4) {
+        e->wlo.assign((size_t)e->nq, 0.0);
+        e->whi.assign((size_t)e->nq, 0.0);
+        e->wmin_act = HUGE_VAL;
+        e->wmax_all = 0.0;
+        for (int64_t q = 0; q < e->nq; ++q) {
+            double lo = omega[q * nb], hi = omega[q * nb];
+            for (int32_t j = 0; j < nb; ++j) {
+                const double w = omega[q * nb + j];
+                lo = std::min(lo, w);
+                hi = std::max(hi, w);
+                if (w >= omega_floor) e->wmin_act = std::min(e->wmin_act, w);
+            }
+            e->wlo[(size_t)q] = lo;
+            e->whi[(size_t)q] = hi;
+            e->wmax_all = std::max(e->wmax_all, hi);
+        }
+    }
     e->keep_all = keep_fraction >= 1.0;
     e->keep_threshold = e->keep_all ? ~0ULL : (uint64_t)std::ldexp(keep_fraction, 64);
     e->seed = seed;
