@@ -290,6 +290,22 @@ __device__ inline void tbx_batch(const uint64_t (&rec)[kBR], const int32_t (&qpk
             // A_p for this tile: two passes of two M-tiles (Karatsuba, three real
             // MFMAs per complex product: k1 = (Fr + Fi) pr, k2 = Fr (pi - pr),
             // k3 = Fi (pr + pi); Re = k1 - k3, Im = k1 + k2)
+            // FP64: the partner slices of slots 2 and 3 are gathered before the
+            // A_p build, so their L2 latency overlaps the matrix work (a record
+            // outside this tile, or a padding slot, reads a valid mode and is unused)
+            double2 yv[kBR][3], zv[kBR][3];
+            if constexpr (!F32) {
+#pragma unroll
+                for (int k = 0; k < kBR; ++k) {
+                    const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
+                    const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        yv[k][q] = ld_eps(e2 + q, c2);
+                        zv[k][q] = ld_eps(e3 + q, c3);
+                    }
+                }
+            }
             __builtin_amdgcn_s_setprio(0);
             const bool tval = li < nbt;
             const int32_t qa = Qs[tval ? li : 0];
@@ -398,14 +414,8 @@ if constexpr (F32) {
                         V[k].x += (double)acc.x;
                         V[k].y += (double)acc.y;
                     } else {
-                        const double2* e2 = evec + (int64_t)pr[k].g2 * nb + 3 * ac;
-                        const double2* e3 = evec + (int64_t)pr[k].gl * nb + 3 * ad;
-                        double2 y[3], z[3];
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            y[q] = ld_eps(e2 + q, c2);
-                            z[q] = ld_eps(e3 + q, c3);
-                        }
+                        const double2(&y)[3] = yv[k];
+                        const double2(&z)[3] = zv[k];
                         const double2* Ar = A[s] + pr[k].jp * 9;
                         double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
