@@ -973,6 +973,13 @@ __global__ __launch_bounds__(kBlock, FORM == 0 || FORM == 3 ? 3 : 2) void k_fuse
                                             accw);
                         pend = 0;
                         ptup = 0;
+                        // the next batch writes every slot it reads; clearing them
+                        // keeps the old records out of registers across the batch
+#pragma unroll
+                        for (int k = 0; k < kBR; ++k) {
+                            buf[k] = 0;
+                            qbuf[k] = 0;
+                        }
                     }
                 } while (used < total);
                 if (last) break;
