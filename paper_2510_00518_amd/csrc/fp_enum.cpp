@@ -76,6 +76,13 @@ struct Enum {
     // frequency, and over the mesh the smallest active and the largest one
     std::vector<double> wlo, whi;
     double wmin_act = 0.0, wmax_all = 0.0;
+    // adaptive width, order 4: per q-point the largest |v_g . b_d / N_d| over its
+    // branches, so that a (q', q'', q''') triple bounds its processes' widths;
+    // per mode the projections (v_g . b_d) * (1 / N_d), whose pair differences
+    // give the width to within perr, so the filter's own arithmetic is needed
+    // only where |Delta| falls inside that bracket
+    std::vector<double> pq, proj;
+    double perr = 0.0;
 
     // squared projections of one partner pair, summed over the three directions
     // into s2 in order
@@ -90,12 +97,37 @@ struct Enum {
         return s2;
     }
     // the filter: |delta| <= nsigma * sigma_p; s2 holds the pairs not involving
-    // the last partner (summed first, as their slots come first)
-    bool pass(double delta, double cut_fixed, int m, double s2_head, int64_t gl_prev0, int64_t gl_prev1,
-              int64_t gl) const {
+    // the last partner (summed first, as their slots come first).  The fixed
+    // cut decides most candidates, so it stays inline and the width test apart.
+    __attribute__((always_inline)) bool pass(double delta, double cut_fixed, double cut_lim, int m, double s2_head,
+                                             int64_t gl_prev0, int64_t gl_prev1, int64_t gl) const {
         const double ad = std::fabs(delta);
         if (ad <= cut_fixed) return true;   // sigma_p >= sigma
-        if (!adaptive || !(ad <= cut_max)) return false;
+        if (!adaptive || !(ad <= cut_lim)) return false;
+        return pass_width(ad, m, s2_head, gl_prev0, gl_prev1, gl);
+    }
+    bool pass_width(double ad, int m, double s2_head, int64_t gl_prev0, int64_t gl_prev1, int64_t gl) const {
+        if (m == 4) {
+            // the norm of the nine pair projections lies within
+            // [n (1 - rel) - perr, n (1 + rel) + perr] of the table's n; the
+            // outer factors cover the rounding of the width formula itself
+            const double *p1 = &proj[(size_t)gl_prev0 * 3], *p2 = &proj[(size_t)gl_prev1 * 3],
+                         *p3 = &proj[(size_t)gl * 3];
+            const double* pp[3][2] = {{p1, p2}, {p1, p3}, {p2, p3}};
+            double t2 = 0.0;  // pairs in slot order, directions inside
+            for (int k = 0; k < 3; ++k)
+                for (int d = 0; d < 3; ++d) {
+                    const double t = pp[k][0][d] - pp[k][1][d];
+                    t2 += t * t;
+                }
+            const double nrm = std::sqrt(t2);
+            constexpr double rel = 1e-13;
+            const double sp_lo = factor / 3.0 * (nrm * (1.0 - rel) - perr) * (1.0 - rel);
+            const double sp_hi = factor / 3.0 * (nrm * (1.0 + rel) + perr) * (1.0 + rel);
+            if (ad <= nsigma * std::max(sp_lo, sigma) * (1.0 - rel)) return true;
+            if (ad > nsigma * std::max(sp_hi, sigma) * (1.0 + rel)) return false;
+            s2_head = pair_sq(0.0, gl_prev0, gl_prev1);
+        }
         double s2 = pair_sq(s2_head, gl_prev0, gl);
         if (m == 4) s2 = pair_sq(s2, gl_prev1, gl);
         const double sp = factor * std::sqrt(s2 / (3.0 * (double)(m - 1)));
@@ -115,6 +147,20 @@ struct Enum {
     bool keep(uint64_t row_g, uint64_t iq1, uint64_t iq2) const {
         if (keep_all) return true;
         return mix64(seed ^ mix64(row_g ^ mix64((iq1 << 32) | iq2))) < keep_threshold;
+    }
+
+    // The largest nsigma * sigma_p of any branch triple of three q-points: each
+    // pair's projection difference is at most the sum of the two maxima, and the
+    // relative margin lies far above the rounding of either evaluation.
+    double cut_bound(int64_t iq1, int64_t iq2, int64_t iq3) const {
+        const double *p1 = &pq[(size_t)iq1 * 3], *p2 = &pq[(size_t)iq2 * 3], *p3 = &pq[(size_t)iq3 * 3];
+        double b2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double a = p1[d] + p2[d], b = p1[d] + p3[d], c = p2[d] + p3[d];
+            b2 += a * a + b * b + c * c;
+        }
+        const double sp = std::max(factor * std::sqrt(b2 / 9.0), sigma);
+        return std::min(nsigma * sp * (1.0 + 1e-9), cut_max);
     }
 
     // Visit the kept records of row mode g0 in (q', q'', j', j'', j''') order (3ph: q', j', j'').
@@ -156,7 +202,7 @@ struct Enum {
                                  ((uint64_t)minus << 33));
                             continue;
                         }
-                        if (!pass(delta, cut, 3, 0.0, g1, 0, g2)) continue;
+                        if (!pass(delta, cut, cut_max, 3, 0.0, g1, 0, g2)) continue;
                         emit((uint64_t)g1 | ((uint64_t)j2 << 24));
                     }
                 }
@@ -197,7 +243,9 @@ struct Enum {
                 const double hi2 = s[2] > 0 ? whi[(size_t)iq2] : -wlo[(size_t)iq2];
                 const double lo3 = s[3] > 0 ? wlo[(size_t)iq3] : -whi[(size_t)iq3];
                 const double hi3 = s[3] > 0 ? whi[(size_t)iq3] : -wlo[(size_t)iq3];
-                const double cmax = cut_any + 1e-9 * (w0 + whi[(size_t)iq1] + whi[(size_t)iq2] + whi[(size_t)iq3]);
+                // the widest cut of this q-point triple (adaptive: its width bound)
+                const double cut_q = adaptive ? cut_bound(iq1, iq2, iq3) : cut;
+                const double cmax = cut_q + 1e-9 * (w0 + whi[(size_t)iq1] + whi[(size_t)iq2] + whi[(size_t)iq3]);
                 for (int32_t j1 = 0; j1 < nb; ++j1) {
                     const int64_t g1 = iq1 * nb + j1;
                     const double w1 = omega[g1];
@@ -211,14 +259,13 @@ struct Enum {
                         if (!(w2 >= floor_)) continue;
                         const double d2 = s[2] > 0 ? d1 + w2 : d1 - w2;
                         if (d2 + lo3 > cmax || d2 + hi3 < -cmax) continue;
-                        const double s2_12 = adaptive ? pair_sq(0.0, g1, g2) : 0.0;
                         for (int32_t j3 = 0; j3 < nb; ++j3) {
                             const int64_t g3 = iq3 * nb + j3;
                             if (tri23 && g3 < g2) continue;
                             const double w3 = omega[g3];
                             if (!(w3 >= floor_)) continue;
                             const double delta = s[3] > 0 ? d2 + w3 : d2 - w3;
-                            if (!pass(delta, cut, 4, s2_12, g1, g2, g3)) continue;
+                            if (!pass(delta, cut, cut_q, 4, 0.0, g1, g2, g3)) continue;
                             emit((uint64_t)g1 | ((uint64_t)g2 << 24) | ((uint64_t)j3 << 48));
                         }
                     }
@@ -305,6 +352,23 @@ fp_status setup(Enum* e, int32_t type, const int32_t mesh[3], int32_t nb, const 
         const double smax = std::max(e->factor * std::sqrt(n_pairs * b2 / (3.0 * (double)(m - 1))), sigma);
         // relative margin far above the rounding of either evaluation
         e->cut_max = nsigma * smax * (1.0 + 1e-9);
+        if (m == 4) {
+            e->pq.assign((size_t)e->nq * 3, 0.0);
+            e->proj.assign((size_t)nm * 3, 0.0);
+            double babs = 0.0;  // max over modes and directions of sum_k |v_k b_dk| / N_d
+            for (int64_t g = 0; g < nm; ++g)
+                for (int d = 0; d < 3; ++d) {
+                    const double* v = vel + g * 3;
+                    const double* b = e->recip + d * 3;
+                    const double p = std::fabs(v[0] * b[0] + v[1] * b[1] + v[2] * b[2]) / (double)e->N[d];
+                    double& x = e->pq[(size_t)(g / nb) * 3 + d];
+                    if (p > x) x = p;
+                    e->proj[(size_t)g * 3 + d] = (v[0] * b[0] + v[1] * b[1] + v[2] * b[2]) * (1.0 / (double)e->N[d]);
+                    babs = std::max(babs, (std::fabs(v[0] * b[0]) + std::fabs(v[1] * b[1]) + std::fabs(v[2] * b[2])) /
+                                              (double)e->N[d]);
+                }
+            e->perr = 3e-12 * babs;
+        }
     }
     return FP_OK;
 }
