@@ -218,6 +218,22 @@ struct Enum {
         // a block whose interval misses the widest cut holds no kept record.  The
         // decisions and the order of the kept records are the filter's own.
         const double cut_any = adaptive ? cut_max : cut;
+        // q''' per axis as a function of q'' (s3 q''' = -(q + s1 q' + s2 q'')),
+        // tabulated once per q', with q'' stepped through the mesh in index order:
+        // no integer division per q-point pair
+        std::vector<int64_t> t3((size_t)(N[0] + N[1] + N[2]));
+        int64_t* const t30 = t3.data();
+        int64_t* const t31 = t30 + N[0];
+        int64_t* const t32 = t31 + N[1];
+        auto step = [&](int64_t* c) {
+            if (++c[2] == N[2]) {
+                c[2] = 0;
+                if (++c[1] == N[1]) {
+                    c[1] = 0;
+                    ++c[0];
+                }
+            }
+        };
         // q-point pairs outermost, so the records of one (q', q'') tuple are contiguous
         for (int64_t iq1 = 0; iq1 < nq; ++iq1) {
             {
@@ -233,12 +249,15 @@ struct Enum {
             }
             int64_t q1[3];
             coords(iq1, q1);
-            for (int64_t iq2 = tri12 ? iq1 : 0; iq2 < nq; ++iq2) {
+            int64_t* const tt[3] = {t30, t31, t32};
+            for (int d = 0; d < 3; ++d)
+                for (int64_t x = 0; x < N[d]; ++x) tt[d][x] = wrapi(s[3] * (-(q0[d] + s[1] * q1[d] + s[2] * x)), N[d]);
+            const int64_t iq2_0 = tri12 ? iq1 : 0;
+            int64_t q2[3];
+            coords(iq2_0, q2);
+            for (int64_t iq2 = iq2_0; iq2 < nq; ++iq2, step(q2)) {
                 if (!keep((uint64_t)g0, (uint64_t)iq1, (uint64_t)iq2)) continue;
-                int64_t q2[3], q3[3];
-                coords(iq2, q2);
-                for (int d = 0; d < 3; ++d) q3[d] = s[3] * (-(q0[d] + s[1] * q1[d] + s[2] * q2[d]));
-                const int64_t iq3 = index(q3);
+                const int64_t iq3 = (t30[q2[0]] * N[1] + t31[q2[1]]) * N[2] + t32[q2[2]];
                 const double lo2 = s[2] > 0 ? wlo[(size_t)iq2] : -whi[(size_t)iq2];
                 const double hi2 = s[2] > 0 ? whi[(size_t)iq2] : -wlo[(size_t)iq2];
                 const double lo3 = s[3] > 0 ? wlo[(size_t)iq3] : -whi[(size_t)iq3];
