@@ -241,3 +241,19 @@ def test_fcc8_4ph_list_sizes():
         rm, off, _ = fp.enumerate_list(t, cfg)
         total += off[-1]
     assert 5e7 < total < 3e8
+
+
+@pytest.mark.parametrize("ptype", [fp.FP_4PM, fp.FP_4MM])
+def test_enumerator_adaptive_eight_atom_cell_matches_oracle(ptype):
+    """24 branches per q-point on a non-cubic mesh: the order-4 adaptive filter
+    (per-triple width bound, projection-table bracket, then the exact width)
+    keeps exactly the oracle's brute-force set."""
+    cfg = small_config((2, 2, 3), cell="conv")
+    b = {"factor": 0.3, "recip": _tilted(cfg)}
+    rows = row_modes(cfg)[::23]
+    rm, off, rec = fp.enumerate_list(ptype, cfg, row_mode=rows, sigma=0.02, broadening=b)
+    S = oracle.System(cfg, broadening=b)
+    want = [S.enumerate_row(ptype, int(g), 0.02) for g in rows]
+    assert off[-1] == sum(len(w) for w in want) > 0
+    for r, w in enumerate(want):
+        np.testing.assert_array_equal(np.sort(rec[off[r]:off[r + 1]]), w)
