@@ -11,7 +11,9 @@ projection as ((v_i - v_j) . b_d) / N_d, summed left to right.  This test
 emulates both forms in double precision (the table with and without fused
 multiply-adds) on random, nearly equal and large-but-close velocities, and
 checks that the enumerator's norm always lies inside the bracket, so the
-kernel's early decisions agree with the enumerator's.
+kernel's early decisions agree with the enumerator's.  The host enumerator's
+order-4 adaptive filter takes the same early decisions from the same table
+(formed without fused multiply-adds, pairs summed in slot order).
 """
 import math
 from fractions import Fraction
