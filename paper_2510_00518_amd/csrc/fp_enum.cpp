@@ -225,6 +225,19 @@ struct Enum {
         int64_t* const t30 = t3.data();
         int64_t* const t31 = t30 + N[0];
         int64_t* const t32 = t31 + N[1];
+        // per mode the signed frequencies of slots 2 and 3 (a - b is a + (-b), so
+        // the mismatch keeps its bits), NaN below the floor: a NaN mismatch fails
+        // every cut, so the floor test leaves the innermost loop
+        const int64_t nm = nq * nb;
+        std::vector<double> sw((size_t)nm * 2);
+        double* const sw2 = sw.data();
+        double* const sw3 = sw2 + nm;
+        for (int64_t g = 0; g < nm; ++g) {
+            const double w = omega[g];
+            const bool act = w >= floor_;
+            sw2[g] = act ? (s[2] > 0 ? w : -w) : NAN;
+            sw3[g] = act ? (s[3] > 0 ? w : -w) : NAN;
+        }
         auto step = [&](int64_t* c) {
             if (++c[2] == N[2]) {
                 c[2] = 0;
@@ -258,6 +271,7 @@ struct Enum {
             for (int64_t iq2 = iq2_0; iq2 < nq; ++iq2, step(q2)) {
                 if (!keep((uint64_t)g0, (uint64_t)iq1, (uint64_t)iq2)) continue;
                 const int64_t iq3 = (t30[q2[0]] * N[1] + t31[q2[1]]) * N[2] + t32[q2[2]];
+                if (tri23 && iq3 < iq2) continue;  // every g''' < g'': the triangle keeps none
                 const double lo2 = s[2] > 0 ? wlo[(size_t)iq2] : -whi[(size_t)iq2];
                 const double hi2 = s[2] > 0 ? whi[(size_t)iq2] : -wlo[(size_t)iq2];
                 const double lo3 = s[3] > 0 ? wlo[(size_t)iq3] : -whi[(size_t)iq3];
@@ -274,16 +288,12 @@ struct Enum {
                     for (int32_t j2 = 0; j2 < nb; ++j2) {
                         const int64_t g2 = iq2 * nb + j2;
                         if (tri12 && g2 < g1) continue;
-                        const double w2 = omega[g2];
-                        if (!(w2 >= floor_)) continue;
-                        const double d2 = s[2] > 0 ? d1 + w2 : d1 - w2;
-                        if (d2 + lo3 > cmax || d2 + hi3 < -cmax) continue;
-                        for (int32_t j3 = 0; j3 < nb; ++j3) {
+                        const double d2 = d1 + sw2[g2];
+                        if (!(d2 + lo3 <= cmax && d2 + hi3 >= -cmax)) continue;  // NaN: inactive
+                        for (int32_t j3 = tri23 && iq3 == iq2 ? j2 : 0; j3 < nb; ++j3) {
                             const int64_t g3 = iq3 * nb + j3;
                             if (tri23 && g3 < g2) continue;
-                            const double w3 = omega[g3];
-                            if (!(w3 >= floor_)) continue;
-                            const double delta = s[3] > 0 ? d2 + w3 : d2 - w3;
+                            const double delta = d2 + sw3[g3];
                             if (!pass(delta, cut, cut_q, 4, 0.0, g1, g2, g3)) continue;
                             emit((uint64_t)g1 | ((uint64_t)g2 << 24) | ((uint64_t)j3 << 48));
                         }
